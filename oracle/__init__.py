@@ -1,0 +1,17 @@
+"""CPU FP64 oracle for frame theoretic convolutional gridding (FTCG).
+
+TEST INFRASTRUCTURE, NOT PRODUCT CODE. Only the test suite, the smoke check of
+the package entry module and the CPU-baseline leg of the benchmark may import
+or call anything in this package. The GPU library never calls it, and this
+package imports nothing from the GPU library.
+
+Every routine here is a plain, slow, direct implementation of what the paper
+defines, in float64/complex128, with numpy/scipy primitives (bincount, FFT,
+k-d tree, lstsq) as single steps and no blocking or reordering beyond the
+definition. Each function cites the passage it follows (Sec. / equation label
+of arXiv:1706.08575).
+"""
+from .ftcg_ref import (  # noqa: F401
+    kernel_beta, grid_size, pixel_coords, nudft, nudft_at, frame_weights,
+    frame_weights_at, spread, grid_to_image, deapod_factors, ftcg_image, rel_l2,
+)
