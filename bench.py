@@ -1,0 +1,254 @@
+"""Benchmark of the FTCG hot path on one MI355X.
+
+A step is one pass of the whole path over one synthetic input already
+resident in HBM: input check + tile binning, neighbour binning + float64
+frame weights, weighting + spreading, both inverse-FFT passes, deapodization
+and crop (ftcg_set_points followed by ftcg_execute).
+
+Prints ONE JSON line. `value` is Msamples/s gridded end to end (samples per
+step / step time); images/s, the spreading-only rate, the per-step times
+(HIP events recorded by the library on its stream over the timed region),
+the roofline of the dominant kernel, the error against the FP64 oracle and
+the oracle's own CPU rate are reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Msamples/s gridded + images/s at rel L2 <=1e-4 vs FP64 oracle (plain vs batched/learned)"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# float64 operations per in-box neighbour pair of the weight sum, per axis:
+# difference, sin-difference (mul + fma), pi*d; then num/den, square, add
+FLOPS_PER_PAIR = {1: 1 * 5 + 3, 2: 2 * 5 + 5}
+
+WORKLOADS = {
+    # name: (description, builder)
+    "sas512_plain": "2D polar-format SAS, plain weights, 256 pulses x 512 samples, 512x512 image, FP32 spread/FFT",
+    "sas4096_precision": "2D polar-format SAS, 2048 pulses x 4096 samples (8 388 608), 4096x4096 image, "
+                         "FP32 spread/FFT, FP64 weights and deapodization",
+    "jitter1d_f64": "1D jittered raster, 512 samples, 256 pixels, FP64",
+}
+
+
+def make_inputs(name):
+    from paper_1706_08575_amd import synth as S
+    if name == "sas512_plain":
+        k, f, _ = S.workload_2d_plain()
+        return k, f, 512, "f32"
+    if name == "sas4096_precision":
+        k, f, _ = S.workload_2d_precision()
+        return k, f, 4096, "f32"
+    if name == "jitter1d_f64":
+        k, f, _ = S.make_1d()
+        return k, f, 256, "f64"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def step_bytes(step, m, nrec, n, G, dim, dtype):
+    """Algorithmic HBM bytes of one launch of each step."""
+    cs = 8 if dtype == "f32" else 16
+    rs = 4 if dtype == "f32" else 8
+    if step == "spread":
+        # read per sample: dim offsets + one complex value; write every grid cell once
+        return m * (dim * rs + cs) + G ** dim * cs
+    if step == "fft1":
+        return G * G * cs + n * G * cs
+    if step == "fft2_deapod":
+        return (n * G * cs + n * n * cs) if dim == 2 else (G * cs + n * cs)
+    if step == "bin":
+        # read k, write one record (2 offsets, cell, index) + weight per record
+        return m * 8 * dim + nrec * (16 + rs)
+    return None
+
+
+def count_box_pairs(k, R, sample=None):
+    """Number of ordered pairs (i, n) with ||k_i - k_n||_inf <= R (self included),
+    exact or estimated from a random subset of n."""
+    from scipy.spatial import cKDTree
+    tree = cKDTree(k)
+    if sample is None or sample >= len(k):
+        return int(np.sum(tree.query_ball_point(k, r=R, p=np.inf, return_length=True)))
+    rng = np.random.default_rng(0)
+    idx = rng.choice(len(k), size=sample, replace=False)
+    c = tree.query_ball_point(k[idx], r=R, p=np.inf, return_length=True)
+    return int(round(np.mean(c) * len(k)))
+
+
+def cpu_baseline(name, k, f, n, R=8.0):
+    """The oracle as it stands, single-threaded, on a bounded sample."""
+    import oracle as O
+    m = len(f)
+    t0 = time.perf_counter()
+    if m <= 200_000:
+        a = O.frame_weights(k, R)
+        img = O.ftcg_image(k, f, a, n)
+        dt = time.perf_counter() - t0
+        return {"value": m / dt / 1e6, "unit": "Msamples/s", "cores": 1, "kind": "oracle",
+                "sample": f"whole workload: {m} samples, {n}^{k.shape[1]} image (weights + spread + FFT + deapod)",
+                "seconds": dt}, img, a
+    # large workloads: weights of a contiguous 1/64 of the samples (their
+    # neighbour sums use the whole raster), spreading of the same subset onto
+    # the full grid, and the full-grid FFT; the rate is scaled to all samples
+    # for the per-sample stages and counted once for the FFT
+    sub = slice(0, m // 64)
+    t0 = time.perf_counter()
+    idx = np.arange(m)[sub]
+    a_sub = O.frame_weights_at(k, idx, R)
+    t_w = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    H = O.spread(k[sub], a_sub * f[sub], n)
+    t_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.grid_to_image(H, n)
+    t_f = time.perf_counter() - t0
+    per_sample = (t_w + t_s) / len(idx)
+    total = per_sample * m + t_f
+    return {"value": m / total / 1e6, "unit": "Msamples/s", "cores": 1, "kind": "oracle",
+            "sample": f"weights + spreading of {len(idx)} of {m} samples (scaled x{m / len(idx):.0f}) "
+                      f"+ one full {2 * n}^2 FFT/deapod; measured {t_w + t_s + t_f:.1f} s",
+            "seconds_projected": total}, None, None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sas512_plain", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--copies", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1706_08575_amd.ftcg import Plan
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    k, f, n, dtype = make_inputs(args.workload)
+    m, dim = len(f), k.shape[1]
+    cdt = torch.complex64 if dtype == "f32" else torch.complex128
+    kd = torch.from_numpy(k).to(dev)
+    fd = torch.from_numpy(f).to(cdt).to(dev)
+    out = torch.empty((n,) * dim, dtype=cdt, device=dev)
+
+    P = Plan(n, dim=dim, dtype=dtype, weights="plain", R=8.0)
+    if args.tile or args.copies != 1:
+        P.set_tuning(args.tile, args.copies)
+
+    def step():
+        P.set_points(kd)
+        P.execute(fd, out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    P.enable_timing(True)
+    P.timing()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = P.timing()
+    P.enable_timing(False)
+    info = P.info()
+    img = out.cpu().numpy()
+    alpha = P.get_weights().cpu().numpy()
+    sec = (t1 - t0) / args.steps
+    G = info["grid_size"]
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    stage_ms = {s: ms / c for s, (ms, c) in stages.items()}
+    # roofline of the dominant kernel
+    dom = max(stage_ms, key=stage_ms.get)
+    roof = None
+    if dom == "weights":
+        pairs = count_box_pairs(k, 8.0, sample=None if m <= 200_000 else 20000)
+        flops = pairs * FLOPS_PER_PAIR[dim]
+        ach = flops / (stage_ms[dom] * 1e-3) / 1e12
+        roof = {"kernel": "k_frame_weights", "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                "work_per_launch": f"{pairs} in-box pairs x {FLOPS_PER_PAIR[dim]} FP64 flops"}
+    else:
+        b = step_bytes(dom, m, info["n_records"], n, G, dim, dtype)
+        ach = b / (stage_ms[dom] * 1e-3) / 1e9
+        kname = {"spread": "k_spread2d" if dim == 2 else "k_spread1d", "fft1": "k_fft_rows (pass 1)",
+                 "fft2_deapod": "k_fft_rows (pass 2)", "bin": "binning kernels"}.get(dom, dom)
+        roof = {"kernel": kname, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": b}
+    # every HBM-bound step, for reference
+    steps_hbm = {}
+    for s in ("spread", "fft1", "fft2_deapod", "bin"):
+        if s in stage_ms:
+            b = step_bytes(s, m, info["n_records"], n, G, dim, dtype)
+            steps_hbm[s] = {"ms": stage_ms[s], "GB/s": b / (stage_ms[s] * 1e-3) / 1e9,
+                            "frac_hbm": b / (stage_ms[s] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    cpu = None
+    rel = None
+    if not args.no_cpu:
+        cpu, img_ref, a_ref = cpu_baseline(args.workload, k, f, n)
+        if img_ref is not None:
+            import oracle as O
+            rel = O.rel_l2(img, img_ref)
+            rel_w = float(np.max(np.abs(alpha - a_ref) / a_ref))
+            cpu["weights_max_rel_err"] = rel_w
+
+    res = {
+        "metric": METRIC,
+        "value": m / sec / 1e6,
+        "unit": "Msamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 spread/FFT, f64 weights/deapod" if dtype == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n": n, "m": m,
+                   "dim": dim, "W": 6, "sigma": 2.0, "R": 8.0, "weights": "plain", "grid": G,
+                   "tile": info["tile"], "records": info["n_records"], "lds_copies": args.copies},
+        "images_per_s": 1.0 / sec,
+        "spread_msamples_per_s": m / (stage_ms["spread"] * 1e-3) / 1e6 if "spread" in stage_ms else None,
+        "rel_l2_vs_oracle": rel,
+        "stage_ms": stage_ms,
+        "hbm_steps": steps_hbm,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

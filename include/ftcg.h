@@ -1,0 +1,153 @@
+/*
+ * ftcg.h -- C ABI of libftcg, an MI355X (gfx950) implementation of the
+ * data-parallel hot path of frame theoretic convolutional gridding (FTCG),
+ * McKay, Gelb, Monga, Raj, "Using Frame Theoretic Convolutional Gridding for
+ * Robust Synthetic Aperture Sonar Imaging", arXiv:1706.08575.
+ *
+ * The path (Sec. III-A eq:ffind / eq:cgmatrix in 1D, Sec. IV eq:twodcg /
+ * eq:twodcgmatrix in 2D):
+ *   1. weight every non-uniform Fourier sample fhat_j by its frame-optimal
+ *      quadrature weight alpha_j (the diagonal D of eq:difopt),
+ *   2. spread alpha_j fhat_j onto a sigma-times oversampled uniform grid with
+ *      a truncated Gaussian (the matrix Omega),
+ *   3. inverse FFT the grid (the sum over psi_m = e^{2 pi i m x} / w(x)),
+ *   4. divide by the window w(x) (deapodize) and crop to the n^d image.
+ *
+ * Conventions shared by every call:
+ *   - Sample locations k are in cycles per field of view; the FOV is the
+ *     centred box [-1/2, 1/2)^d; pixel p sits at x_p = (p - n/2) / n.
+ *   - The image approximates I(x_p) = sum_j alpha_j fhat_j exp(+2 pi i k_j . x_p)
+ *     (synthesis sign +, no 1/n normalisation).
+ *   - Grid index g <-> k = (g - G/2) / sigma with G = sigma * n per axis;
+ *     grid indices are taken modulo G, so samples outside the k-box
+ *     [-n/2, n/2) wrap (pixel-centred evaluation is n-periodic in k).
+ *   - Kernel: exp(-beta s^2) in grid units, beta = pi (sigma - 1/2) / (sigma W),
+ *     2W taps per axis (the tap at distance exactly W, weight
+ *     exp(-beta W^2) ~ 7e-7 at sigma = 2, W = 6, is dropped when u is integral).
+ *   - Deapodization divides by Phi(x / sigma) per axis, Phi(t) =
+ *     sqrt(pi / beta) exp(-pi^2 t^2 / beta), computed in float64.
+ *   - Complex data are interleaved (re, im): complex128 for FTCG_F64 plans,
+ *     complex64 for FTCG_F32 plans. Images are row-major; image axis a
+ *     corresponds to k[:, a].
+ *
+ * Memory and threading:
+ *   - Every pointer named *_dev is a DEVICE pointer owned by the caller; the
+ *     plan owns its own device workspace and frees it in ftcg_plan_destroy.
+ *   - Calls enqueue work on the plan's HIP stream and return without
+ *     synchronising the host, except where a call says otherwise.
+ *   - A plan is used by one host thread at a time and with one stream.
+ *   - Errors are returned as status codes; no C++ exception crosses the ABI.
+ *     On an error the plan is left in its previous valid state unless the
+ *     status is FTCG_EHIP (then destroy the plan).
+ */
+#ifndef FTCG_H
+#define FTCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ftcg_plan_s* ftcg_plan;
+
+typedef enum {
+  FTCG_OK = 0,
+  FTCG_EINVAL = 1,        /* bad argument (sizes, null pointer, non-finite k) */
+  FTCG_ENOMEM = 2,        /* device allocation failed */
+  FTCG_EHIP = 3,          /* a HIP runtime call failed */
+  FTCG_ESTATE = 4,        /* call out of order (e.g. execute before set_points) */
+  FTCG_EUNSUPPORTED = 5   /* valid request this build does not implement */
+} ftcg_status;
+
+typedef enum { FTCG_F64 = 0, FTCG_F32 = 1 } ftcg_dtype;
+
+typedef enum {
+  FTCG_W_PLAIN = 0,       /* frame-optimal diagonal weights, computed on the GPU in float64 */
+  FTCG_W_LEARNED = 1,     /* weights predicted by the plan's MLP, audited against FTCG_W_PLAIN */
+  FTCG_W_USER = 2,        /* caller supplies alpha with ftcg_set_weights */
+  FTCG_W_NONE = 3         /* alpha_j = 1 */
+} ftcg_wmode;
+
+/* Human-readable name of a status code (static storage). */
+const char* ftcg_status_string(ftcg_status s);
+
+/* Create a plan.
+ *   out           : receives the plan handle (host pointer).
+ *   dim           : 1 or 2.
+ *   n             : host array of dim image sizes per axis (each even, 8..8192;
+ *                   in 2D both entries must be equal).
+ *   half_width    : W, kernel half-width in grid cells (2..8).
+ *   oversampling  : sigma; sigma * n must be an even integer and G = sigma*n
+ *                   must be a power of two <= 16384 (FTCG_F32) / 8192 (FTCG_F64).
+ *   dtype         : precision of values, spreading and FFT.
+ *   wmode         : how the quadrature weights alpha are obtained.
+ *   weight_radius : R, the infinity-norm neighbourhood (cycles/FOV) of the
+ *                   frame-weight sum (eq:difopt truncated to ||k_i - k_j||_inf <= R), 0 < R <= 64.
+ *   hip_stream    : hipStream_t to enqueue on (NULL = the default stream).
+ * Weights follow eq:difopt; the grid and window follow eq:ffind / eq:twodcg. */
+ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half_width,
+                             double oversampling, ftcg_dtype dtype, ftcg_wmode wmode,
+                             double weight_radius, void* hip_stream);
+
+/* Release the plan and its device workspace (synchronises the plan's stream). */
+ftcg_status ftcg_plan_destroy(ftcg_plan plan);
+
+/* Set the sample locations (the raster {lambda_j}, Sec. III-A / Sec. IV eq:twoddataframe).
+ *   m     : number of samples, 1 <= m < 2^31.
+ *   k_dev : device float64 array, m x dim, row-major (k_dev[j*dim + a]).
+ * Bins the samples by grid tile and, in FTCG_W_PLAIN / FTCG_W_LEARNED mode,
+ * computes the weights. Non-finite coordinates give FTCG_EINVAL (checked on
+ * the device; this call synchronises the stream once to read that flag and
+ * the record count). */
+ftcg_status ftcg_set_points(ftcg_plan plan, int64_t m, const double* k_dev);
+
+/* FTCG_W_USER only: alpha_dev is a device float64 array of m weights. */
+ftcg_status ftcg_set_weights(ftcg_plan plan, const double* alpha_dev);
+
+/* Copy the weights in use (m float64, sample order) to alpha_dev (device).
+ * used_fallback_host (may be NULL) receives 1 when a FTCG_W_LEARNED plan fell
+ * back to the plain weights, else 0 (synchronises the stream). */
+ftcg_status ftcg_get_weights(ftcg_plan plan, double* alpha_dev, int* used_fallback_host);
+
+/* Run weighting, spreading, inverse FFT, deapodization and crop.
+ *   fhat_dev  : device, m complex values (complex128 / complex64 by dtype).
+ *   image_dev : device, n^dim complex values, row-major, written entirely. */
+ftcg_status ftcg_execute(ftcg_plan plan, const void* fhat_dev, void* image_dev);
+
+/* Steps of ftcg_execute, for per-step checks:
+ *   ftcg_spread_only writes the oversampled grid H (G^dim complex, row-major,
+ *   grid index g as in the conventions above) to grid_dev;
+ *   ftcg_grid_to_image runs the inverse FFT, deapodization and crop on a
+ *   caller grid (grid_dev is read only). */
+ftcg_status ftcg_spread_only(ftcg_plan plan, const void* fhat_dev, void* grid_dev);
+ftcg_status ftcg_grid_to_image(ftcg_plan plan, const void* grid_dev, void* image_dev);
+
+/* Plan properties: G per axis, number of spread records after halo
+ * duplication, number of tiles, tile edge. Any output pointer may be NULL. */
+ftcg_status ftcg_plan_info(ftcg_plan plan, int64_t* grid_size, int64_t* n_records,
+                           int64_t* n_tiles, int* tile);
+
+/* Tuning knobs (take effect at the next ftcg_set_points):
+ *   tile          : tile edge in grid cells (16, 32, 64 or 128; 0 = automatic).
+ *   lds_copies    : 1 = plain float accumulation in one LDS tile;
+ *                   2 or 4 = per-wave partial tiles combined at flush with
+ *                   compensated (TwoSum) addition. */
+ftcg_status ftcg_plan_set_tuning(ftcg_plan plan, int tile, int lds_copies);
+
+/* Per-step timing with HIP events on the plan's stream.
+ * enable != 0 records events around every step of later calls; ftcg_plan_timing
+ * synchronises the stream and returns, for each step s in
+ * {0 input check + tile binning, 1 frame-weight sum kernel, 2 spread,
+ *  3 fft pass 1, 4 fft pass 2 + deapodize + crop, 5 neighbour binning for weights},
+ * the summed milliseconds ms[s] and the number of launches count[s]
+ * (arrays of 8 entries; unused entries are 0), then resets the sums. */
+ftcg_status ftcg_plan_enable_timing(ftcg_plan plan, int enable);
+ftcg_status ftcg_plan_timing(ftcg_plan plan, double* ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTCG_H */

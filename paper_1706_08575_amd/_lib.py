@@ -1,0 +1,80 @@
+"""ctypes binding of libftcg (include/ftcg.h): the C entry points under the
+same names, argument marshalling only. Every step of the path runs in the
+library's HIP kernels; nothing here computes.
+
+The library is loaded from this package directory. If it is missing the
+import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libftcg.so")
+
+FTCG_OK, FTCG_EINVAL, FTCG_ENOMEM, FTCG_EHIP, FTCG_ESTATE, FTCG_EUNSUPPORTED = range(6)
+FTCG_F64, FTCG_F32 = 0, 1
+FTCG_W_PLAIN, FTCG_W_LEARNED, FTCG_W_USER, FTCG_W_NONE = range(4)
+
+STEP_NAMES = ("bin", "weights", "spread", "fft1", "fft2_deapod", "weight_bin", "s6", "s7")
+
+
+class FtcgError(RuntimeError):
+    def __init__(self, status: int, call: str):
+        self.status = status
+        super().__init__(f"{call}: {status_string(status)}")
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("ftcg_status_string", C.c_char_p, [C.c_int]),
+    ("ftcg_plan_create", C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int64), C.c_int, C.c_double,
+                                   C.c_int, C.c_int, C.c_double, C.c_void_p]),
+    ("ftcg_plan_destroy", C.c_int, [C.c_void_p]),
+    ("ftcg_set_points", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p]),
+    ("ftcg_set_weights", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("ftcg_get_weights", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]),
+    ("ftcg_execute", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ftcg_spread_only", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ftcg_grid_to_image", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ftcg_plan_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int)]),
+    ("ftcg_plan_set_tuning", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    ("ftcg_plan_enable_timing", C.c_int, [C.c_void_p, C.c_int]),
+    ("ftcg_plan_timing", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+]
+
+EXPORTED = [s[0] for s in _SIGS]
+
+
+def lib() -> C.CDLL:
+    """Load libftcg.so (once). Raises ImportError when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().ftcg_status_string(int(s)).decode()
+
+
+def check(status: int, call: str) -> None:
+    if status != FTCG_OK:
+        raise FtcgError(status, call)
+
+
+def call(name: str, *args) -> int:
+    """Call entry point ``name`` and return its raw status."""
+    return getattr(lib(), name)(*args)

@@ -1,0 +1,320 @@
+// C ABI of libftcg: plan lifecycle, argument checking, step sequencing.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "ftcg_internal.h"
+
+namespace ftcg {
+
+static hipEvent_t take_event(Timing& t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  FTCG_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void timing_begin(ftcg_plan p, int step) {
+  Timing& t = p->timing;
+  if (!t.enabled) return;
+  t.open_ev = take_event(t);
+  t.open_step = step;
+  FTCG_HIP(hipEventRecord(t.open_ev, p->stream));
+}
+
+void timing_end(ftcg_plan p, int step) {
+  Timing& t = p->timing;
+  if (!t.enabled || t.open_step != step) return;
+  hipEvent_t e = take_event(t);
+  FTCG_HIP(hipEventRecord(e, p->stream));
+  t.pending.push_back({step, t.open_ev, e});
+  t.open_step = -1;
+  t.open_ev = nullptr;
+}
+
+static double decode_ordered(unsigned long long o) {
+  unsigned long long b = (o & 0x8000000000000000ull) ? (o & 0x7fffffffffffffffull) : ~o;
+  double x;
+  memcpy(&x, &b, sizeof x);
+  return x;
+}
+
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+static int auto_tile(ftcg_plan p) {
+  if (p->dim == 1) return (int)(p->G < 1024 ? p->G : 1024);
+  int t = 64;
+  if (t > p->G) t = (int)p->G;
+  return t;
+}
+
+static void setup_tiles(ftcg_plan p) {
+  int t = p->tile_req ? p->tile_req : auto_tile(p);
+  if (t > p->G) t = (int)p->G;
+  p->tile = t;
+  p->nt = p->G / t;
+  p->ntiles = p->dim == 1 ? p->nt : p->nt * p->nt;
+}
+
+}  // namespace ftcg
+
+using namespace ftcg;
+
+template <class F>
+static ftcg_status guarded(F&& f) {
+  try {
+    f();
+    return FTCG_OK;
+  } catch (const StatusError& e) {
+    return e.status;
+  } catch (const HipError& e) {
+    (void)hipGetLastError();
+    return FTCG_EHIP;
+  } catch (const std::bad_alloc&) {
+    return FTCG_ENOMEM;
+  } catch (...) {
+    return FTCG_EHIP;
+  }
+}
+
+extern "C" {
+
+const char* ftcg_status_string(ftcg_status s) {
+  switch (s) {
+    case FTCG_OK: return "FTCG_OK";
+    case FTCG_EINVAL: return "FTCG_EINVAL: invalid argument";
+    case FTCG_ENOMEM: return "FTCG_ENOMEM: device allocation failed";
+    case FTCG_EHIP: return "FTCG_EHIP: HIP runtime error";
+    case FTCG_ESTATE: return "FTCG_ESTATE: call out of order";
+    case FTCG_EUNSUPPORTED: return "FTCG_EUNSUPPORTED: not supported by this build";
+  }
+  return "FTCG_?: unknown status";
+}
+
+ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half_width, double oversampling,
+                             ftcg_dtype dtype, ftcg_wmode wmode, double weight_radius, void* hip_stream) {
+  if (!out || !n) return FTCG_EINVAL;
+  *out = nullptr;
+  if (dim != 1 && dim != 2) return FTCG_EINVAL;
+  const int64_t n0 = n[0];
+  if (dim == 2 && n[1] != n0) return FTCG_EUNSUPPORTED;
+  if (n0 < 8 || n0 > 8192 || (n0 & 1)) return FTCG_EINVAL;
+  if (half_width < 2 || half_width > 8) return FTCG_EINVAL;
+  if (!(oversampling >= 1.25 && oversampling <= 4.0)) return FTCG_EINVAL;
+  if (dtype != FTCG_F32 && dtype != FTCG_F64) return FTCG_EINVAL;
+  if (wmode < FTCG_W_PLAIN || wmode > FTCG_W_NONE) return FTCG_EINVAL;
+  if (!(weight_radius > 0.0 && weight_radius <= 64.0)) return FTCG_EINVAL;
+  const double g = oversampling * (double)n0;
+  if (fabs(g - nearbyint(g)) > 1e-9) return FTCG_EINVAL;
+  const int64_t G = (int64_t)nearbyint(g);
+  if ((G % 4) != 0 || !is_pow2(G)) return FTCG_EUNSUPPORTED;
+  if (G > (dtype == FTCG_F32 ? 16384 : 8192)) return FTCG_EUNSUPPORTED;
+  if (2 * half_width > G) return FTCG_EINVAL;
+  if (wmode == FTCG_W_LEARNED) return FTCG_EUNSUPPORTED;
+
+  ftcg_plan p = new (std::nothrow) ftcg_plan_s();
+  if (!p) return FTCG_ENOMEM;
+  p->dim = dim;
+  p->n = n0;
+  p->W = half_width;
+  p->sigma = oversampling;
+  p->dtype = dtype;
+  p->wmode = wmode;
+  p->R = weight_radius;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  p->G = G;
+  p->beta = M_PI * (oversampling - 0.5) / (oversampling * half_width);
+  ftcg_status st = guarded([&] {
+    setup_tiles(p);
+    p->flags.ensure(64);
+    p->deapod.ensure(sizeof(double) * n0);
+    compute_deapod(p);
+    const size_t csz = dtype == FTCG_F64 ? 16 : 8;
+    p->grid.ensure(csz * (size_t)(dim == 2 ? G * G : G));
+    if (dim == 2) p->fft_tmp.ensure(csz * (size_t)(n0 * G));
+    if (hipHostMalloc((void**)&p->host_flags, 64, hipHostMallocDefault) != hipSuccess) {
+      p->host_flags = nullptr;
+      throw StatusError{FTCG_ENOMEM};
+    }
+  });
+  if (st != FTCG_OK) {
+    ftcg_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return FTCG_OK;
+}
+
+ftcg_status ftcg_plan_destroy(ftcg_plan p) {
+  if (!p) return FTCG_EINVAL;
+  (void)hipStreamSynchronize(p->stream);
+  DevBuf* bufs[] = {&p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp,
+                    &p->flags,  &p->wb_cnt, &p->wb_off, &p->ws_k,   &p->ws_idx,   &p->wb_of,
+                    &p->grid,   &p->fft_tmp, &p->deapod, &p->tile_order};
+  for (DevBuf* b : bufs) b->release();
+  for (auto& pr : p->timing.pending) {
+    (void)hipEventDestroy(pr.a);
+    (void)hipEventDestroy(pr.b);
+  }
+  for (hipEvent_t e : p->timing.pool) (void)hipEventDestroy(e);
+  if (p->timing.open_ev) (void)hipEventDestroy(p->timing.open_ev);
+  if (p->host_flags) (void)hipHostFree(p->host_flags);
+  delete p;
+  return FTCG_OK;
+}
+
+ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
+  if (!p || !k_dev) return FTCG_EINVAL;
+  if (m < 1 || m >= (int64_t(1) << 31)) return FTCG_EINVAL;
+  return guarded([&] {
+    p->have_points = false;
+    p->have_weights = false;
+    p->m = m;
+    // 1) finiteness + bounding box (one host synchronisation)
+    timing_begin(p, STEP_BIN);
+    launch_check_points(p, k_dev, m, p->flags.as<double>());
+    FTCG_HIP(hipMemcpyAsync(p->host_flags, p->flags.p, 40, hipMemcpyDeviceToHost, p->stream));
+    FTCG_HIP(hipStreamSynchronize(p->stream));
+    const unsigned long long* hf = reinterpret_cast<const unsigned long long*>(p->host_flags);
+    if (hf[0] != 0) throw StatusError{FTCG_EINVAL};
+    double kmin[2] = {0, 0}, kmax[2] = {0, 0};
+    for (int a = 0; a < p->dim; ++a) {
+      kmin[a] = decode_ordered(hf[1 + a]);
+      kmax[a] = decode_ordered(hf[3 + a]);
+    }
+    // 2) weights (caller order)
+    p->alpha.ensure(sizeof(double) * m);
+    if (p->wmode == FTCG_W_PLAIN) {
+      timing_end(p, STEP_BIN);
+      compute_plain_weights_k(p, k_dev, kmin, kmax);
+      timing_begin(p, STEP_BIN);
+      p->have_weights = true;
+    } else if (p->wmode == FTCG_W_NONE) {
+      fill_ones(p->alpha.as<double>(), m, p->stream);
+      p->have_weights = true;
+    }
+    // 3) tile binning of spread records (worst case 2^dim records per sample)
+    setup_tiles(p);
+    const int64_t cap = m << p->dim;
+    const size_t rsz = p->dtype == FTCG_F64 ? sizeof(Rec<double>) : sizeof(Rec<float>);
+    const size_t asz = p->dtype == FTCG_F64 ? sizeof(double) : sizeof(float);
+    p->recs.ensure(rsz * cap);
+    p->alpha_s.ensure(asz * cap);
+    p->tile_cnt.ensure(sizeof(int32_t) * (p->ntiles + 1));
+    p->tile_off.ensure(sizeof(int32_t) * (p->ntiles + 1));
+    p->scan_tmp.ensure(scan_tmp_bytes(p->ntiles));
+    bin_points_k(p, k_dev);
+    FTCG_HIP(hipMemcpyAsync(p->host_flags, p->tile_off.as<int32_t>() + p->ntiles, sizeof(int32_t),
+                            hipMemcpyDeviceToHost, p->stream));
+    FTCG_HIP(hipStreamSynchronize(p->stream));
+    timing_end(p, STEP_BIN);
+    p->nrec = *reinterpret_cast<const int32_t*>(p->host_flags);
+    p->have_points = true;
+  });
+}
+
+ftcg_status ftcg_set_weights(ftcg_plan p, const double* alpha_dev) {
+  if (!p || !alpha_dev) return FTCG_EINVAL;
+  if (p->wmode != FTCG_W_USER) return FTCG_ESTATE;
+  if (!p->have_points) return FTCG_ESTATE;
+  return guarded([&] {
+    FTCG_HIP(hipMemcpyAsync(p->alpha.p, alpha_dev, sizeof(double) * p->m, hipMemcpyDeviceToDevice, p->stream));
+    refill_alpha(p);
+    p->have_weights = true;
+  });
+}
+
+ftcg_status ftcg_get_weights(ftcg_plan p, double* alpha_dev, int* used_fallback_host) {
+  if (!p || !alpha_dev) return FTCG_EINVAL;
+  if (!p->have_points || !p->have_weights) return FTCG_ESTATE;
+  return guarded([&] {
+    FTCG_HIP(hipMemcpyAsync(alpha_dev, p->alpha.p, sizeof(double) * p->m, hipMemcpyDeviceToDevice, p->stream));
+    if (used_fallback_host) {
+      FTCG_HIP(hipStreamSynchronize(p->stream));
+      *used_fallback_host = p->used_fallback;
+    }
+  });
+}
+
+ftcg_status ftcg_spread_only(ftcg_plan p, const void* fhat_dev, void* grid_dev) {
+  if (!p || !fhat_dev || !grid_dev) return FTCG_EINVAL;
+  if (!p->have_points || !p->have_weights) return FTCG_ESTATE;
+  return guarded([&] {
+    timing_begin(p, STEP_SPREAD);
+    spread(p, fhat_dev, grid_dev);
+    timing_end(p, STEP_SPREAD);
+  });
+}
+
+ftcg_status ftcg_grid_to_image(ftcg_plan p, const void* grid_dev, void* image_dev) {
+  if (!p || !grid_dev || !image_dev) return FTCG_EINVAL;
+  return guarded([&] { grid_to_image(p, grid_dev, image_dev); });
+}
+
+ftcg_status ftcg_execute(ftcg_plan p, const void* fhat_dev, void* image_dev) {
+  if (!p || !fhat_dev || !image_dev) return FTCG_EINVAL;
+  if (!p->have_points || !p->have_weights) return FTCG_ESTATE;
+  return guarded([&] {
+    timing_begin(p, STEP_SPREAD);
+    spread(p, fhat_dev, p->grid.p);
+    timing_end(p, STEP_SPREAD);
+    grid_to_image(p, p->grid.p, image_dev);
+  });
+}
+
+ftcg_status ftcg_plan_info(ftcg_plan p, int64_t* grid_size, int64_t* n_records, int64_t* n_tiles, int* tile) {
+  if (!p) return FTCG_EINVAL;
+  if (grid_size) *grid_size = p->G;
+  if (n_records) *n_records = p->nrec;
+  if (n_tiles) *n_tiles = p->ntiles;
+  if (tile) *tile = p->tile;
+  return FTCG_OK;
+}
+
+ftcg_status ftcg_plan_set_tuning(ftcg_plan p, int tile, int lds_copies) {
+  if (!p) return FTCG_EINVAL;
+  if (tile != 0 && tile != 16 && tile != 32 && tile != 64 && tile != 128 && !(p->dim == 1 && is_pow2(tile)))
+    return FTCG_EINVAL;
+  if (tile != 0 && tile < 2 * p->W) return FTCG_EINVAL;
+  if (lds_copies != 1 && lds_copies != 2 && lds_copies != 4) return FTCG_EINVAL;
+  const int64_t t = tile ? tile : 64;
+  if (p->dim == 2 && (size_t)lds_copies * 2 * t * (t + 1) * sizeof(double) > 160 * 1024) return FTCG_EUNSUPPORTED;
+  p->tile_req = tile;
+  p->lds_copies = lds_copies;
+  p->have_points = false;
+  return FTCG_OK;
+}
+
+ftcg_status ftcg_plan_enable_timing(ftcg_plan p, int enable) {
+  if (!p) return FTCG_EINVAL;
+  p->timing.enabled = enable != 0;
+  return FTCG_OK;
+}
+
+ftcg_status ftcg_plan_timing(ftcg_plan p, double* ms, int64_t* count) {
+  if (!p || !ms || !count) return FTCG_EINVAL;
+  return guarded([&] {
+    FTCG_HIP(hipStreamSynchronize(p->stream));
+    for (int s = 0; s < N_STEPS; ++s) {
+      ms[s] = 0.0;
+      count[s] = 0;
+    }
+    Timing& t = p->timing;
+    for (auto& pr : t.pending) {
+      float v = 0.f;
+      FTCG_HIP(hipEventElapsedTime(&v, pr.a, pr.b));
+      ms[pr.step] += v;
+      count[pr.step] += 1;
+      t.pool.push_back(pr.a);
+      t.pool.push_back(pr.b);
+    }
+    t.pending.clear();
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+// Geometry stage: input checks, tile binning of spread records, and the
+// neighbour binning used by the frame-weight sum.
+//
+// Tile binning (counting sort by tile): every sample j has grid position
+// u_j = sigma k_j + G/2 per axis, taken modulo G and evaluated in float64.
+// Its footprint covers cells floor(u) - W + 1 .. floor(u) + W per axis, which
+// touches one or two tiles per axis; the sample gets one record per touched
+// tile, so each tile can later be accumulated and written by one workgroup
+// without global atomics. Records keep the integer cell relative to the tile
+// origin and the fractional position u - floor(u) (exact in float64, rounded
+// once to the spread precision), so the float32 path never handles absolute
+// grid coordinates.
+#include "ftcg_internal.h"
+
+namespace ftcg {
+
+constexpr int BIN_BLOCK = 256;
+
+// ---------------------------------------------------------------------------
+// input check: finiteness and bounding box (order-preserving integer encoding)
+// ---------------------------------------------------------------------------
+
+__device__ inline unsigned long long ordered_bits(double x) {
+  unsigned long long b = __double_as_longlong(x);
+  return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// flags layout (unsigned long long): [0] bad flag, [1..2] min per axis, [3..4] max per axis
+__global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __restrict__ k, int64_t m, int dim,
+                                                            unsigned long long* __restrict__ flags) {
+  __shared__ unsigned long long smin[2][BIN_BLOCK];
+  __shared__ unsigned long long smax[2][BIN_BLOCK];
+  unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
+  bool bad = false;
+  for (int64_t j = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; j < m; j += (int64_t)gridDim.x * BIN_BLOCK) {
+    for (int a = 0; a < dim; ++a) {
+      double x = k[j * dim + a];
+      if (!isfinite(x)) { bad = true; continue; }
+      unsigned long long o = ordered_bits(x);
+      lo[a] = o < lo[a] ? o : lo[a];
+      hi[a] = o > hi[a] ? o : hi[a];
+    }
+  }
+  if (bad) atomicOr(&flags[0], 1ull);
+  for (int a = 0; a < 2; ++a) { smin[a][threadIdx.x] = lo[a]; smax[a][threadIdx.x] = hi[a]; }
+  __syncthreads();
+  for (int off = BIN_BLOCK / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      for (int a = 0; a < 2; ++a) {
+        unsigned long long x = smin[a][threadIdx.x + off];
+        if (x < smin[a][threadIdx.x]) smin[a][threadIdx.x] = x;
+        unsigned long long y = smax[a][threadIdx.x + off];
+        if (y > smax[a][threadIdx.x]) smax[a][threadIdx.x] = y;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int a = 0; a < dim; ++a) {
+      atomicMin(&flags[1 + a], smin[a][0]);
+      atomicMax(&flags[3 + a], smax[a][0]);
+    }
+  }
+}
+
+__global__ void k_init_flags(unsigned long long* flags) {
+  if (threadIdx.x == 0) {
+    flags[0] = 0ull;
+    flags[1] = flags[2] = ~0ull;
+    flags[3] = flags[4] = 0ull;
+  }
+}
+
+void launch_check_points(ftcg_plan p, const double* k, int64_t m, double* flags_d) {
+  auto* f = reinterpret_cast<unsigned long long*>(flags_d);
+  hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, p->stream, f);
+  int64_t nb = (m + BIN_BLOCK - 1) / BIN_BLOCK;
+  if (nb > 4096) nb = 4096;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_check_points, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream, k, m, p->dim, f);
+  FTCG_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// tile binning
+// ---------------------------------------------------------------------------
+
+struct TileGeom {
+  double sigma, half_g;   // u = sigma k + G/2
+  int64_t G;
+  int T;                  // tile edge
+  int nt;                 // tiles per axis
+  int W;
+};
+
+__device__ inline double wrap_u(double u, double G) {
+  double w = u - G * floor(u / G);
+  if (w >= G) w -= G;   // rounding can land exactly on G
+  if (w < 0.0) w = 0.0;
+  return w;
+}
+
+__device__ inline int floor_div(int a, int b) {  // b > 0
+  int q = a / b;
+  return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+__device__ inline int wrap_tile(int t, int nt) { return t < 0 ? t + nt : (t >= nt ? t - nt : t); }
+
+template <int DIM>
+__device__ inline void sample_tiles(const double* __restrict__ k, int64_t j, const TileGeom& g, double* u,
+                                    int* c, int* tlo, int* thi) {
+  for (int a = 0; a < DIM; ++a) {
+    u[a] = wrap_u(g.sigma * k[j * DIM + a] + g.half_g, (double)g.G);
+    c[a] = (int)floor(u[a]);
+    tlo[a] = floor_div(c[a] - g.W + 1, g.T);
+    thi[a] = floor_div(c[a] + g.W, g.T);
+  }
+}
+
+// up to 2^DIM (tile, local cell) pairs of one sample, invalid slots have key -1
+template <int DIM>
+__device__ inline void sample_keys(const double* __restrict__ k, int64_t j, int64_t m, const TileGeom& g,
+                                   double* u, int* c, int* key, int* l0, int* l1) {
+  int tlo[DIM], thi[DIM];
+  for (int q = 0; q < 4; ++q) key[q] = -1;
+  if (j >= m) return;
+  sample_tiles<DIM>(k, j, g, u, c, tlo, thi);
+  int q = 0;
+  for (int t0 = tlo[0]; t0 <= thi[0]; ++t0) {
+    if (DIM == 1) {
+      key[q] = wrap_tile(t0, g.nt);
+      l0[q] = c[0] - t0 * g.T;
+      l1[q] = 0;
+      ++q;
+    } else {
+      for (int t1 = tlo[DIM - 1]; t1 <= thi[DIM - 1]; ++t1) {
+        key[q] = wrap_tile(t0, g.nt) * g.nt + wrap_tile(t1, g.nt);
+        l0[q] = c[0] - t0 * g.T;
+        l1[q] = c[DIM - 1] - t1 * g.T;
+        ++q;
+      }
+    }
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(BIN_BLOCK) void k_tile_count(const double* __restrict__ k, int64_t m, TileGeom g,
+                                                          int32_t* __restrict__ cnt) {
+  const int64_t j = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x;
+  double u[DIM];
+  int c[DIM], key[4], l0[4], l1[4];
+  sample_keys<DIM>(k, j, m, g, u, c, key, l0, l1);
+#pragma unroll
+  for (int q = 0; q < (1 << DIM); ++q) agg_atomic_add(cnt, key[q] < 0 ? 0 : key[q], key[q] >= 0);
+}
+
+template <int DIM, class real>
+__global__ __launch_bounds__(BIN_BLOCK) void k_tile_scatter(const double* __restrict__ k, int64_t m, TileGeom g,
+                                                            const double* __restrict__ alpha,
+                                                            int32_t* __restrict__ cursor,
+                                                            Rec<real>* __restrict__ recs,
+                                                            real* __restrict__ alpha_s) {
+  const int64_t j = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x;
+  double u[DIM] = {};
+  int c[DIM] = {}, key[4], l0[4], l1[4];
+  sample_keys<DIM>(k, j, m, g, u, c, key, l0, l1);
+  const real a = (j < m && alpha) ? (real)alpha[j] : (real)1;
+  Rec<real> r;
+  r.f0 = (real)(u[0] - (double)c[0]);
+  r.f1 = (DIM == 2) ? (real)(u[DIM - 1] - (double)c[DIM - 1]) : (real)0;
+  r.src = (int32_t)j;
+#pragma unroll
+  for (int q = 0; q < (1 << DIM); ++q) {
+    const int pos = agg_atomic_add(cursor, key[q] < 0 ? 0 : key[q], key[q] >= 0);
+    if (key[q] >= 0) {
+      r.c01 = (int32_t)(((uint32_t)l0[q] & 0xffffu) | ((uint32_t)l1[q] << 16));
+      recs[pos] = r;
+      alpha_s[pos] = a;
+    }
+  }
+}
+
+template <class real>
+__global__ __launch_bounds__(BIN_BLOCK) void k_refill_alpha(const Rec<real>* __restrict__ recs, int64_t nrec,
+                                                            const double* __restrict__ alpha,
+                                                            real* __restrict__ alpha_s) {
+  int64_t r = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x;
+  if (r < nrec) alpha_s[r] = (real)alpha[recs[r].src];
+}
+
+static TileGeom tile_geom(ftcg_plan p) {
+  TileGeom g;
+  g.sigma = p->sigma;
+  g.half_g = (double)(p->G / 2);
+  g.G = p->G;
+  g.T = p->tile;
+  g.nt = (int)p->nt;
+  g.W = p->W;
+  return g;
+}
+
+template <class real>
+static void bin_points_t(ftcg_plan p, const double* k) {
+  const TileGeom g = tile_geom(p);
+  hipStream_t s = p->stream;
+  const int64_t m = p->m;
+  const unsigned nb = (unsigned)((m + BIN_BLOCK - 1) / BIN_BLOCK);
+  int32_t* cnt = p->tile_cnt.as<int32_t>();
+  int32_t* off = p->tile_off.as<int32_t>();
+  FTCG_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (p->ntiles + 1), s));
+  if (p->dim == 1)
+    hipLaunchKernelGGL(k_tile_count<1>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
+  else
+    hipLaunchKernelGGL(k_tile_count<2>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
+  exclusive_scan_i32(cnt, off, p->ntiles, p->scan_tmp.as<int32_t>(), s);
+  FTCG_HIP(hipMemcpyAsync(cnt, off, sizeof(int32_t) * p->ntiles, hipMemcpyDeviceToDevice, s));
+  const double* alpha = p->have_weights ? p->alpha.as<double>() : nullptr;
+  if (p->dim == 1)
+    hipLaunchKernelGGL((k_tile_scatter<1, real>), dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, alpha, cnt,
+                       p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
+  else
+    hipLaunchKernelGGL((k_tile_scatter<2, real>), dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, alpha, cnt,
+                       p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
+  FTCG_HIP(hipGetLastError());
+}
+
+void bin_points_k(ftcg_plan p, const double* k) {
+  if (p->dtype == FTCG_F64)
+    bin_points_t<double>(p, k);
+  else
+    bin_points_t<float>(p, k);
+}
+
+void refill_alpha(ftcg_plan p) {
+  const unsigned nb = (unsigned)((p->nrec + BIN_BLOCK - 1) / BIN_BLOCK);
+  if (p->nrec == 0) return;
+  if (p->dtype == FTCG_F64)
+    hipLaunchKernelGGL(k_refill_alpha<double>, dim3(nb), dim3(BIN_BLOCK), 0, p->stream,
+                       p->recs.as<Rec<double>>(), p->nrec, p->alpha.as<double>(), p->alpha_s.as<double>());
+  else
+    hipLaunchKernelGGL(k_refill_alpha<float>, dim3(nb), dim3(BIN_BLOCK), 0, p->stream,
+                       p->recs.as<Rec<float>>(), p->nrec, p->alpha.as<double>(), p->alpha_s.as<float>());
+  FTCG_HIP(hipGetLastError());
+}
+
+__global__ void k_fill_ones(double* a, int64_t m) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) a[j] = 1.0;
+}
+
+void fill_ones(double* a, int64_t m, hipStream_t s) {
+  if (m == 0) return;
+  hipLaunchKernelGGL(k_fill_ones, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a, m);
+  FTCG_HIP(hipGetLastError());
+}
+
+}  // namespace ftcg

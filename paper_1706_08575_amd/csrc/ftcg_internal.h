@@ -1,0 +1,197 @@
+// Internal declarations of libftcg: plan state, record layout, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ftcg.h"
+
+namespace ftcg {
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+
+struct HipError {
+  hipError_t err;
+  const char* what;
+};
+
+#define FTCG_HIP(call)                                 \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) throw ::ftcg::HipError{e_, #call}; \
+  } while (0)
+
+struct StatusError {
+  ftcg_status status;
+};
+
+// ---------------------------------------------------------------------------
+// device buffer owned by a plan (grow-only)
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t need) {
+    if (need <= bytes) return;
+    release();
+    if (hipMalloc(&p, need) != hipSuccess) {
+      p = nullptr;
+      bytes = 0;
+      (void)hipGetLastError();
+      throw StatusError{FTCG_ENOMEM};
+    }
+    bytes = need;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// spread record: one (sample, tile) pair; a sample whose 2W x 2W footprint
+// crosses tile edges gets one record per tile it touches.
+//   c0, c1 : integer grid cell floor(u) relative to the tile origin (int16 each,
+//            packed c0 | c1 << 16), can be negative or >= tile for halo records;
+//   f0, f1 : u - floor(u) in [0, 1) per axis (the fractional position);
+//   src    : index of the sample in caller order.
+// The footprint of a record covers local cells c - W + 1 .. c + W per axis.
+// ---------------------------------------------------------------------------
+
+template <class real>
+struct Rec {
+  real f0, f1;
+  int32_t c01;
+  int32_t src;
+};
+
+enum Step {
+  STEP_BIN = 0,      // input check + tile binning of spread records
+  STEP_WEIGHTS = 1,  // frame-weight sum kernel
+  STEP_SPREAD = 2,
+  STEP_FFT1 = 3,
+  STEP_FFT2 = 4,     // second FFT pass + deapodize + crop (the only pass in 1D)
+  STEP_WBIN = 5,     // neighbour binning for the weight sum
+  N_STEPS = 8
+};
+
+// per-step HIP event pairs recorded on the plan's stream; resolved (and
+// returned to the pool) when the caller asks for the sums
+struct Timing {
+  bool enabled = false;
+  struct Pair {
+    int step;
+    hipEvent_t a, b;
+  };
+  std::vector<Pair> pending;
+  std::vector<hipEvent_t> pool;
+  int open_step = -1;
+  hipEvent_t open_ev = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// wavefront-aggregated counter increment: lanes holding the same key share one
+// global atomic (rasters arrive in acquisition order, so neighbouring lanes
+// usually bin to the same tile); returns this lane's slot. Lanes with
+// valid == false take part in the vote but get -1.
+// ---------------------------------------------------------------------------
+
+__device__ inline int agg_atomic_add(int32_t* counters, int key, bool valid) {
+  unsigned long long todo = __ballot(valid);
+  const int lane = __lane_id();
+  int slot = -1;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lkey = __builtin_amdgcn_readlane(key, leader);
+    const unsigned long long match = __ballot(valid && key == lkey) & todo;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counters[lkey], __popcll(match));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if ((match >> lane) & 1ull) {
+      const unsigned long long below = match & ((1ull << lane) - 1ull);
+      slot = base + __popcll(below);
+    }
+    todo &= ~match;
+  }
+  return slot;
+}
+
+}  // namespace ftcg
+
+struct ftcg_plan_s {
+  int dim = 0;
+  int64_t n = 0;      // image edge (same on every axis)
+  int W = 6;
+  double sigma = 2.0;
+  ftcg_dtype dtype = FTCG_F32;
+  ftcg_wmode wmode = FTCG_W_PLAIN;
+  double R = 8.0;
+  hipStream_t stream = nullptr;
+
+  int64_t G = 0;       // grid edge
+  double beta = 0.0;   // kernel exp(-beta s^2)
+  int tile_req = 0;    // requested tile edge (0 = automatic)
+  int lds_copies = 1;
+
+  // geometry state
+  int tile = 64;
+  int64_t nt = 0;       // tiles per axis
+  int64_t ntiles = 0;
+  int64_t m = 0;
+  int64_t nrec = 0;
+  bool have_points = false;
+  bool have_weights = false;
+  int used_fallback = 0;
+
+  ftcg::DevBuf alpha;        // m float64, caller order
+  ftcg::DevBuf recs;         // nrec records
+  ftcg::DevBuf alpha_s;      // nrec weights in record order (dtype real)
+  ftcg::DevBuf tile_cnt;     // ntiles + 1 int32 (count, then cursor)
+  ftcg::DevBuf tile_off;     // ntiles + 1 int32
+  ftcg::DevBuf scan_tmp;     // scan scratch
+  ftcg::DevBuf flags;        // small device scratch: [0] bad-input flag, doubles for bbox
+
+  // weight binning
+  ftcg::DevBuf wb_cnt, wb_off;
+  ftcg::DevBuf ws_k;         // sorted samples: k, sin(pi k), cos(pi k) (3*dim doubles each)
+  ftcg::DevBuf ws_idx;       // sorted original index
+  ftcg::DevBuf wb_of;        // weight-bin id per sample (caller order)
+
+  // execute workspace
+  ftcg::DevBuf grid;         // G^dim complex
+  ftcg::DevBuf fft_tmp;      // n x G complex (2D)
+  ftcg::DevBuf deapod;       // n float64
+  ftcg::DevBuf tile_order;   // ntiles int32 (heavy tiles first)
+
+  ftcg::Timing timing;
+  double* host_flags = nullptr;  // pinned host mirror of small flags
+};
+
+namespace ftcg {
+
+// launchers (defined in the .hip files); all enqueue on plan->stream
+void launch_check_points(ftcg_plan p, const double* k, int64_t m, double* flags);
+void bin_points_k(ftcg_plan p, const double* k);   // fills recs, alpha_s, tile_off
+void refill_alpha(ftcg_plan p);                     // alpha_s[r] = alpha[recs[r].src]
+void compute_plain_weights_k(ftcg_plan p, const double* k, const double* kmin,
+                             const double* kmax);   // fills alpha (caller order)
+void fill_ones(double* a, int64_t m, hipStream_t s);
+void spread(ftcg_plan p, const void* fhat, void* grid);
+void grid_to_image(ftcg_plan p, const void* grid, void* image);
+void compute_deapod(ftcg_plan p);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s);
+size_t scan_tmp_bytes(int64_t n);
+
+void timing_begin(ftcg_plan p, int step);
+void timing_end(ftcg_plan p, int step);
+
+}  // namespace ftcg

@@ -1,0 +1,203 @@
+// Frame-optimal diagonal quadrature weights in float64 (Sec. III-C, eq:difopt).
+//
+// min over diagonal D of ||T D - I||_F separates into one least-squares
+// problem per column n: alpha_n = conj(T_nn) / sum_i |T_in|^2. With T the
+// Gram matrix of the data frame on the unit field of view,
+// T_in = prod_a sinc(k_ia - k_na) (sinc t = sin(pi t) / (pi t)), T_nn = 1 and
+// alpha_n = 1 / sum_i T_in^2. The sum is truncated to the infinity-norm box
+// ||k_i - k_n||_inf <= R (a tensor box keeps the weights of tensor rasters
+// exactly separable).
+//
+// GPU layout: samples are counting-sorted into square neighbour bins of edge
+// h >= R/2 (k units), so the box of every sample lies in the (2s+1)^d bins
+// around its own (s = ceil(R/h) <= 2). Sorted arrays hold k and the
+// per-sample sin(pi k), cos(pi k), so each pair needs
+// sin(pi (k_i - k_n)) = sin(pi k_i) cos(pi k_n) - cos(pi k_i) sin(pi k_n)
+// instead of a transcendental, and one float64 reciprocal.
+#include "ftcg_internal.h"
+
+namespace ftcg {
+
+constexpr int WB_BLOCK = 256;
+
+struct WBinGeom {
+  double kmin[2];
+  double h;          // bin edge (k units)
+  int nb[2];         // bins per axis
+  int span;          // neighbour bins each side
+  double R;
+};
+
+template <int DIM>
+__device__ inline int wbin_of(const double* x, const WBinGeom& g, int* b) {
+  int id = 0;
+  for (int a = 0; a < DIM; ++a) {
+    int v = (int)floor((x[a] - g.kmin[a]) / g.h);
+    v = v < 0 ? 0 : (v >= g.nb[a] ? g.nb[a] - 1 : v);
+    b[a] = v;
+    id = id * g.nb[a] + v;
+  }
+  return id;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(WB_BLOCK) void k_wbin_count(const double* __restrict__ k, int64_t m, WBinGeom g,
+                                                         int32_t* __restrict__ cnt, int32_t* __restrict__ bin_of) {
+  const int64_t j = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
+  int id = 0;
+  if (j < m) {
+    double x[DIM];
+    int b[DIM];
+    for (int a = 0; a < DIM; ++a) x[a] = k[j * DIM + a];
+    id = wbin_of<DIM>(x, g, b);
+    bin_of[j] = id;
+  }
+  agg_atomic_add(cnt, id, j < m);
+}
+
+// sorted sample: coordinates, then sin(pi k_a), cos(pi k_a) per axis
+template <int DIM>
+struct WSample {
+  double k[DIM];
+  double sc[DIM][2];
+};
+
+template <int DIM>
+__global__ __launch_bounds__(WB_BLOCK) void k_wbin_scatter(const double* __restrict__ k, int64_t m,
+                                                           const int32_t* __restrict__ bin_of,
+                                                           int32_t* __restrict__ cursor,
+                                                           WSample<DIM>* __restrict__ ss, int32_t* __restrict__ sidx) {
+  const int64_t j = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
+  const int pos = agg_atomic_add(cursor, j < m ? bin_of[j] : 0, j < m);
+  if (j >= m) return;
+  WSample<DIM> w;
+  for (int a = 0; a < DIM; ++a) {
+    w.k[a] = k[j * DIM + a];
+    sincospi(w.k[a], &w.sc[a][0], &w.sc[a][1]);
+  }
+  ss[pos] = w;
+  sidx[pos] = (int32_t)j;
+}
+
+// 1/x to full float64 precision: hardware reciprocal estimate + two Newton steps
+__device__ inline double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// one thread per sorted sample; neighbours of nearby sorted samples are the
+// same bins, so a wavefront walks the same candidate lists together
+template <int DIM>
+__global__ __launch_bounds__(WB_BLOCK) void k_frame_weights(const WSample<DIM>* __restrict__ ss,
+                                                            const int32_t* __restrict__ sidx,
+                                                            const int32_t* __restrict__ boff, int64_t m, WBinGeom g,
+                                                            double* __restrict__ alpha) {
+  int64_t t = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
+  if (t >= m) return;
+  double x[DIM], sn[DIM], cs[DIM];
+  int b[DIM];
+  {
+    const WSample<DIM> me = ss[t];
+    for (int a = 0; a < DIM; ++a) {
+      x[a] = me.k[a];
+      sn[a] = me.sc[a][0];
+      cs[a] = me.sc[a][1];
+    }
+  }
+  wbin_of<DIM>(x, g, b);
+  const double pi = 3.141592653589793238462643383279502884;
+  const double R = g.R;
+  double acc = 0.0;
+  const int lo0 = max(b[0] - g.span, 0), hi0 = min(b[0] + g.span, g.nb[0] - 1);
+  const int lo1 = DIM == 2 ? max(b[DIM - 1] - g.span, 0) : 0;
+  const int hi1 = DIM == 2 ? min(b[DIM - 1] + g.span, g.nb[DIM - 1] - 1) : 0;
+  for (int b0 = lo0; b0 <= hi0; ++b0) {
+    for (int b1 = lo1; b1 <= hi1; ++b1) {
+      const int bin = DIM == 2 ? b0 * g.nb[1] + b1 : b0;
+      const int beg = boff[bin], end = boff[bin + 1];
+      for (int i = beg; i < end; ++i) {
+        const WSample<DIM> o = ss[i];
+        double num = 1.0, den = 1.0;
+        bool inside = true;
+        for (int a = 0; a < DIM; ++a) {
+          const double d = o.k[a] - x[a];
+          inside = inside && (fabs(d) <= R);
+          if (d != 0.0) {
+            // sin(pi (k_i - k_n)) from the per-sample sin/cos
+            num *= o.sc[a][0] * cs[a] - o.sc[a][1] * sn[a];
+            den *= pi * d;
+          }
+        }
+        if (inside) {
+          const double q = num * rcp64(den);
+          acc += q * q;
+        }
+      }
+    }
+  }
+  alpha[sidx[t]] = 1.0 / acc;
+}
+
+static WBinGeom wbin_geom(ftcg_plan p, const double* kmin, const double* kmax) {
+  WBinGeom g{};
+  g.R = p->R;
+  double h = p->R / 2.0;
+  const int max_bins = p->dim == 1 ? (1 << 22) : 2048;
+  for (int a = 0; a < p->dim; ++a) {
+    double ext = kmax[a] - kmin[a];
+    if (ext / h + 1.0 > (double)max_bins) h = ext / (double)(max_bins - 1);
+  }
+  g.h = h;
+  g.span = (int)ceil(p->R / h);
+  for (int a = 0; a < 2; ++a) {
+    g.kmin[a] = a < p->dim ? kmin[a] : 0.0;
+    g.nb[a] = a < p->dim ? (int)floor((kmax[a] - kmin[a]) / h) + 1 : 1;
+  }
+  return g;
+}
+
+void compute_plain_weights_k(ftcg_plan p, const double* k, const double* kmin, const double* kmax) {
+  const WBinGeom g = wbin_geom(p, kmin, kmax);
+  const int64_t m = p->m;
+  const int dim = p->dim;
+  const int64_t nbins = (int64_t)g.nb[0] * g.nb[1];
+  hipStream_t s = p->stream;
+  p->wb_cnt.ensure(sizeof(int32_t) * (nbins + 1));
+  p->wb_off.ensure(sizeof(int32_t) * (nbins + 1));
+  p->wb_of.ensure(sizeof(int32_t) * m);
+  p->ws_k.ensure(sizeof(double) * m * dim * 3);
+  p->ws_idx.ensure(sizeof(int32_t) * m);
+  p->scan_tmp.ensure(scan_tmp_bytes(nbins));
+  int32_t* cnt = p->wb_cnt.as<int32_t>();
+  int32_t* off = p->wb_off.as<int32_t>();
+  const unsigned nb = (unsigned)((m + WB_BLOCK - 1) / WB_BLOCK);
+  timing_begin(p, STEP_WBIN);
+  FTCG_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (nbins + 1), s));
+  if (dim == 1)
+    hipLaunchKernelGGL(k_wbin_count<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, cnt, p->wb_of.as<int32_t>());
+  else
+    hipLaunchKernelGGL(k_wbin_count<2>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, cnt, p->wb_of.as<int32_t>());
+  exclusive_scan_i32(cnt, off, nbins, p->scan_tmp.as<int32_t>(), s);
+  FTCG_HIP(hipMemcpyAsync(cnt, off, sizeof(int32_t) * nbins, hipMemcpyDeviceToDevice, s));
+  if (dim == 1)
+    hipLaunchKernelGGL(k_wbin_scatter<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
+                       p->ws_k.as<WSample<1>>(), p->ws_idx.as<int32_t>());
+  else
+    hipLaunchKernelGGL(k_wbin_scatter<2>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
+                       p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>());
+  timing_end(p, STEP_WBIN);
+  timing_begin(p, STEP_WEIGHTS);
+  if (dim == 1)
+    hipLaunchKernelGGL(k_frame_weights<1>, dim3(nb), dim3(WB_BLOCK), 0, s, p->ws_k.as<WSample<1>>(),
+                       p->ws_idx.as<int32_t>(), off, m, g, p->alpha.as<double>());
+  else
+    hipLaunchKernelGGL(k_frame_weights<2>, dim3(nb), dim3(WB_BLOCK), 0, s, p->ws_k.as<WSample<2>>(),
+                       p->ws_idx.as<int32_t>(), off, m, g, p->alpha.as<double>());
+  FTCG_HIP(hipGetLastError());
+  timing_end(p, STEP_WEIGHTS);
+}
+
+}  // namespace ftcg

@@ -1,0 +1,133 @@
+"""Plan object over the C ABI, taking torch device tensors.
+
+PyTorch only provides device memory and the HIP stream here; every step of
+weighting, binning, spreading, FFT and deapodization runs in libftcg.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib as L
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dptr(t: torch.Tensor, dtype: torch.dtype, numel: int, name: str) -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+class Plan:
+    """One FTCG reconstruction geometry: image size n (per axis), dimension,
+    kernel half-width W, oversampling sigma, precision, weight mode and the
+    weight neighbourhood R. See include/ftcg.h for the conventions."""
+
+    def __init__(self, n: int, dim: int = 2, W: int = 6, sigma: float = 2.0, dtype: str = "f32",
+                 weights: str = "plain", R: float = 8.0, stream=None, device=None):
+        self.n, self.dim, self.W, self.sigma, self.R = int(n), int(dim), int(W), float(sigma), float(R)
+        self.dtype = {"f32": L.FTCG_F32, "f64": L.FTCG_F64}[dtype]
+        self.wmode = {"plain": L.FTCG_W_PLAIN, "learned": L.FTCG_W_LEARNED, "user": L.FTCG_W_USER,
+                      "none": L.FTCG_W_NONE}[weights]
+        self.cdtype = torch.complex64 if self.dtype == L.FTCG_F32 else torch.complex128
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream
+        self._h = C.c_void_p()
+        nn = (C.c_int64 * dim)(*([self.n] * dim))
+        L.check(L.call("ftcg_plan_create", C.byref(self._h), self.dim, nn, self.W, self.sigma, self.dtype,
+                       self.wmode, self.R, C.c_void_p(_stream_ptr(stream))), "ftcg_plan_create")
+        self.m = 0
+        self._k = None
+
+    # -- lifecycle -----------------------------------------------------------
+    def close(self):
+        if self._h:
+            L.call("ftcg_plan_destroy", self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- calls -----------------------------------------------------------------
+    def set_points(self, k: torch.Tensor) -> None:
+        """k: (m, dim) float64 device tensor, cycles per FOV."""
+        m = int(k.shape[0])
+        L.check(L.call("ftcg_set_points", self._h, m, C.c_void_p(_dptr(k, torch.float64, m * self.dim, "k"))),
+                "ftcg_set_points")
+        self.m = m
+
+    def set_weights(self, alpha: torch.Tensor) -> None:
+        L.check(L.call("ftcg_set_weights", self._h, C.c_void_p(_dptr(alpha, torch.float64, self.m, "alpha"))),
+                "ftcg_set_weights")
+
+    def get_weights(self, out: torch.Tensor | None = None):
+        if out is None:
+            out = torch.empty(self.m, dtype=torch.float64, device=self.device)
+        fb = C.c_int(0)
+        L.check(L.call("ftcg_get_weights", self._h, C.c_void_p(_dptr(out, torch.float64, self.m, "alpha")),
+                       C.byref(fb)), "ftcg_get_weights")
+        self.used_fallback = bool(fb.value)
+        return out
+
+    def execute(self, fhat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((self.n,) * self.dim, dtype=self.cdtype, device=self.device)
+        L.check(L.call("ftcg_execute", self._h, C.c_void_p(_dptr(fhat, self.cdtype, self.m, "fhat")),
+                       C.c_void_p(_dptr(out, self.cdtype, self.n ** self.dim, "image"))), "ftcg_execute")
+        return out
+
+    def spread_only(self, fhat: torch.Tensor, grid: torch.Tensor | None = None) -> torch.Tensor:
+        G = self.info()["grid_size"]
+        if grid is None:
+            grid = torch.empty((G,) * self.dim, dtype=self.cdtype, device=self.device)
+        L.check(L.call("ftcg_spread_only", self._h, C.c_void_p(_dptr(fhat, self.cdtype, self.m, "fhat")),
+                       C.c_void_p(_dptr(grid, self.cdtype, G ** self.dim, "grid"))), "ftcg_spread_only")
+        return grid
+
+    def grid_to_image(self, grid: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        G = self.info()["grid_size"]
+        if out is None:
+            out = torch.empty((self.n,) * self.dim, dtype=self.cdtype, device=self.device)
+        L.check(L.call("ftcg_grid_to_image", self._h, C.c_void_p(_dptr(grid, self.cdtype, G ** self.dim, "grid")),
+                       C.c_void_p(_dptr(out, self.cdtype, self.n ** self.dim, "image"))), "ftcg_grid_to_image")
+        return out
+
+    def info(self) -> dict:
+        g, r, t = C.c_int64(), C.c_int64(), C.c_int64()
+        tile = C.c_int()
+        L.check(L.call("ftcg_plan_info", self._h, C.byref(g), C.byref(r), C.byref(t), C.byref(tile)),
+                "ftcg_plan_info")
+        return {"grid_size": g.value, "n_records": r.value, "n_tiles": t.value, "tile": tile.value}
+
+    def set_tuning(self, tile: int = 0, lds_copies: int = 1) -> None:
+        L.check(L.call("ftcg_plan_set_tuning", self._h, int(tile), int(lds_copies)), "ftcg_plan_set_tuning")
+
+    def enable_timing(self, on: bool = True) -> None:
+        L.check(L.call("ftcg_plan_enable_timing", self._h, 1 if on else 0), "ftcg_plan_enable_timing")
+
+    def timing(self) -> dict:
+        ms = (C.c_double * 8)()
+        cnt = (C.c_int64 * 8)()
+        L.check(L.call("ftcg_plan_timing", self._h, ms, cnt), "ftcg_plan_timing")
+        return {L.STEP_NAMES[i]: (ms[i], cnt[i]) for i in range(8) if cnt[i]}
