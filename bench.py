@@ -131,6 +131,7 @@ def main():
     ap.add_argument("--workload", default="sas512_plain", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--accum", default=None, choices=["fixed", "f64"])
     ap.add_argument("--copies", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
@@ -154,8 +155,8 @@ def main():
     out = torch.empty((n,) * dim, dtype=cdt, device=dev)
 
     P = Plan(n, dim=dim, dtype=dtype, weights="plain", R=8.0)
-    if args.tile or args.copies != 1:
-        P.set_tuning(args.tile, args.copies)
+    if args.tile or args.copies != 1 or args.accum:
+        P.set_tuning(args.tile, args.accum, args.copies)
 
     def step():
         P.set_points(kd)
@@ -238,7 +239,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload], "n": n, "m": m,
                    "dim": dim, "W": 6, "sigma": 2.0, "R": 8.0, "weights": "plain", "grid": G,
-                   "tile": info["tile"], "records": info["n_records"], "lds_copies": args.copies},
+                   "tile": info["tile"], "records": info["n_records"], "lds_copies": args.copies,
+                   "accum": args.accum or ("fixed" if dtype == "f32" else "f64")},
         "images_per_s": 1.0 / sec,
         "spread_msamples_per_s": m / (stage_ms["spread"] * 1e-3) / 1e6 if "spread" in stage_ms else None,
         "rel_l2_vs_oracle": rel,

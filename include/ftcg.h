@@ -129,12 +129,27 @@ ftcg_status ftcg_grid_to_image(ftcg_plan plan, const void* grid_dev, void* image
 ftcg_status ftcg_plan_info(ftcg_plan plan, int64_t* grid_size, int64_t* n_records,
                            int64_t* n_tiles, int* tile);
 
-/* Tuning knobs (take effect at the next ftcg_set_points):
- *   tile          : tile edge in grid cells (16, 32, 64 or 128; 0 = automatic).
- *   lds_copies    : 1 = plain float accumulation in one LDS tile;
- *                   2 or 4 = per-wave partial tiles combined at flush with
- *                   compensated (TwoSum) addition. */
-ftcg_status ftcg_plan_set_tuning(ftcg_plan plan, int tile, int lds_copies);
+/* Tile accumulation of the spreading step.
+ *   FTCG_ACCUM_FIXED : float32 plans only (their default). Taps are scaled by a
+ *                      per-tile bound and accumulated exactly as packed int32
+ *                      (re, im) pairs with one 64-bit LDS integer add per tap;
+ *                      results are bitwise reproducible, error <= 2^-31 of the
+ *                      tile bound per tap.
+ *   FTCG_ACCUM_F64   : taps accumulated with float64 LDS atomics (the default
+ *                      and only mode of float64 plans); lds_copies > 1 gives
+ *                      each wavefront its own partial tile, combined at the
+ *                      flush with compensated (TwoSum) addition. */
+typedef enum { FTCG_ACCUM_FIXED = 0, FTCG_ACCUM_F64 = 1 } ftcg_accum;
+
+/* Tuning knobs (take effect at the next ftcg_set_points; the points must be
+ * set again):
+ *   tile       : tile edge in grid cells (16, 32, 64, 128; 0 = automatic);
+ *                FTCG_ACCUM_F64 supports tile <= 64 and
+ *                lds_copies * 16 * tile * (tile + 1) <= 160 KiB.
+ *   accum      : ftcg_accum (FTCG_ACCUM_FIXED needs a float32 plan).
+ *   lds_copies : 1, 2 or 4 (FTCG_ACCUM_F64 only; must be 1 otherwise).
+ * Returns FTCG_EUNSUPPORTED for combinations that do not fit LDS. */
+ftcg_status ftcg_plan_set_tuning(ftcg_plan plan, int tile, int accum, int lds_copies);
 
 /* Per-step timing with HIP events on the plan's stream.
  * enable != 0 records events around every step of later calls; ftcg_plan_timing

@@ -129,6 +129,7 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
   p->stream = static_cast<hipStream_t>(hip_stream);
   p->G = G;
   p->beta = M_PI * (oversampling - 0.5) / (oversampling * half_width);
+  p->accum = dtype == FTCG_F32 ? ACCUM_FIXED : ACCUM_F64;
   ftcg_status st = guarded([&] {
     setup_tiles(p);
     p->flags.ensure(64);
@@ -276,15 +277,20 @@ ftcg_status ftcg_plan_info(ftcg_plan p, int64_t* grid_size, int64_t* n_records, 
   return FTCG_OK;
 }
 
-ftcg_status ftcg_plan_set_tuning(ftcg_plan p, int tile, int lds_copies) {
+ftcg_status ftcg_plan_set_tuning(ftcg_plan p, int tile, int accum, int lds_copies) {
   if (!p) return FTCG_EINVAL;
   if (tile != 0 && tile != 16 && tile != 32 && tile != 64 && tile != 128 && !(p->dim == 1 && is_pow2(tile)))
     return FTCG_EINVAL;
   if (tile != 0 && tile < 2 * p->W) return FTCG_EINVAL;
+  if (accum != FTCG_ACCUM_FIXED && accum != FTCG_ACCUM_F64) return FTCG_EINVAL;
   if (lds_copies != 1 && lds_copies != 2 && lds_copies != 4) return FTCG_EINVAL;
-  const int64_t t = tile ? tile : 64;
-  if (p->dim == 2 && (size_t)lds_copies * 2 * t * (t + 1) * sizeof(double) > 160 * 1024) return FTCG_EUNSUPPORTED;
+  if (accum == FTCG_ACCUM_FIXED && (p->dtype != FTCG_F32 || lds_copies != 1)) return FTCG_EUNSUPPORTED;
+  if (accum == FTCG_ACCUM_F64 && p->dim == 2) {
+    const int64_t t = tile ? tile : 64;
+    if (t > 64 || (size_t)lds_copies * 2 * t * (t + 1) * sizeof(double) > 160 * 1024) return FTCG_EUNSUPPORTED;
+  }
   p->tile_req = tile;
+  p->accum = accum;
   p->lds_copies = lds_copies;
   p->have_points = false;
   return FTCG_OK;

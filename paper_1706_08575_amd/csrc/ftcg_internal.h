@@ -74,6 +74,9 @@ struct Rec {
   int32_t src;
 };
 
+// tile accumulation of float32 plans
+enum Accum { ACCUM_FIXED = 0, ACCUM_F64 = 1 };
+
 enum Step {
   STEP_BIN = 0,      // input check + tile binning of spread records
   STEP_WEIGHTS = 1,  // frame-weight sum kernel
@@ -141,6 +144,7 @@ struct ftcg_plan_s {
   double beta = 0.0;   // kernel exp(-beta s^2)
   int tile_req = 0;    // requested tile edge (0 = automatic)
   int lds_copies = 1;
+  int accum = 0;       // ftcg::Accum for float32 plans (float64 plans always use ACCUM_F64)
 
   // geometry state
   int tile = 64;

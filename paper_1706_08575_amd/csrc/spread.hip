@@ -21,6 +21,8 @@
 //
 // With lds_copies > 1, wave w accumulates into partial tile w % copies and the
 // partial tiles are combined at the flush with compensated (TwoSum) addition.
+#include <type_traits>
+
 #include "ftcg_internal.h"
 
 namespace ftcg {
@@ -135,6 +137,140 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d(const Rec<real>* __re
   }
 }
 
+// ---------------------------------------------------------------------------
+// float32 plans, fixed-point tile accumulation (the default for FTCG_F32)
+//
+// Each tap value x (complex) is scaled by s = (2^31 - 2^24) / B_t, where B_t >=
+// sum over the tile's records of max(|Re c_r|, |Im c_r|) bounds every cell of
+// the tile (kernel values never exceed 1; B_t is formed from order-independent
+// reductions, so it is the same for any record order), truncated to int32 per
+// component,
+// and both components are added with ONE 64-bit LDS integer atomic: the pair
+// (re, im) is packed as im * 2^32 + re in two's complement, and integer
+// addition of packed pairs adds both components exactly as long as neither
+// sum leaves int32, which the bound guarantees. The accumulation is therefore
+// exact and independent of record order (bitwise reproducible), and its only
+// error is the truncation of each tap to 2^-31 B_t.
+//
+// The LDS tile carries 2W - 1 halo rows above and below, so the 2W rows of a
+// record's footprint never need a bounds check (halo rows are dropped at the
+// flush); columns outside the tile are skipped per lane.
+// ---------------------------------------------------------------------------
+
+template <int W, int T>
+__global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* __restrict__ recs,
+                                                              const float* __restrict__ alpha_s,
+                                                              const int32_t* __restrict__ tile_off,
+                                                              const float2* __restrict__ fhat,
+                                                              float2* __restrict__ grid, int64_t G, int nt,
+                                                              float beta) {
+  constexpr int L = 2 * W;              // lanes per record / taps per axis
+  constexpr int PAD = 2 * W - 1;        // halo rows each side
+  constexpr int TP = T + 1;             // row pitch (64-bit words)
+  constexpr int ROWS = T + 2 * PAD;
+  __shared__ unsigned long long acc[ROWS * TP];
+  __shared__ float red[SPREAD_BLOCK / 64];
+  __shared__ long long red2[SPREAD_BLOCK / 64];
+
+  const int tile = blockIdx.x;
+  const int t0 = tile / nt, t1 = tile - (tile / nt) * nt;
+  const int beg = tile_off[tile], end = tile_off[tile + 1];
+  float2* out = grid + (int64_t)t0 * T * G + (int64_t)t1 * T;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  if (beg == end) {
+    const float2 z = {0.f, 0.f};
+    for (int idx = tid; idx < T * T; idx += SPREAD_BLOCK) out[(int64_t)(idx / T) * G + (idx % T)] = z;
+    return;
+  }
+  // Bound of every cell of the tile, computed so that it does not depend on
+  // the order of the records: first the largest |component| of alpha * fhat,
+  // then the integer sum of each record's component bound rounded up in
+  // units of 2^-20 of that maximum.
+  float mx = 0.f;
+  for (int r = beg + tid; r < end; r += SPREAD_BLOCK) {
+    const float a = alpha_s[r];
+    const float2 v = fhat[recs[r].src];
+    mx = fmaxf(mx, fmaxf(fabsf(v.x * a), fabsf(v.y * a)));
+  }
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  if (lane == 0) red[wave] = mx;
+  for (int idx = tid; idx < ROWS * TP; idx += SPREAD_BLOCK) acc[idx] = 0ull;
+  __syncthreads();
+  mx = 0.f;
+#pragma unroll
+  for (int w = 0; w < SPREAD_BLOCK / 64; ++w) mx = fmaxf(mx, red[w]);
+  if (!(mx > 0.f) || !isfinite(mx)) {
+    // all-zero tile, or non-finite values: propagate as the float path would
+    const float fill = mx == 0.f ? 0.f : __builtin_nanf("");
+    const float2 z = {fill, fill};
+    for (int idx = tid; idx < T * T; idx += SPREAD_BLOCK) out[(int64_t)(idx / T) * G + (idx % T)] = z;
+    return;
+  }
+  const float qs = 1048576.f / mx;
+  long long qsum = 0;
+  for (int r = beg + tid; r < end; r += SPREAD_BLOCK) {
+    const float a = alpha_s[r];
+    const float2 v = fhat[recs[r].src];
+    qsum += (long long)ceilf(fmaxf(fabsf(v.x * a), fabsf(v.y * a)) * qs) + 1;
+  }
+  for (int off = 32; off > 0; off >>= 1) qsum += __shfl_xor(qsum, off);
+  __syncthreads();
+  if (lane == 0) reinterpret_cast<long long*>(red2)[wave] = qsum;
+  __syncthreads();
+  qsum = 0;
+#pragma unroll
+  for (int w = 0; w < SPREAD_BLOCK / 64; ++w) qsum += reinterpret_cast<long long*>(red2)[w];
+  const float bound = (float)((double)qsum * (double)mx * (1.0 / 1048576.0) * (1.0 + 1e-6));
+  const float scale = (2147483648.f - 16777216.f) / bound;
+
+  constexpr int RPW = 64 / L;
+  const int s = lane / L, i = lane - (lane / L) * L;
+  const float e2b = __expf(-2.f * beta);
+  constexpr int NWAVES = SPREAD_BLOCK / 64;
+  for (int base = beg + wave * RPW; base < end; base += NWAVES * RPW) {
+    const int r = base + s;
+    if (s < RPW && r < end) {
+      const Rec<float> rec = recs[r];
+      const int c1 = rec.c01 >> 16;
+      const int col = c1 - W + 1 + i;
+      if (col >= 0 && col < T) {
+        const float a = alpha_s[r] * scale;
+        const float2 v = fhat[rec.src];
+        const int c0 = (int)(int16_t)(rec.c01 & 0xffff);
+        const float d1 = (float)(i - W + 1) - rec.f1;
+        const float d0 = (float)(1 - W) - rec.f0;
+        const float w10 = __expf(-beta * (d1 * d1 + d0 * d0)) * a;
+        float q = __expf(-beta * (2.f * d0 + 1.f));
+        float pr = v.x * w10, pi = v.y * w10;
+        unsigned long long* dst = acc + (c0 - W + 1 + PAD) * TP + col;
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+          const int ir = (int)pr, ii = (int)pi;   // truncation toward zero
+          const unsigned hi = (unsigned)ii + (unsigned)(ir >> 31);
+          const unsigned long long packed = ((unsigned long long)hi << 32) | (unsigned)ir;
+          __hip_atomic_fetch_add(dst + j * TP, packed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          pr *= q;
+          pi *= q;
+          q *= e2b;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const float inv = bound / (2147483648.f - 16777216.f);
+  for (int idx = tid; idx < T * T; idx += SPREAD_BLOCK) {
+    const int row = idx / T, col = idx - (idx / T) * T;
+    const unsigned long long vv = acc[(row + PAD) * TP + col];
+    const int re = (int)(unsigned)(vv & 0xffffffffull);
+    const int im = (int)((long long)(vv - (unsigned long long)(long long)re) >> 32);
+    float2 o;
+    o.x = (float)re * inv;
+    o.y = (float)im * inv;
+    out[(int64_t)row * G + col] = o;
+  }
+}
+
 // 1D: one thread per record walks its 2W taps
 template <class real, int W>
 __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread1d(const Rec<real>* __restrict__ recs,
@@ -186,10 +322,33 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread1d(const Rec<real>* __re
   }
 }
 
+template <int W, int T>
+static void launch_fx(ftcg_plan p, const void* fhat, void* grid) {
+  hipLaunchKernelGGL((k_spread2d_fx<W, T>), dim3((unsigned)p->ntiles), dim3(SPREAD_BLOCK), 0, p->stream,
+                     p->recs.as<Rec<float>>(), p->alpha_s.as<float>(), p->tile_off.as<int32_t>(),
+                     static_cast<const float2*>(fhat), static_cast<float2*>(grid), p->G, (int)p->nt, (float)p->beta);
+}
+
+template <int W>
+static void launch_fx_t(ftcg_plan p, const void* fhat, void* grid) {
+  switch (p->tile) {
+    case 16: launch_fx<W, 16>(p, fhat, grid); break;
+    case 32: launch_fx<W, 32>(p, fhat, grid); break;
+    case 64: launch_fx<W, 64>(p, fhat, grid); break;
+    case 128: launch_fx<W, 128>(p, fhat, grid); break;
+    default: throw StatusError{FTCG_EUNSUPPORTED};
+  }
+  FTCG_HIP(hipGetLastError());
+}
+
 template <class real, int W>
 static void launch_spread_w(ftcg_plan p, const void* fhat, void* grid) {
   using cx = typename Cx<real>::t;
   const int T = p->tile;
+  if (std::is_same<real, float>::value && p->dim == 2 && p->accum == ACCUM_FIXED) {
+    launch_fx_t<W>(p, fhat, grid);
+    return;
+  }
   const real beta = (real)p->beta;
   const int copies = p->lds_copies;
   if (p->dim == 2) {

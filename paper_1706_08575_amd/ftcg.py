@@ -120,8 +120,13 @@ class Plan:
                 "ftcg_plan_info")
         return {"grid_size": g.value, "n_records": r.value, "n_tiles": t.value, "tile": tile.value}
 
-    def set_tuning(self, tile: int = 0, lds_copies: int = 1) -> None:
-        L.check(L.call("ftcg_plan_set_tuning", self._h, int(tile), int(lds_copies)), "ftcg_plan_set_tuning")
+    def set_tuning(self, tile: int = 0, accum: str | None = None, lds_copies: int = 1) -> None:
+        """tile: 0 (automatic) or 16/32/64/128; accum: "fixed" (float32 plans'
+        default) or "f64"; lds_copies: partial tiles for "f64"."""
+        if accum is None:
+            accum = "fixed" if self.dtype == L.FTCG_F32 else "f64"
+        a = {"fixed": L.FTCG_ACCUM_FIXED, "f64": L.FTCG_ACCUM_F64}[accum]
+        L.check(L.call("ftcg_plan_set_tuning", self._h, int(tile), a, int(lds_copies)), "ftcg_plan_set_tuning")
 
     def enable_timing(self, on: bool = True) -> None:
         L.check(L.call("ftcg_plan_enable_timing", self._h, 1 if on else 0), "ftcg_plan_enable_timing")

@@ -109,10 +109,12 @@ def test_2d_plain_f64_image(sas512):
     assert O.rel_l2(img, ref) < TOL_F64
 
 
-@pytest.mark.parametrize("tile,copies", [(16, 1), (32, 1), (32, 4), (64, 2)])
-def test_2d_tilings_agree(sas512, tile, copies):
+@pytest.mark.parametrize("tile,accum,copies", [(16, "fixed", 1), (32, "fixed", 1), (64, "fixed", 1),
+                                               (128, "fixed", 1), (16, "f64", 1), (32, "f64", 4),
+                                               (64, "f64", 1), (64, "f64", 2)])
+def test_2d_tilings_agree(sas512, tile, accum, copies):
     k, f, a_ref, ref = sas512
-    img, _, info = run(k, f, 512, "f32", tune=(tile, copies))
+    img, _, info = run(k, f, 512, "f32", tune=(tile, accum, copies))
     assert info["tile"] == tile
     assert O.rel_l2(img, ref) < TOL_F32
 
@@ -121,10 +123,28 @@ def test_tiling_beyond_lds_rejected():
     from paper_1706_08575_amd import _lib as L
     from paper_1706_08575_amd.ftcg import Plan
     with Plan(512, dim=2) as P:
-        for tile, copies in ((128, 1), (64, 4)):
+        for tile, accum, copies in ((128, "f64", 1), (64, "f64", 4), (64, "fixed", 2)):
             with pytest.raises(L.FtcgError) as e:
-                P.set_tuning(tile, copies)
+                P.set_tuning(tile, accum, copies)
             assert e.value.status == L.FTCG_EUNSUPPORTED
+    with Plan(64, dim=2, dtype="f64") as P:
+        with pytest.raises(L.FtcgError) as e:
+            P.set_tuning(64, "fixed", 1)
+        assert e.value.status == L.FTCG_EUNSUPPORTED
+
+
+def test_fixed_accumulation_is_bitwise_reproducible(sas512):
+    # integer accumulation does not depend on the order records are binned in
+    k, f, _, _ = sas512
+    from paper_1706_08575_amd.ftcg import Plan
+    with Plan(512, dim=2) as P:
+        P.set_tuning(64, "fixed", 1)
+        ff = dev(f, torch.complex64)
+        P.set_points(dev(k))
+        a = host(P.execute(ff))
+        P.set_points(dev(k))        # re-binned (atomic slot order may differ)
+        b = host(P.execute(ff))
+    assert np.array_equal(a, b)
 
 
 def test_2d_spread_step_vs_oracle():
