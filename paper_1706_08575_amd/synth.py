@@ -235,3 +235,26 @@ def random_values(seed: int, m: int) -> np.ndarray:
     property tests). Draw order: re (m), im (m)."""
     rng = np.random.default_rng(seed)
     return speckle(rng, m, 1.0)
+
+
+# ----------------------------------------------------------------------------
+# initial parameters of the learned-weight MLP (32 -> 64 -> 64 -> 1)
+# ----------------------------------------------------------------------------
+
+MLP_SHAPES = (("W1", (32, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (64, 1)), ("b3", (1,)))
+
+
+def mlp_init(seed: int = SEED_BASE + 40) -> dict:
+    """Float32 initial parameters, each entry U(-1/sqrt(fan_in), 1/sqrt(fan_in))
+    (the last layer scaled by 0.1 so the initial correction is small).
+    Draw order: the shapes above, in order."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for name, shp in MLP_SHAPES:
+        fan_in = shp[0] if len(shp) == 2 else (64 if name != "b1" else 32)
+        lim = 1.0 / math.sqrt(fan_in)
+        v = rng.uniform(-lim, lim, size=shp)
+        if name in ("W3", "b3"):
+            v = 0.1 * v
+        out[name] = v.astype(np.float32)
+    return out
