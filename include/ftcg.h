@@ -155,11 +155,86 @@ ftcg_status ftcg_plan_set_tuning(ftcg_plan plan, int tile, int accum, int lds_co
  * enable != 0 records events around every step of later calls; ftcg_plan_timing
  * synchronises the stream and returns, for each step s in
  * {0 input check + tile binning, 1 frame-weight sum kernel, 2 spread,
- *  3 fft pass 1, 4 fft pass 2 + deapodize + crop, 5 neighbour binning for weights},
+ *  3 fft pass 1, 4 fft pass 2 + deapodize + crop, 5 neighbour binning for weights,
+ *  6 learned-weight inference, 7 learned-weight audit},
  * the summed milliseconds ms[s] and the number of launches count[s]
  * (arrays of 8 entries; unused entries are 0), then resets the sums. */
 ftcg_status ftcg_plan_enable_timing(ftcg_plan plan, int enable);
 ftcg_status ftcg_plan_timing(ftcg_plan plan, double* ms, int64_t* count);
+
+/* ------------------------------------------------------------------------
+ * Learned frame weights (FTCG_W_LEARNED). Not in the paper: a small network
+ * predicts the frame-optimal weight of eq:difopt from the local raster
+ * geometry, and the plain float64 weights remain the fallback and the judge
+ * of its error.
+ *   feature of sample j : offsets k_i - k_j (float32, nearest first) of the 16
+ *                         nearest other samples within ||k_i - k_j||_inf <= R,
+ *                         ranked by float32 squared distance, ties by the
+ *                         smaller index; missing neighbours are (R, R);
+ *   base_j              : 1 / (1 + sum over the 16 of sinc^2(dx) sinc^2(dy));
+ *   network             : y = W3^T s(W2^T s(W1^T x + b1) + b2) + b3, SiLU s,
+ *                         widths 32 -> 64 -> 64 -> 1; inference in half
+ *                         precision weights/activations, float32 accumulation;
+ *   weight              : alpha_hat_j = base_j exp(y_j);
+ *   training target     : log(alpha_j / base_j), mean squared error, Adam on
+ *                         float32 master weights.
+ * Parameter vector (FTCG_MLP_NPARAM floats, host order): W1 [32][64]
+ * row-major, b1 [64], W2 [64][64] row-major, b2 [64], W3 [64], b3 [1].
+ * ------------------------------------------------------------------------ */
+#define FTCG_MLP_NPARAM 6337
+
+typedef struct ftcg_mlp_s* ftcg_mlp;
+
+/* Create / destroy a network (parameters zero until set or loaded). */
+ftcg_status ftcg_mlp_create(ftcg_mlp* out, void* hip_stream);
+ftcg_status ftcg_mlp_destroy(ftcg_mlp mlp);
+
+/* Host parameter vectors of FTCG_MLP_NPARAM floats (n must equal it).
+ * Setting parameters resets the Adam state. Both calls synchronise. */
+ftcg_status ftcg_mlp_set_params(ftcg_mlp mlp, const float* params_host, int64_t n);
+ftcg_status ftcg_mlp_get_params(ftcg_mlp mlp, float* params_host, int64_t n);
+
+/* Serialise parameters + Adam state (little-endian, versioned header).
+ * blob_host == NULL: *bytes receives the size needed. */
+ftcg_status ftcg_mlp_save(ftcg_mlp mlp, void* blob_host, size_t* bytes);
+ftcg_status ftcg_mlp_load(ftcg_mlp mlp, const void* blob_host, size_t bytes);
+
+/* Features (m x 32 float32, device) and base (m float64, device) of a 2D
+ * raster k_dev (m x 2 float64, device); with target_dev != NULL also the
+ * training target log(alpha / base) (m float32) from the plain weights. */
+ftcg_status ftcg_mlp_features(ftcg_mlp mlp, int64_t m, const double* k_dev, double R, float* feat_dev,
+                              double* base_dev, float* target_dev);
+
+/* Network output y for n feature rows (inference kernel, half precision). */
+ftcg_status ftcg_mlp_forward(ftcg_mlp mlp, int64_t n, const float* feat_dev, float* y_dev);
+
+/* Gradient (FTCG_MLP_NPARAM floats, device) and loss (host) of the mean
+ * squared error over n rows; fp16 != 0 rounds weights and activations to half
+ * in the forward pass as inference does. Does not change the parameters. */
+ftcg_status ftcg_mlp_loss_grad(ftcg_mlp mlp, int64_t n, const float* feat_dev, const float* target_dev,
+                               int fp16, float* grad_dev, double* loss_host);
+
+/* One Adam step (learning rate lr) on the mean squared error of n rows. */
+ftcg_status ftcg_mlp_train_batch(ftcg_mlp mlp, int64_t n, const float* feat_dev, const float* target_dev,
+                                 int fp16, float lr, double* loss_host);
+
+/* Train on one raster: plain weights and features on the GPU, then Adam
+ * steps over minibatches of `batch` samples (sample j in minibatch j mod
+ * ceil(m / batch)). loss_host receives the mean loss over the raster. */
+ftcg_status ftcg_mlp_train_raster(ftcg_mlp mlp, int64_t m, const double* k_dev, double R, int64_t batch,
+                                  float lr, int fp16, double* loss_host);
+
+/* Attach a network to a FTCG_W_LEARNED plan (the plan keeps the pointer; the
+ * network must outlive it). At each ftcg_set_points the plan predicts all
+ * weights, recomputes the plain weights of audit_samples evenly spaced
+ * samples (caller indices floor(q m / n)), and falls back to the plain
+ * weights of every sample when the relative RMS difference exceeds
+ * audit_threshold (the estimated relative L2 error of the image for values
+ * of equal magnitude). */
+ftcg_status ftcg_plan_set_mlp(ftcg_plan plan, ftcg_mlp mlp, double audit_threshold, int64_t audit_samples);
+
+/* Estimate of the last audit and whether the plan fell back (host outputs). */
+ftcg_status ftcg_plan_learned_report(ftcg_plan plan, double* audit_estimate, int* used_fallback);
 
 #ifdef __cplusplus
 }

@@ -10,10 +10,12 @@ frame-optimal weights of Sec. III-C eq:difopt); the definitions below are the
 ones the GPU library implements, written out plainly:
 
   features of sample j: the 16 other samples i with ||k_i - k_j||_inf <= R
-    nearest to j in squared Euclidean distance d2 = dx*dx + dy*dy (float64,
-    products and sum rounded separately), ties broken by the smaller index;
-    the feature is (dx_1, dy_1, ..., dx_16, dy_16) with d = k_i - k_j, nearest
-    first; missing neighbours are (R, R).
+    nearest to j in squared Euclidean distance, ranked in float32: with
+    d = k_i - k_j formed in float64 and rounded to float32 per axis,
+    d2 = dx*dx + dy*dy with each product and the sum rounded to float32 (no
+    fused multiply-add); ties broken by the smaller index. The feature is
+    (dx_1, dy_1, ..., dx_16, dy_16) as float32, nearest first; missing
+    neighbours are (R, R).
   analytic estimate: base_j = 1 / (1 + sum over the 16 of sinc^2(dx) sinc^2(dy)).
   network: y = W3^T s(W2^T s(W1^T x + b1) + b2) + b3 with s(z) = z / (1 + e^-z)
     (SiLU), x the 32 features, widths 32 -> 64 -> 64 -> 1.
@@ -61,7 +63,7 @@ def knn_features(k: np.ndarray, R: float = 8.0, K: int = K_NN, at=None):
     k = np.asarray(k, dtype=np.float64)
     targets_ = np.arange(k.shape[0]) if at is None else np.asarray(at, dtype=np.int64)
     tree = cKDTree(k)
-    feats = np.full((len(targets_), 2 * K), R, dtype=np.float64)
+    feats = np.full((len(targets_), 2 * K), R, dtype=np.float32)
     base = np.empty(len(targets_))
     lists = tree.query_ball_point(k[targets_], r=R, p=np.inf)
     for t, j in enumerate(targets_):
@@ -70,10 +72,11 @@ def knn_features(k: np.ndarray, R: float = 8.0, K: int = K_NN, at=None):
             base[t] = 1.0
             continue
         d = k[idx] - k[j]
-        d2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]
+        d32 = d.astype(np.float32)
+        d2 = d32[:, 0] * d32[:, 0] + d32[:, 1] * d32[:, 1]     # float32 arithmetic
         order = np.lexsort((idx, d2))[:K]
         sel = d[order]
-        feats[t, :2 * len(sel)] = sel.ravel()
+        feats[t, :2 * len(sel)] = sel.astype(np.float32).ravel()
         g = np.prod(np.sinc(sel), axis=1)
         base[t] = 1.0 / (1.0 + np.sum(g * g))
     return feats, base

@@ -18,7 +18,7 @@ FTCG_F64, FTCG_F32 = 0, 1
 FTCG_W_PLAIN, FTCG_W_LEARNED, FTCG_W_USER, FTCG_W_NONE = range(4)
 FTCG_ACCUM_FIXED, FTCG_ACCUM_F64 = 0, 1
 
-STEP_NAMES = ("bin", "weights", "spread", "fft1", "fft2_deapod", "weight_bin", "s6", "s7")
+STEP_NAMES = ("bin", "weights", "spread", "fft1", "fft2_deapod", "weight_bin", "learned", "audit")
 
 
 class FtcgError(RuntimeError):
@@ -46,9 +46,27 @@ _SIGS = [
     ("ftcg_plan_set_tuning", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     ("ftcg_plan_enable_timing", C.c_int, [C.c_void_p, C.c_int]),
     ("ftcg_plan_timing", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    ("ftcg_mlp_create", C.c_int, [C.POINTER(C.c_void_p), C.c_void_p]),
+    ("ftcg_mlp_destroy", C.c_int, [C.c_void_p]),
+    ("ftcg_mlp_set_params", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    ("ftcg_mlp_get_params", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    ("ftcg_mlp_save", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_size_t)]),
+    ("ftcg_mlp_load", C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    ("ftcg_mlp_features", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
+    ("ftcg_mlp_forward", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    ("ftcg_mlp_loss_grad", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                     C.POINTER(C.c_double)]),
+    ("ftcg_mlp_train_batch", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_float,
+                                       C.POINTER(C.c_double)]),
+    ("ftcg_mlp_train_raster", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_double, C.c_int64, C.c_float,
+                                        C.c_int, C.POINTER(C.c_double)]),
+    ("ftcg_plan_set_mlp", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]),
+    ("ftcg_plan_learned_report", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
 ]
 
 EXPORTED = [s[0] for s in _SIGS]
+MLP_NPARAM = 6337
 
 
 def lib() -> C.CDLL:

@@ -5,6 +5,7 @@
 #include <new>
 
 #include "ftcg_internal.h"
+#include "mlp_internal.h"
 
 namespace ftcg {
 
@@ -115,7 +116,7 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
   if ((G % 4) != 0 || !is_pow2(G)) return FTCG_EUNSUPPORTED;
   if (G > (dtype == FTCG_F32 ? 16384 : 8192)) return FTCG_EUNSUPPORTED;
   if (2 * half_width > G) return FTCG_EINVAL;
-  if (wmode == FTCG_W_LEARNED) return FTCG_EUNSUPPORTED;
+  if (wmode == FTCG_W_LEARNED && dim != 2) return FTCG_EUNSUPPORTED;
 
   ftcg_plan p = new (std::nothrow) ftcg_plan_s();
   if (!p) return FTCG_ENOMEM;
@@ -132,13 +133,13 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
   p->accum = dtype == FTCG_F32 ? ACCUM_FIXED : ACCUM_F64;
   ftcg_status st = guarded([&] {
     setup_tiles(p);
-    p->flags.ensure(64);
+    p->flags.ensure(128);
     p->deapod.ensure(sizeof(double) * n0);
     compute_deapod(p);
     const size_t csz = dtype == FTCG_F64 ? 16 : 8;
     p->grid.ensure(csz * (size_t)(dim == 2 ? G * G : G));
     if (dim == 2) p->fft_tmp.ensure(csz * (size_t)(n0 * G));
-    if (hipHostMalloc((void**)&p->host_flags, 64, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&p->host_flags, 128, hipHostMallocDefault) != hipSuccess) {
       p->host_flags = nullptr;
       throw StatusError{FTCG_ENOMEM};
     }
@@ -155,7 +156,7 @@ ftcg_status ftcg_plan_destroy(ftcg_plan p) {
   if (!p) return FTCG_EINVAL;
   (void)hipStreamSynchronize(p->stream);
   DevBuf* bufs[] = {&p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp,
-                    &p->flags,  &p->wb_cnt, &p->wb_off, &p->ws_k,   &p->ws_idx,   &p->wb_of,
+                    &p->flags,  &p->wb_cnt, &p->wb_off, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->sc_orig, &p->audit_buf,
                     &p->grid,   &p->fft_tmp, &p->deapod, &p->tile_order};
   for (DevBuf* b : bufs) b->release();
   for (auto& pr : p->timing.pending) {
@@ -192,12 +193,36 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     p->alpha.ensure(sizeof(double) * m);
     if (p->wmode == FTCG_W_PLAIN) {
       timing_end(p, STEP_BIN);
-      compute_plain_weights_k(p, k_dev, kmin, kmax);
+      build_weight_bins(p, k_dev, kmin, kmax);
+      run_plain_weights(p);
+      timing_begin(p, STEP_BIN);
+      p->have_weights = true;
+    } else if (p->wmode == FTCG_W_LEARNED) {
+      if (!p->mlp) throw StatusError{FTCG_ESTATE};
+      timing_end(p, STEP_BIN);
+      build_weight_bins(p, k_dev, kmin, kmax);
+      timing_begin(p, STEP_LEARNED);
+      launch_learned_weights(p, k_dev, p->mlp);
+      timing_end(p, STEP_LEARNED);
+      timing_begin(p, STEP_AUDIT);
+      double* est_dev = p->flags.as<double>() + 6;
+      launch_audit(p, k_dev, est_dev);
+      FTCG_HIP(hipMemcpyAsync(p->host_flags + 6, est_dev, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+      FTCG_HIP(hipStreamSynchronize(p->stream));
+      timing_end(p, STEP_AUDIT);
+      p->audit_estimate = p->host_flags[6];
+      p->used_fallback = !(p->audit_estimate <= p->audit_threshold);
+      if (p->used_fallback) run_plain_weights(p);
       timing_begin(p, STEP_BIN);
       p->have_weights = true;
     } else if (p->wmode == FTCG_W_NONE) {
       fill_ones(p->alpha.as<double>(), m, p->stream);
       p->have_weights = true;
+    }
+    if (p->weights_only) {
+      timing_end(p, STEP_BIN);
+      p->have_points = true;
+      return;
     }
     // 3) tile binning of spread records (worst case 2^dim records per sample)
     setup_tiles(p);
@@ -266,6 +291,25 @@ ftcg_status ftcg_execute(ftcg_plan p, const void* fhat_dev, void* image_dev) {
     timing_end(p, STEP_SPREAD);
     grid_to_image(p, p->grid.p, image_dev);
   });
+}
+
+ftcg_status ftcg_plan_set_mlp(ftcg_plan p, ftcg_mlp mlp, double audit_threshold, int64_t audit_samples) {
+  if (!p || !mlp) return FTCG_EINVAL;
+  if (p->wmode != FTCG_W_LEARNED) return FTCG_ESTATE;
+  if (!(audit_threshold >= 0.0) || audit_samples < 1) return FTCG_EINVAL;
+  p->mlp = mlp;
+  p->audit_threshold = audit_threshold;
+  p->audit_samples = audit_samples;
+  p->have_points = false;
+  return FTCG_OK;
+}
+
+ftcg_status ftcg_plan_learned_report(ftcg_plan p, double* audit_estimate, int* used_fallback) {
+  if (!p) return FTCG_EINVAL;
+  if (p->wmode != FTCG_W_LEARNED || !p->have_weights) return FTCG_ESTATE;
+  if (audit_estimate) *audit_estimate = p->audit_estimate;
+  if (used_fallback) *used_fallback = p->used_fallback;
+  return FTCG_OK;
 }
 
 ftcg_status ftcg_plan_info(ftcg_plan p, int64_t* grid_size, int64_t* n_records, int64_t* n_tiles, int* tile) {

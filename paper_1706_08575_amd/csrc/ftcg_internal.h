@@ -74,6 +74,22 @@ struct Rec {
   int32_t src;
 };
 
+// neighbour bins of the frame-weight sum (square bins of edge h in k units)
+struct WBinGeom {
+  double kmin[2];
+  double h;          // bin edge (k units)
+  int nb[2];         // bins per axis
+  int span;          // neighbour bins each side covering the box of radius R
+  double R;
+};
+
+// a sample in bin order: coordinates, then sin(pi k_a), cos(pi k_a) per axis
+template <int DIM>
+struct WSample {
+  double k[DIM];
+  double sc[DIM][2];
+};
+
 // tile accumulation of float32 plans
 enum Accum { ACCUM_FIXED = 0, ACCUM_F64 = 1 };
 
@@ -84,6 +100,8 @@ enum Step {
   STEP_FFT1 = 3,
   STEP_FFT2 = 4,     // second FFT pass + deapodize + crop (the only pass in 1D)
   STEP_WBIN = 5,     // neighbour binning for the weight sum
+  STEP_LEARNED = 6,  // fused 16-NN + MLP inference
+  STEP_AUDIT = 7,    // audit of learned weights against plain ones
   N_STEPS = 8
 };
 
@@ -169,6 +187,17 @@ struct ftcg_plan_s {
   ftcg::DevBuf ws_k;         // sorted samples: k, sin(pi k), cos(pi k) (3*dim doubles each)
   ftcg::DevBuf ws_idx;       // sorted original index
   ftcg::DevBuf wb_of;        // weight-bin id per sample (caller order)
+  ftcg::DevBuf sc_orig;      // sin(pi k_a), cos(pi k_a) per sample, caller order (2*dim doubles)
+  ftcg::WBinGeom wgeom{};
+  bool have_wbins = false;
+  bool weights_only = false;  // internal plans that only compute weights (no tile binning)
+
+  // learned weights
+  struct ftcg_mlp_s* mlp = nullptr;
+  double audit_threshold = 1e-4;
+  int64_t audit_samples = 4096;
+  double audit_estimate = -1.0;
+  ftcg::DevBuf audit_buf;    // audit indices / plain weights / scratch
 
   // execute workspace
   ftcg::DevBuf grid;         // G^dim complex
@@ -186,8 +215,11 @@ namespace ftcg {
 void launch_check_points(ftcg_plan p, const double* k, int64_t m, double* flags);
 void bin_points_k(ftcg_plan p, const double* k);   // fills recs, alpha_s, tile_off
 void refill_alpha(ftcg_plan p);                     // alpha_s[r] = alpha[recs[r].src]
-void compute_plain_weights_k(ftcg_plan p, const double* k, const double* kmin,
-                             const double* kmax);   // fills alpha (caller order)
+void build_weight_bins(ftcg_plan p, const double* k, const double* kmin,
+                       const double* kmax);         // sorted neighbour bins (+ sin/cos)
+void run_plain_weights(ftcg_plan p);                // alpha (caller order) from the bins
+// plain weights of the samples idx[0..n) (caller indices) into out[0..n)
+void plain_weights_at(ftcg_plan p, const double* k, const int32_t* idx, int64_t n, double* out);
 void fill_ones(double* a, int64_t m, hipStream_t s);
 void spread(ftcg_plan p, const void* fhat, void* grid);
 void grid_to_image(ftcg_plan p, const void* grid, void* image);

@@ -20,14 +20,6 @@ namespace ftcg {
 
 constexpr int WB_BLOCK = 256;
 
-struct WBinGeom {
-  double kmin[2];
-  double h;          // bin edge (k units)
-  int nb[2];         // bins per axis
-  int span;          // neighbour bins each side
-  double R;
-};
-
 template <int DIM>
 __device__ inline int wbin_of(const double* x, const WBinGeom& g, int* b) {
   int id = 0;
@@ -55,18 +47,12 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wbin_count(const double* __restric
   agg_atomic_add(cnt, id, j < m);
 }
 
-// sorted sample: coordinates, then sin(pi k_a), cos(pi k_a) per axis
-template <int DIM>
-struct WSample {
-  double k[DIM];
-  double sc[DIM][2];
-};
-
 template <int DIM>
 __global__ __launch_bounds__(WB_BLOCK) void k_wbin_scatter(const double* __restrict__ k, int64_t m,
                                                            const int32_t* __restrict__ bin_of,
                                                            int32_t* __restrict__ cursor,
-                                                           WSample<DIM>* __restrict__ ss, int32_t* __restrict__ sidx) {
+                                                           WSample<DIM>* __restrict__ ss, int32_t* __restrict__ sidx,
+                                                           double* __restrict__ sc_orig) {
   const int64_t j = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
   const int pos = agg_atomic_add(cursor, j < m ? bin_of[j] : 0, j < m);
   if (j >= m) return;
@@ -74,6 +60,8 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wbin_scatter(const double* __restr
   for (int a = 0; a < DIM; ++a) {
     w.k[a] = k[j * DIM + a];
     sincospi(w.k[a], &w.sc[a][0], &w.sc[a][1]);
+    sc_orig[j * 2 * DIM + 2 * a] = w.sc[a][0];
+    sc_orig[j * 2 * DIM + 2 * a + 1] = w.sc[a][1];
   }
   ss[pos] = w;
   sidx[pos] = (int32_t)j;
@@ -88,25 +76,11 @@ __device__ inline double rcp64(double x) {
   return fma(r, e, r);
 }
 
-// one thread per sorted sample; neighbours of nearby sorted samples are the
-// same bins, so a wavefront walks the same candidate lists together
+// sum over the box neighbours i of sample (x, sin, cos) of T_in^2
 template <int DIM>
-__global__ __launch_bounds__(WB_BLOCK) void k_frame_weights(const WSample<DIM>* __restrict__ ss,
-                                                            const int32_t* __restrict__ sidx,
-                                                            const int32_t* __restrict__ boff, int64_t m, WBinGeom g,
-                                                            double* __restrict__ alpha) {
-  int64_t t = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
-  if (t >= m) return;
-  double x[DIM], sn[DIM], cs[DIM];
+__device__ inline double gram_row_sum(const WSample<DIM>* __restrict__ ss, const int32_t* __restrict__ boff,
+                                      const WBinGeom& g, const double* x, const double* sn, const double* cs) {
   int b[DIM];
-  {
-    const WSample<DIM> me = ss[t];
-    for (int a = 0; a < DIM; ++a) {
-      x[a] = me.k[a];
-      sn[a] = me.sc[a][0];
-      cs[a] = me.sc[a][1];
-    }
-  }
   wbin_of<DIM>(x, g, b);
   const double pi = 3.141592653589793238462643383279502884;
   const double R = g.R;
@@ -138,7 +112,46 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights(const WSample<DIM>* 
       }
     }
   }
-  alpha[sidx[t]] = 1.0 / acc;
+  return acc;
+}
+
+// one thread per sorted sample; neighbours of nearby sorted samples are the
+// same bins, so a wavefront walks the same candidate lists together
+template <int DIM>
+__global__ __launch_bounds__(WB_BLOCK) void k_frame_weights(const WSample<DIM>* __restrict__ ss,
+                                                            const int32_t* __restrict__ sidx,
+                                                            const int32_t* __restrict__ boff, int64_t m, WBinGeom g,
+                                                            double* __restrict__ alpha) {
+  int64_t t = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
+  if (t >= m) return;
+  double x[DIM], sn[DIM], cs[DIM];
+  const WSample<DIM> me = ss[t];
+  for (int a = 0; a < DIM; ++a) {
+    x[a] = me.k[a];
+    sn[a] = me.sc[a][0];
+    cs[a] = me.sc[a][1];
+  }
+  alpha[sidx[t]] = 1.0 / gram_row_sum<DIM>(ss, boff, g, x, sn, cs);
+}
+
+// the same sum for listed samples (caller indices), for audits and checks
+template <int DIM>
+__global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const double* __restrict__ k,
+                                                               const double* __restrict__ sc_orig,
+                                                               const int32_t* __restrict__ idx, int64_t n,
+                                                               const WSample<DIM>* __restrict__ ss,
+                                                               const int32_t* __restrict__ boff, WBinGeom g,
+                                                               double* __restrict__ out) {
+  int64_t t = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
+  if (t >= n) return;
+  const int64_t j = idx[t];
+  double x[DIM], sn[DIM], cs[DIM];
+  for (int a = 0; a < DIM; ++a) {
+    x[a] = k[j * DIM + a];
+    sn[a] = sc_orig[j * 2 * DIM + 2 * a];
+    cs[a] = sc_orig[j * 2 * DIM + 2 * a + 1];
+  }
+  out[t] = 1.0 / gram_row_sum<DIM>(ss, boff, g, x, sn, cs);
 }
 
 static WBinGeom wbin_geom(ftcg_plan p, const double* kmin, const double* kmax) {
@@ -159,8 +172,9 @@ static WBinGeom wbin_geom(ftcg_plan p, const double* kmin, const double* kmax) {
   return g;
 }
 
-void compute_plain_weights_k(ftcg_plan p, const double* k, const double* kmin, const double* kmax) {
+void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const double* kmax) {
   const WBinGeom g = wbin_geom(p, kmin, kmax);
+  p->wgeom = g;
   const int64_t m = p->m;
   const int dim = p->dim;
   const int64_t nbins = (int64_t)g.nb[0] * g.nb[1];
@@ -170,6 +184,7 @@ void compute_plain_weights_k(ftcg_plan p, const double* k, const double* kmin, c
   p->wb_of.ensure(sizeof(int32_t) * m);
   p->ws_k.ensure(sizeof(double) * m * dim * 3);
   p->ws_idx.ensure(sizeof(int32_t) * m);
+  p->sc_orig.ensure(sizeof(double) * m * dim * 2);
   p->scan_tmp.ensure(scan_tmp_bytes(nbins));
   int32_t* cnt = p->wb_cnt.as<int32_t>();
   int32_t* off = p->wb_off.as<int32_t>();
@@ -184,20 +199,41 @@ void compute_plain_weights_k(ftcg_plan p, const double* k, const double* kmin, c
   FTCG_HIP(hipMemcpyAsync(cnt, off, sizeof(int32_t) * nbins, hipMemcpyDeviceToDevice, s));
   if (dim == 1)
     hipLaunchKernelGGL(k_wbin_scatter<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
-                       p->ws_k.as<WSample<1>>(), p->ws_idx.as<int32_t>());
+                       p->ws_k.as<WSample<1>>(), p->ws_idx.as<int32_t>(), p->sc_orig.as<double>());
   else
     hipLaunchKernelGGL(k_wbin_scatter<2>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
-                       p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>());
+                       p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), p->sc_orig.as<double>());
+  FTCG_HIP(hipGetLastError());
   timing_end(p, STEP_WBIN);
+  p->have_wbins = true;
+}
+
+void run_plain_weights(ftcg_plan p) {
+  const int64_t m = p->m;
+  const unsigned nb = (unsigned)((m + WB_BLOCK - 1) / WB_BLOCK);
+  const int32_t* off = p->wb_off.as<int32_t>();
   timing_begin(p, STEP_WEIGHTS);
-  if (dim == 1)
-    hipLaunchKernelGGL(k_frame_weights<1>, dim3(nb), dim3(WB_BLOCK), 0, s, p->ws_k.as<WSample<1>>(),
-                       p->ws_idx.as<int32_t>(), off, m, g, p->alpha.as<double>());
+  if (p->dim == 1)
+    hipLaunchKernelGGL(k_frame_weights<1>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, p->ws_k.as<WSample<1>>(),
+                       p->ws_idx.as<int32_t>(), off, m, p->wgeom, p->alpha.as<double>());
   else
-    hipLaunchKernelGGL(k_frame_weights<2>, dim3(nb), dim3(WB_BLOCK), 0, s, p->ws_k.as<WSample<2>>(),
-                       p->ws_idx.as<int32_t>(), off, m, g, p->alpha.as<double>());
+    hipLaunchKernelGGL(k_frame_weights<2>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, p->ws_k.as<WSample<2>>(),
+                       p->ws_idx.as<int32_t>(), off, m, p->wgeom, p->alpha.as<double>());
   FTCG_HIP(hipGetLastError());
   timing_end(p, STEP_WEIGHTS);
+}
+
+void plain_weights_at(ftcg_plan p, const double* k, const int32_t* idx, int64_t n, double* out) {
+  if (n <= 0) return;
+  const unsigned nb = (unsigned)((n + WB_BLOCK - 1) / WB_BLOCK);
+  const int32_t* off = p->wb_off.as<int32_t>();
+  if (p->dim == 1)
+    hipLaunchKernelGGL(k_frame_weights_at<1>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, k, p->sc_orig.as<double>(),
+                       idx, n, p->ws_k.as<WSample<1>>(), off, p->wgeom, out);
+  else
+    hipLaunchKernelGGL(k_frame_weights_at<2>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, k, p->sc_orig.as<double>(),
+                       idx, n, p->ws_k.as<WSample<2>>(), off, p->wgeom, out);
+  FTCG_HIP(hipGetLastError());
 }
 
 }  // namespace ftcg

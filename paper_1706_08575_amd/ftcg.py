@@ -128,6 +128,19 @@ class Plan:
         a = {"fixed": L.FTCG_ACCUM_FIXED, "f64": L.FTCG_ACCUM_F64}[accum]
         L.check(L.call("ftcg_plan_set_tuning", self._h, int(tile), a, int(lds_copies)), "ftcg_plan_set_tuning")
 
+    def set_mlp(self, mlp, audit_threshold: float = 1e-4, audit_samples: int = 4096) -> None:
+        """Attach a learned-weight network (FTCG_W_LEARNED plans); the plan
+        keeps a reference so the network outlives it."""
+        self._mlp = mlp
+        L.check(L.call("ftcg_plan_set_mlp", self._h, mlp._h, float(audit_threshold), int(audit_samples)),
+                "ftcg_plan_set_mlp")
+
+    def learned_report(self) -> dict:
+        est = C.c_double(0.0)
+        fb = C.c_int(0)
+        L.check(L.call("ftcg_plan_learned_report", self._h, C.byref(est), C.byref(fb)), "ftcg_plan_learned_report")
+        return {"audit_estimate": est.value, "used_fallback": bool(fb.value)}
+
     def enable_timing(self, on: bool = True) -> None:
         L.check(L.call("ftcg_plan_enable_timing", self._h, 1 if on else 0), "ftcg_plan_enable_timing")
 

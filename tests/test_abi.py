@@ -73,5 +73,15 @@ def test_null_arguments():
                        ("ftcg_get_weights", (None, None, None)), ("ftcg_plan_set_tuning", (None, 64, 0, 1)),
                        ("ftcg_plan_info", (None, None, None, None, None)),
                        ("ftcg_spread_only", (None, None, None)), ("ftcg_grid_to_image", (None, None, None)),
-                       ("ftcg_plan_enable_timing", (None, 1)), ("ftcg_plan_timing", (None, None, None))):
+                       ("ftcg_plan_enable_timing", (None, 1)), ("ftcg_plan_timing", (None, None, None)),
+                       ("ftcg_mlp_create", (None, None)), ("ftcg_mlp_destroy", (None,)),
+                       ("ftcg_mlp_set_params", (None, None, 6337)), ("ftcg_mlp_get_params", (None, None, 6337)),
+                       ("ftcg_mlp_save", (None, None, None)), ("ftcg_mlp_load", (None, None, 0)),
+                       ("ftcg_mlp_features", (None, 1, None, 8.0, None, None, None)),
+                       ("ftcg_mlp_forward", (None, 1, None, None)),
+                       ("ftcg_mlp_loss_grad", (None, 1, None, None, 0, None, None)),
+                       ("ftcg_mlp_train_batch", (None, 1, None, None, 0, 0.0, None)),
+                       ("ftcg_mlp_train_raster", (None, 1, None, 8.0, 16, 0.0, 0, None)),
+                       ("ftcg_plan_set_mlp", (None, None, 1e-4, 16)),
+                       ("ftcg_plan_learned_report", (None, None, None))):
         assert L.call(name, *args) == L.FTCG_EINVAL, name

@@ -104,11 +104,15 @@ def test_knn_features_vs_full_distance_matrix():
     R = 30.0   # the box covers everything: plain k-nearest on the full matrix
     F, base = M.knn_features(k, R)
     D = k[None, :, :] - k[:, None, :]
-    d2 = D[..., 0] * D[..., 0] + D[..., 1] * D[..., 1]
+    D32 = D.astype(np.float32)
+    d2 = (D32[..., 0] * D32[..., 0] + D32[..., 1] * D32[..., 1]).astype(np.float64)
     np.fill_diagonal(d2, np.inf)
     for j in (0, 17, 299):
         order = np.lexsort((np.arange(300), d2[j]))[:16]
-        assert np.array_equal(F[j].reshape(16, 2), D[j, order])
+        assert np.array_equal(F[j].reshape(16, 2), D32[j, order])
+        # ranking in float32 agrees with exact distances away from ties
+        exact = np.argsort(np.sum(D[j] ** 2, axis=1) + np.where(np.arange(300) == j, np.inf, 0))[:16]
+        assert set(exact) == set(order)
         g = np.prod(np.sinc(D[j, order]), axis=1)
         assert abs(base[j] - 1.0 / (1.0 + np.sum(g * g))) < 1e-15
     sub, bsub = M.knn_features(k, R, at=[17, 299])
