@@ -236,6 +236,45 @@ ftcg_status ftcg_plan_set_mlp(ftcg_plan plan, ftcg_mlp mlp, double audit_thresho
 /* Estimate of the last audit and whether the plan fell back (host outputs). */
 ftcg_status ftcg_plan_learned_report(ftcg_plan plan, double* audit_estimate, int* used_fallback);
 
+/* ------------------------------------------------------------------------
+ * Batched execution: n_items independent reconstructions (pings or
+ * sub-swaths) with their own sample counts and image sizes, float32,
+ * kernel/oversampling/weight mode shared. Spreading of all items runs as ONE
+ * persistent launch over a queue of (tile, record chunk) tasks ordered
+ * heaviest first; the FFT passes run batched per grid size; ftcg_batch_execute
+ * replays a captured hipGraph of the whole sequence.
+ * Concatenation: item i's samples follow those of items 0..i-1 in k_dev
+ * (m_i x 2 float64), fhat_dev (complex64) and alpha_dev (float64); its image
+ * (n_i x n_i complex64, row-major) follows the images of items 0..i-1.
+ * ------------------------------------------------------------------------ */
+typedef struct ftcg_batch_s* ftcg_batch;
+
+ftcg_status ftcg_batch_create(ftcg_batch* out, int n_items, const int64_t* n_host, int half_width,
+                              double oversampling, ftcg_wmode wmode, double weight_radius, void* hip_stream);
+ftcg_status ftcg_batch_destroy(ftcg_batch batch);
+
+/* tile edge (16/32/64/128, default 32), records per task (>= 64, default
+ * 4096), workgroups of the persistent launch (default 8 per CU), graph replay
+ * on/off (default on). The points must be set again afterwards. */
+ftcg_status ftcg_batch_set_tuning(ftcg_batch batch, int tile, int64_t chunk_records, int persistent_blocks,
+                                  int use_graph);
+
+/* FTCG_W_LEARNED batches: the network and audit of every item (see ftcg_plan_set_mlp). */
+ftcg_status ftcg_batch_set_mlp(ftcg_batch batch, ftcg_mlp mlp, double audit_threshold, int64_t audit_samples);
+
+/* m_host: n_items sample counts (host); k_dev: concatenated locations (device).
+ * Synchronises the stream (task tables are built on the host). */
+ftcg_status ftcg_batch_set_points(ftcg_batch batch, const int64_t* m_host, const double* k_dev);
+ftcg_status ftcg_batch_set_weights(ftcg_batch batch, const double* alpha_dev);   /* FTCG_W_USER */
+ftcg_status ftcg_batch_get_weights(ftcg_batch batch, double* alpha_dev);
+ftcg_status ftcg_batch_execute(ftcg_batch batch, const void* fhat_dev, void* images_dev);
+
+/* tasks of the persistent launch, tiles split over several tasks, spread
+ * records and tiles over all items (host outputs, any may be NULL) */
+ftcg_status ftcg_batch_info(ftcg_batch batch, int64_t* n_tasks, int64_t* n_split_tiles, int64_t* n_records,
+                            int64_t* n_tiles);
+ftcg_status ftcg_batch_enable_timing(ftcg_batch batch, int enable);
+
 #ifdef __cplusplus
 }
 #endif

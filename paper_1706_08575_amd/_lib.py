@@ -63,6 +63,18 @@ _SIGS = [
                                         C.c_int, C.POINTER(C.c_double)]),
     ("ftcg_plan_set_mlp", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]),
     ("ftcg_plan_learned_report", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    ("ftcg_batch_create", C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_int64), C.c_int, C.c_double,
+                                    C.c_int, C.c_double, C.c_void_p]),
+    ("ftcg_batch_destroy", C.c_int, [C.c_void_p]),
+    ("ftcg_batch_set_tuning", C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_int]),
+    ("ftcg_batch_set_mlp", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]),
+    ("ftcg_batch_set_points", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.c_void_p]),
+    ("ftcg_batch_set_weights", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("ftcg_batch_get_weights", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("ftcg_batch_execute", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ftcg_batch_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64)]),
+    ("ftcg_batch_enable_timing", C.c_int, [C.c_void_p, C.c_int]),
 ]
 
 EXPORTED = [s[0] for s in _SIGS]

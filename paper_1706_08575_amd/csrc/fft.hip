@@ -21,6 +21,7 @@
 // stores of neighbouring rows then meet in that XCD's L2 and leave it as whole
 // lines.
 #include "ftcg_internal.h"
+#include "batch_internal.h"
 
 namespace ftcg {
 
@@ -145,16 +146,14 @@ __device__ inline int xcd_row(int b, int rows) {
   return (b & 7) * (rows >> 3) + (b >> 3);
 }
 
+// one row: load (with the (-1)^(row+g) modulation when pre_sign), transform,
+// store the cropped outputs at out[q' * out_stride_q] times (-1)^q * fr * dq[q']
 template <class real>
-__global__ void k_fft_rows(const typename CxF<real>::t* __restrict__ in, int64_t in_row_stride,
-                           typename CxF<real>::t* __restrict__ out, int64_t out_stride_q, int64_t out_stride_row,
-                           int L, int log2L, int ncrop, int crop_off, int rows, int pre_sign,
-                           const double* __restrict__ dq, const double* __restrict__ drow) {
+__device__ inline void fft_row(const typename CxF<real>::t* __restrict__ src, typename CxF<real>::t* __restrict__ dst,
+                               int64_t out_stride_q, int L, int log2L, int ncrop, int crop_off, int row,
+                               int pre_sign, const double* __restrict__ dq, double fr,
+                               typename CxF<real>::t* buf) {
   using cx = typename CxF<real>::t;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx* buf = reinterpret_cast<cx*>(smem_raw);
-  const int row = xcd_row(blockIdx.x, rows);
-  const cx* src = in + (int64_t)row * in_row_stride;
   for (int g = threadIdx.x; g < L; g += blockDim.x) {
     cx v = src[g];
     if (pre_sign && ((row + g) & 1)) {
@@ -165,8 +164,6 @@ __global__ void k_fft_rows(const typename CxF<real>::t* __restrict__ in, int64_t
   }
   __syncthreads();
   lds_ifft<real>(buf, L, log2L);
-  const double fr = drow ? drow[row] : 1.0;
-  cx* dst = out + (int64_t)row * out_stride_row;
   for (int qp = threadIdx.x; qp < ncrop; qp += blockDim.x) {
     const int q = qp + crop_off;
     double f = ((q & 1) ? -1.0 : 1.0) * fr;
@@ -177,6 +174,73 @@ __global__ void k_fft_rows(const typename CxF<real>::t* __restrict__ in, int64_t
     v.y *= fs;
     dst[(int64_t)qp * out_stride_q] = v;
   }
+}
+
+template <class real>
+__global__ void k_fft_rows(const typename CxF<real>::t* __restrict__ in, int64_t in_row_stride,
+                           typename CxF<real>::t* __restrict__ out, int64_t out_stride_q, int64_t out_stride_row,
+                           int L, int log2L, int ncrop, int crop_off, int rows, int pre_sign,
+                           const double* __restrict__ dq, const double* __restrict__ drow) {
+  using cx = typename CxF<real>::t;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx* buf = reinterpret_cast<cx*>(smem_raw);
+  const int row = xcd_row(blockIdx.x, rows);
+  fft_row<real>(in + (int64_t)row * in_row_stride, out + (int64_t)row * out_stride_row, out_stride_q, L, log2L,
+                ncrop, crop_off, row, pre_sign, dq, drow ? drow[row] : 1.0, buf);
+}
+
+// batched passes over the items of one grid size G (all with n = G / sigma):
+// pass 1 maps row r to item list[r / G], grid row r % G; pass 2 maps row r to
+// item list[r / n], intermediate row r % n
+__global__ void k_fft_rows_batched(const BatchItem* __restrict__ items, const int* __restrict__ list,
+                                   const BatchArgs* __restrict__ args, int pass, int L, int log2L, int n,
+                                   int rows) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* buf = reinterpret_cast<float2*>(smem_raw);
+  const int r = xcd_row(blockIdx.x, rows);
+  const int per = pass == 1 ? L : n;
+  const BatchItem it = items[list[r / per]];
+  const int row = r % per;
+  const int crop_off = (L - n) / 2;
+  if (pass == 1) {
+    fft_row<float>(args->grid + it.grid_off + (int64_t)row * L, args->tmp + it.tmp_off + row, L, L, log2L, n,
+                   crop_off, row, 1, nullptr, 1.0, buf);
+  } else {
+    const double* d = args->deapod + it.deapod_off;
+    fft_row<float>(args->tmp + it.tmp_off + (int64_t)row * L, args->images + it.img_off + row, n, L, log2L, n,
+                   crop_off, row, 0, d, d[row], buf);
+  }
+}
+
+void batch_fft_prepare() {
+  static bool attr_done = false;
+  if (!attr_done) {
+    FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows_batched, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 160 * 1024));
+    attr_done = true;
+  }
+}
+
+void batch_fft(ftcg_batch_s* b) {
+  const int* lists = b->group_items.as<int>();
+  int64_t list_off = 0;
+  for (const auto& grp : b->fft_groups) {
+    const int64_t G = b->items[grp[0]].G;
+    const int n = b->items[grp[0]].n;
+    int log2L = 0;
+    while ((int64_t(1) << log2L) < G) ++log2L;
+    int nth = (int)(G / 16);
+    nth = nth < 64 ? 64 : (nth > 1024 ? 1024 : nth);
+    const size_t lds = (size_t)G * sizeof(float2);
+    for (int pass = 1; pass <= 2; ++pass) {
+      const int rows = (int)grp.size() * (pass == 1 ? (int)G : n);
+      hipLaunchKernelGGL(k_fft_rows_batched, dim3((unsigned)rows), dim3(nth), lds, b->stream,
+                         b->items_dev.as<BatchItem>(), lists + list_off, b->args_dev.as<BatchArgs>(), pass, (int)G,
+                         log2L, n, rows);
+    }
+    list_off += (int64_t)grp.size();
+  }
+  FTCG_HIP(hipGetLastError());
 }
 
 template <class real>

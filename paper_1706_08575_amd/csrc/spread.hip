@@ -191,7 +191,9 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
   for (int r = beg + tid; r < end; r += SPREAD_BLOCK) {
     const float a = alpha_s[r];
     const float2 v = fhat[recs[r].src];
-    mx = fmaxf(mx, fmaxf(fabsf(v.x * a), fabsf(v.y * a)));
+    const float cr = v.x * a, ci = v.y * a;
+    // fmaxf drops NaN operands: flag non-finite values explicitly
+    mx = (isfinite(cr) && isfinite(ci)) ? fmaxf(mx, fmaxf(fabsf(cr), fabsf(ci))) : __builtin_inff();
   }
   for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
   if (lane == 0) red[wave] = mx;

@@ -97,13 +97,17 @@ class Scene2D:
     amp: np.ndarray   # (S,) complex amplitudes
 
     def fourier(self, k: np.ndarray, chunk: int = 1 << 18) -> np.ndarray:
-        """Exact fhat(k) = sum_s a_s exp(-2 pi i k . x_s) for point scatterers."""
+        """Exact fhat(k) = sum_s a_s exp(-2 pi i k . x_s) for point scatterers
+        (float64; evaluated with multithreaded torch CPU ops, chunked)."""
+        import torch
         k = np.asarray(k, dtype=np.float64)
         out = np.empty(k.shape[0], dtype=np.complex128)
+        pos_t = torch.from_numpy(np.ascontiguousarray(self.pos.T))
+        amp = torch.from_numpy(np.ascontiguousarray(self.amp))
         for b in range(0, k.shape[0], chunk):
-            kk = k[b:b + chunk]
-            ph = kk @ self.pos.T                      # (c, S)
-            out[b:b + chunk] = np.exp(-2j * np.pi * ph) @ self.amp
+            ph = (-2.0 * math.pi) * (torch.from_numpy(k[b:b + chunk]) @ pos_t)     # (c, S)
+            e = torch.polar(torch.ones_like(ph), ph)
+            out[b:b + chunk] = (e @ amp).numpy()
         return out
 
 
