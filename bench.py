@@ -123,6 +123,137 @@ def cpu_baseline(name, k, f, n, R=8.0):
             "seconds_projected": total}, None, None
 
 
+MODEL_PATH = os.path.join(ROOT, "paper_1706_08575_amd", "models", "mlp_sas.bin")
+
+
+def bench_batched(steps: int, warmup: int, tune: bool = True) -> dict:
+    """Batched form: 64 SAS pings of uneven size (2^16..2^22 samples, images
+    256..2048 squared), plain weights, one persistent spreading launch per
+    step under a replayed hipGraph. A step = set_points of all items (weights,
+    binning, task tables) + one batched execute."""
+    import torch
+
+    from paper_1706_08575_amd import synth as S
+    from paper_1706_08575_amd.batch import Batch
+    from paper_1706_08575_amd import autotune
+
+    items = S.batch_items()
+    t0 = time.perf_counter()
+    data = [S.make_batch_item(it) for it in items]
+    t_gen = time.perf_counter() - t0
+    sizes = [it.n for it in items]
+    m = [it.m for it in items]
+    K = torch.from_numpy(np.concatenate([d[0] for d in data])).cuda()
+    F = torch.from_numpy(np.concatenate([d[1] for d in data])).to(torch.complex64).cuda()
+    B = Batch(sizes)
+    tuned = None
+    if tune:
+        tuned, _ = autotune.tune_batch(B, m, K, F, reps=1)
+    else:
+        B.set_tuning(tile=32, chunk=4096)
+        B.set_points(m, K)
+    out = B.execute(F)
+    for _ in range(warmup):
+        B.set_points(m, K)
+        out = B.execute(F, out)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(steps):
+        B.set_points(m, K)
+        out = B.execute(F, out)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - ta) / steps
+    # execute alone (geometry fixed): the graph replay
+    tb = time.perf_counter()
+    for _ in range(steps):
+        out = B.execute(F, out)
+    torch.cuda.synchronize()
+    sec_exec = (time.perf_counter() - tb) / steps
+    info = B.info()
+    # parity on the two smallest items against the oracle
+    import oracle as O
+    order = np.argsort(m)[:2]
+    errs = {}
+    for i in order:
+        k, f = data[i][0], data[i][1]
+        ref = O.ftcg_image(k, f, O.frame_weights(k, 8.0), sizes[i])
+        errs[int(i)] = O.rel_l2(B.image(out, int(i)).cpu().numpy(), ref)
+    B.close()
+    mt = int(sum(m))
+    return {"workload": "batch64_sas", "items": len(items), "samples": mt, "ms_per_step": sec * 1e3,
+            "images_per_s": len(items) / sec, "msamples_per_s": mt / sec / 1e6,
+            "execute_only_ms": sec_exec * 1e3, "execute_only_images_per_s": len(items) / sec_exec,
+            "tuned_tile_chunk": tuned, "tasks": info["tasks"], "split_tiles": info["split_tiles"],
+            "records": info["records"], "rel_l2_vs_oracle_smallest_items": errs,
+            "input_generation_s": t_gen}
+
+
+def bench_learned(steps: int, warmup: int) -> dict:
+    """Learned form: 512 pulses x 2048 samples (2^20), 1024x1024 image. The
+    network (trained by paper_1706_08575_amd.train on 10k rasters) predicts the
+    weights; the audit recomputes plain weights of 4096 samples and falls
+    back when the relative RMS weight error exceeds 1e-4. Reported: the audited
+    form (same accuracy as plain), the form without fallback (its weight and
+    image error against the plain form), and the plain form on the same input."""
+    import torch
+
+    from paper_1706_08575_amd import synth as S
+    from paper_1706_08575_amd.ftcg import Plan
+    from paper_1706_08575_amd.mlp import Mlp
+
+    k, f, _ = S.workload_learned_eval()
+    m = len(f)
+    K = torch.from_numpy(k).cuda()
+    F = torch.from_numpy(f).to(torch.complex64).cuda()
+    net = Mlp()
+    trained = os.path.exists(MODEL_PATH)
+    if trained:
+        with open(MODEL_PATH, "rb") as fh:
+            net.load(fh.read())
+    else:
+        net.set_params(S.mlp_init())
+        for i in range(500):
+            net.train_raster(torch.from_numpy(S.train_pattern(i)).cuda(), lr=3e-3 * (1 - i / 500) + 1e-5)
+
+    def timed(P):
+        out = torch.empty((1024, 1024), dtype=torch.complex64, device="cuda")
+        for _ in range(warmup):
+            P.set_points(K)
+            P.execute(F, out)
+        torch.cuda.synchronize()
+        P.enable_timing(True)
+        P.timing()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            P.set_points(K)
+            P.execute(F, out)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        st = {s_: ms / c for s_, (ms, c) in P.timing().items()}
+        P.enable_timing(False)
+        return sec, out, st
+
+    res = {"workload": "learned1024_sas", "samples": m, "model": "trained 10k rasters" if trained else
+           "fallback: 500 rasters trained in-run"}
+    with Plan(1024, dim=2, weights="plain") as P:
+        sec_p, img_p, st_p = timed(P)
+        a_p = P.get_weights()
+    res["plain"] = {"ms_per_step": sec_p * 1e3, "images_per_s": 1 / sec_p, "stage_ms": st_p}
+    for name, thr in (("audited_1e-4", 1e-4), ("no_fallback", float("inf"))):
+        with Plan(1024, dim=2, weights="learned") as P:
+            P.set_mlp(net, audit_threshold=thr, audit_samples=4096)
+            sec, img, st = timed(P)
+            rep = P.learned_report()
+            a = P.get_weights()
+        werr = torch.sqrt(torch.mean(((a - a_p) / a_p) ** 2)).item()
+        ierr = (torch.linalg.vector_norm(img - img_p) / torch.linalg.vector_norm(img_p)).item()
+        res[name] = {"ms_per_step": sec * 1e3, "images_per_s": 1 / sec, "stage_ms": st,
+                     "audit_estimate": rep["audit_estimate"], "used_fallback": rep["used_fallback"],
+                     "weights_rel_rms_vs_plain": werr, "image_rel_l2_vs_plain_gpu": ierr}
+    net.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +264,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--accum", default=None, choices=["fixed", "f64"])
     ap.add_argument("--copies", type=int, default=1)
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and learned forms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -224,6 +356,11 @@ def main():
             rel_w = float(np.max(np.abs(alpha - a_ref) / a_ref))
             cpu["weights_max_rel_err"] = rel_w
 
+    forms = None
+    if not args.no_forms:
+        forms = {"batched": bench_batched(steps=3, warmup=1),
+                 "learned": bench_learned(steps=max(3, min(args.steps, 10)), warmup=1)}
+
     res = {
         "metric": METRIC,
         "value": m / sec / 1e6,
@@ -248,6 +385,7 @@ def main():
         "hbm_steps": steps_hbm,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "forms": forms,
     }
     print(json.dumps(res))
 

@@ -1,0 +1,141 @@
+"""Autotuner for the spreading launch: tile edge (and, for batches, records
+per task) chosen by timing candidates on the caller's own data, remembered in
+a JSON cache keyed by the workload's shape.
+
+Keys: single plans by (precision, W, sigma, n, log2 of samples per grid cell
+rounded to half steps); batches by the same key over the batch's item mix.
+The cache lives at $FTCG_TUNING_CACHE (default: ~/.cache/ftcg_tuning.json);
+every measurement is the mean of the library's own event timings of the
+spreading step over `reps` executions after one warm-up.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import torch
+
+PLAN_TILES = (16, 32, 64, 128)
+BATCH_TILES = (16, 32, 64)
+BATCH_CHUNKS = (1024, 4096, 16384)
+
+
+def cache_path() -> str:
+    return os.environ.get("FTCG_TUNING_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ftcg_tuning.json"))
+
+
+def _load() -> dict:
+    try:
+        with open(cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache: dict) -> None:
+    p = cache_path()
+    try:
+        os.makedirs(os.path.dirname(p), exist_ok=True)
+        tmp = p + f".{os.getpid()}.tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(tmp, p)
+    except OSError:
+        pass   # a read-only home only loses the memory of the result
+
+
+def density_bucket(m: int, n: int, sigma: float) -> float:
+    cells = (sigma * n) ** 2
+    return round(2.0 * math.log2(max(m, 1) / cells)) / 2.0
+
+
+def plan_key(dtype: str, W: int, sigma: float, n: int, m: int) -> str:
+    return f"plan/{dtype}/W{W}/s{sigma:g}/n{n}/d{density_bucket(m, n, sigma):+.1f}"
+
+
+def batch_key(W: int, sigma: float, sizes, ms) -> str:
+    mix = sorted((int(n), density_bucket(int(m), int(n), sigma)) for n, m in zip(sizes, ms))
+    h = 0
+    for n, d in mix:
+        h = (h * 1000003 + hash((n, d))) & 0xFFFFFFFFFFFF
+    return f"batch/W{W}/s{sigma:g}/items{len(mix)}/{h:012x}"
+
+
+def _spread_ms(obj, run, reps: int) -> float:
+    run()
+    torch.cuda.synchronize()
+    obj.enable_timing(True)
+    obj.timing()
+    for _ in range(reps):
+        run()
+    t = obj.timing()
+    obj.enable_timing(False)
+    ms, cnt = t.get("spread", (0.0, 0))
+    return ms / max(cnt, 1)
+
+
+def tune_plan(plan, k: torch.Tensor, fhat: torch.Tensor, tiles=PLAN_TILES, reps: int = 3, use_cache: bool = True):
+    """Pick the tile edge of `plan` (a float32 Plan) for raster k, values fhat.
+    Leaves the plan tuned and with its points set. Returns (tile, {tile: ms})."""
+    dtype = "f32" if plan.cdtype == torch.complex64 else "f64"
+    key = plan_key(dtype, plan.W, plan.sigma, plan.n, int(k.shape[0]))
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        tile = int(cache[key]["tile"])
+        plan.set_tuning(tile)
+        plan.set_points(k)
+        return tile, cache[key].get("ms", {})
+    times = {}
+    accum = "fixed" if dtype == "f32" else "f64"
+    for t in tiles:
+        if t < 2 * plan.W:
+            continue
+        try:
+            plan.set_tuning(t, accum, 1)
+        except Exception:
+            continue
+        plan.set_points(k)
+        times[t] = _spread_ms(plan, lambda: plan.execute(fhat), reps)
+    tile = min(times, key=times.get)
+    plan.set_tuning(tile, accum, 1)
+    plan.set_points(k)
+    if use_cache:
+        cache[key] = {"tile": tile, "ms": {str(a): b for a, b in times.items()}, "when": time.time()}
+        _store(cache)
+    return tile, times
+
+
+def tune_batch(batch, m, k: torch.Tensor, fhat: torch.Tensor, tiles=BATCH_TILES, chunks=BATCH_CHUNKS,
+               reps: int = 3, use_cache: bool = True):
+    """Pick (tile, records per task) of a Batch by timing whole executions.
+    Leaves the batch tuned with its points set. Returns ((tile, chunk), {(tile, chunk): ms})."""
+    key = batch_key(6, 2.0, batch.sizes, m)
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        tile, chunk = int(cache[key]["tile"]), int(cache[key]["chunk"])
+        batch.set_tuning(tile=tile, chunk=chunk)
+        batch.set_points(m, k)
+        return (tile, chunk), {}
+    times = {}
+    out = None
+    for t in tiles:
+        for c in chunks:
+            batch.set_tuning(tile=t, chunk=c)
+            batch.set_points(m, k)
+            out = batch.execute(fhat, out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                out = batch.execute(fhat, out)
+            torch.cuda.synchronize()
+            times[(t, c)] = (time.perf_counter() - t0) / reps * 1e3
+    best = min(times, key=times.get)
+    batch.set_tuning(tile=best[0], chunk=best[1])
+    batch.set_points(m, k)
+    if use_cache:
+        cache[key] = {"tile": best[0], "chunk": best[1],
+                      "ms": {f"{a}x{b}": v for (a, b), v in times.items()}, "when": time.time()}
+        _store(cache)
+    return best, times

@@ -9,8 +9,9 @@
 // exactly separable).
 //
 // GPU layout: samples are counting-sorted into square neighbour bins of edge
-// h >= R/2 (k units), so the box of every sample lies in the (2s+1)^d bins
-// around its own (s = ceil(R/h) <= 2). Sorted arrays hold k and the
+// h (k units, about 16 samples per bin, R/16 <= h <= R/2), so the box of every
+// sample lies in the (2s+1)^d bins around its own (s = ceil(R/h)); the bins of
+// one row are contiguous in bin order, so each row is one candidate range. Sorted arrays hold k and the
 // per-sample sin(pi k), cos(pi k), so each pair needs
 // sin(pi (k_i - k_n)) = sin(pi k_i) cos(pi k_n) - cos(pi k_i) sin(pi k_n)
 // instead of a transcendental, and one float64 reciprocal.
@@ -89,26 +90,26 @@ __device__ inline double gram_row_sum(const WSample<DIM>* __restrict__ ss, const
   const int lo1 = DIM == 2 ? max(b[DIM - 1] - g.span, 0) : 0;
   const int hi1 = DIM == 2 ? min(b[DIM - 1] + g.span, g.nb[DIM - 1] - 1) : 0;
   for (int b0 = lo0; b0 <= hi0; ++b0) {
-    for (int b1 = lo1; b1 <= hi1; ++b1) {
-      const int bin = DIM == 2 ? b0 * g.nb[1] + b1 : b0;
-      const int beg = boff[bin], end = boff[bin + 1];
-      for (int i = beg; i < end; ++i) {
-        const WSample<DIM> o = ss[i];
-        double num = 1.0, den = 1.0;
-        bool inside = true;
-        for (int a = 0; a < DIM; ++a) {
-          const double d = o.k[a] - x[a];
-          inside = inside && (fabs(d) <= R);
-          if (d != 0.0) {
-            // sin(pi (k_i - k_n)) from the per-sample sin/cos
-            num *= o.sc[a][0] * cs[a] - o.sc[a][1] * sn[a];
-            den *= pi * d;
-          }
+    // the bins lo1..hi1 of one row are contiguous in bin order
+    const int first = DIM == 2 ? b0 * g.nb[1] + lo1 : b0;
+    const int last = DIM == 2 ? b0 * g.nb[1] + hi1 : b0;
+    const int beg = boff[first], end = boff[last + 1];
+    for (int i = beg; i < end; ++i) {
+      const WSample<DIM> o = ss[i];
+      double num = 1.0, den = 1.0;
+      bool inside = true;
+      for (int a = 0; a < DIM; ++a) {
+        const double d = o.k[a] - x[a];
+        inside = inside && (fabs(d) <= R);
+        if (d != 0.0) {
+          // sin(pi (k_i - k_n)) from the per-sample sin/cos
+          num *= o.sc[a][0] * cs[a] - o.sc[a][1] * sn[a];
+          den *= pi * d;
         }
-        if (inside) {
-          const double q = num * rcp64(den);
-          acc += q * q;
-        }
+      }
+      if (inside) {
+        const double q = num * rcp64(den);
+        acc += q * q;
       }
     }
   }
@@ -154,10 +155,17 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const double* __r
   out[t] = 1.0 / gram_row_sum<DIM>(ss, boff, g, x, sn, cs);
 }
 
+// Bin edge: about 16 samples per bin at the raster's mean density over its
+// bounding box, between R/16 and R/2 (span = ceil(R/h) <= 16 bins each side),
+// and at most 2048 bins per axis in 2D (4M in 1D).
 static WBinGeom wbin_geom(ftcg_plan p, const double* kmin, const double* kmax) {
   WBinGeom g{};
   g.R = p->R;
-  double h = p->R / 2.0;
+  double vol = 1.0;
+  for (int a = 0; a < p->dim; ++a) vol *= fmax(kmax[a] - kmin[a], 1e-9);
+  const double rho = (double)p->m / vol;
+  double h = p->dim == 2 ? sqrt(16.0 / rho) : 16.0 / rho;
+  h = fmin(fmax(h, p->R / 16.0), p->R / 2.0);
   const int max_bins = p->dim == 1 ? (1 << 22) : 2048;
   for (int a = 0; a < p->dim; ++a) {
     double ext = kmax[a] - kmin[a];
