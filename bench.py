@@ -41,6 +41,10 @@ WORKLOADS = {
     "sas4096_precision": "2D polar-format SAS, 2048 pulses x 4096 samples (8 388 608), 4096x4096 image, "
                          "FP32 spread/FFT, FP64 weights and deapodization",
     "jitter1d_f64": "1D jittered raster, 512 samples, 256 pixels, FP64",
+    "batch64_sas": "64 SAS pings, 2^16..2^22 samples each, images 256..2048 squared, plain weights, "
+                   "one persistent spreading launch per step, hipGraph replay",
+    "learned1024_sas": "2D SAS 512 x 2048 samples (2^20), 1024x1024 image, learned weights (trained MLP) "
+                       "with audit against plain weights",
 }
 
 
@@ -279,6 +283,21 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload in ("batch64_sas", "learned1024_sas"):
+        if args.workload == "batch64_sas":
+            r = bench_batched(steps=args.steps, warmup=args.warmup, tune=args.tile == 0)
+            value, ms, dt = r["msamples_per_s"], r["ms_per_step"], "f32 spread/FFT, f64 weights/deapod"
+        else:
+            r = bench_learned(steps=args.steps, warmup=args.warmup)
+            ms = r["no_fallback"]["ms_per_step"]
+            value, dt = r["samples"] / ms / 1e3, "f32 spread/FFT, fp16/fp32 MLP, f64 audit/deapod"
+        print(json.dumps({"metric": METRIC, "value": value, "unit": "Msamples/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dt,
+                          "data": "synthetic", "config": {"workload": args.workload,
+                                                           "description": WORKLOADS[args.workload]},
+                          "result": r, "roofline": None, "cpu_baseline": None}))
+        return
     k, f, n, dtype = make_inputs(args.workload)
     m, dim = len(f), k.shape[1]
     cdt = torch.complex64 if dtype == "f32" else torch.complex128

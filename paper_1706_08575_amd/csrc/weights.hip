@@ -77,14 +77,51 @@ __device__ inline double rcp64(double x) {
   return fma(r, e, r);
 }
 
+// T_in^2 of one candidate i for sample n = (x, sn, cs), 0 outside the box.
+// Branch free: a coordinate difference of exactly 0 gives the factor
+// sinc(0) = 1 through selects, so every operand of the candidate is loaded
+// up front and the loop body has no data-dependent control flow.
+template <int DIM>
+__device__ inline double pair_term(const WSample<DIM>& o, const double* x, const double* sn, const double* cs,
+                                   double R) {
+  const double pi = 3.141592653589793238462643383279502884;
+  double num = 1.0, den = 1.0;
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const double d = o.k[a] - x[a];
+    inside = inside && (fabs(d) <= R);
+    // sin(pi (k_i - k_n)) from the per-sample sin/cos
+    const double sd = o.sc[a][0] * cs[a] - o.sc[a][1] * sn[a];
+    const bool z = d == 0.0;
+    num *= z ? 1.0 : sd;
+    den *= z ? 1.0 : pi * d;
+  }
+  const double q = num * rcp64(den);
+  return inside ? q * q : 0.0;
+}
+
+// sum over a contiguous candidate range, next candidate loaded ahead
+template <int DIM>
+__device__ inline double range_sum(const WSample<DIM>* __restrict__ ss, int beg, int end, const double* x,
+                                   const double* sn, const double* cs, double R) {
+  double acc = 0.0;
+  if (beg >= end) return acc;
+  WSample<DIM> nxt = ss[beg];
+  for (int i = beg; i < end; ++i) {
+    const WSample<DIM> cur = nxt;
+    if (i + 1 < end) nxt = ss[i + 1];
+    acc += pair_term<DIM>(cur, x, sn, cs, R);
+  }
+  return acc;
+}
+
 // sum over the box neighbours i of sample (x, sin, cos) of T_in^2
 template <int DIM>
 __device__ inline double gram_row_sum(const WSample<DIM>* __restrict__ ss, const int32_t* __restrict__ boff,
                                       const WBinGeom& g, const double* x, const double* sn, const double* cs) {
   int b[DIM];
   wbin_of<DIM>(x, g, b);
-  const double pi = 3.141592653589793238462643383279502884;
-  const double R = g.R;
   double acc = 0.0;
   const int lo0 = max(b[0] - g.span, 0), hi0 = min(b[0] + g.span, g.nb[0] - 1);
   const int lo1 = DIM == 2 ? max(b[DIM - 1] - g.span, 0) : 0;
@@ -93,25 +130,7 @@ __device__ inline double gram_row_sum(const WSample<DIM>* __restrict__ ss, const
     // the bins lo1..hi1 of one row are contiguous in bin order
     const int first = DIM == 2 ? b0 * g.nb[1] + lo1 : b0;
     const int last = DIM == 2 ? b0 * g.nb[1] + hi1 : b0;
-    const int beg = boff[first], end = boff[last + 1];
-    for (int i = beg; i < end; ++i) {
-      const WSample<DIM> o = ss[i];
-      double num = 1.0, den = 1.0;
-      bool inside = true;
-      for (int a = 0; a < DIM; ++a) {
-        const double d = o.k[a] - x[a];
-        inside = inside && (fabs(d) <= R);
-        if (d != 0.0) {
-          // sin(pi (k_i - k_n)) from the per-sample sin/cos
-          num *= o.sc[a][0] * cs[a] - o.sc[a][1] * sn[a];
-          den *= pi * d;
-        }
-      }
-      if (inside) {
-        const double q = num * rcp64(den);
-        acc += q * q;
-      }
-    }
+    acc += range_sum<DIM>(ss, boff[first], boff[last + 1], x, sn, cs, g.R);
   }
   return acc;
 }
@@ -135,7 +154,9 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights(const WSample<DIM>* 
   alpha[sidx[t]] = 1.0 / gram_row_sum<DIM>(ss, boff, g, x, sn, cs);
 }
 
-// the same sum for listed samples (caller indices), for audits and checks
+// the same sum for listed samples (caller indices), for audits and checks:
+// one wavefront per sample, lanes splitting its candidate ranges (the lists
+// are short, so one thread per sample would leave the GPU idle)
 template <int DIM>
 __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const double* __restrict__ k,
                                                                const double* __restrict__ sc_orig,
@@ -143,16 +164,30 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const double* __r
                                                                const WSample<DIM>* __restrict__ ss,
                                                                const int32_t* __restrict__ boff, WBinGeom g,
                                                                double* __restrict__ out) {
-  int64_t t = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
-  if (t >= n) return;
-  const int64_t j = idx[t];
+  const int64_t w = ((int64_t)blockIdx.x * WB_BLOCK + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (w >= n) return;   // whole wavefront
+  const int64_t j = idx[w];
   double x[DIM], sn[DIM], cs[DIM];
   for (int a = 0; a < DIM; ++a) {
     x[a] = k[j * DIM + a];
     sn[a] = sc_orig[j * 2 * DIM + 2 * a];
     cs[a] = sc_orig[j * 2 * DIM + 2 * a + 1];
   }
-  out[t] = 1.0 / gram_row_sum<DIM>(ss, boff, g, x, sn, cs);
+  int b[DIM];
+  wbin_of<DIM>(x, g, b);
+  const int lo0 = max(b[0] - g.span, 0), hi0 = min(b[0] + g.span, g.nb[0] - 1);
+  const int lo1 = DIM == 2 ? max(b[DIM - 1] - g.span, 0) : 0;
+  const int hi1 = DIM == 2 ? min(b[DIM - 1] + g.span, g.nb[DIM - 1] - 1) : 0;
+  double acc = 0.0;
+  for (int b0 = lo0; b0 <= hi0; ++b0) {
+    const int first = DIM == 2 ? b0 * g.nb[1] + lo1 : b0;
+    const int last = DIM == 2 ? b0 * g.nb[1] + hi1 : b0;
+    const int beg = boff[first], end = boff[last + 1];
+    for (int i = beg + lane; i < end; i += 64) acc += pair_term<DIM>(ss[i], x, sn, cs, g.R);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) out[w] = 1.0 / acc;
 }
 
 // Bin edge: about 16 samples per bin at the raster's mean density over its
@@ -233,7 +268,7 @@ void run_plain_weights(ftcg_plan p) {
 
 void plain_weights_at(ftcg_plan p, const double* k, const int32_t* idx, int64_t n, double* out) {
   if (n <= 0) return;
-  const unsigned nb = (unsigned)((n + WB_BLOCK - 1) / WB_BLOCK);
+  const unsigned nb = (unsigned)((n * 64 + WB_BLOCK - 1) / WB_BLOCK);
   const int32_t* off = p->wb_off.as<int32_t>();
   if (p->dim == 1)
     hipLaunchKernelGGL(k_frame_weights_at<1>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, k, p->sc_orig.as<double>(),
