@@ -74,7 +74,11 @@ __device__ inline void knn_visit_bin(const WSample<2>* __restrict__ ss, const in
 }
 
 // keys (float32 d2 bits << 32 | caller index) of the 16 nearest box
-// neighbours of sample (x, jself); empty slots stay ~0
+// neighbours of sample (x, jself); empty slots stay ~0. Bins are visited in
+// rings of growing Chebyshev distance around the sample's bin; after ring r
+// every unvisited sample lies at least `reach` (the distance from x to the
+// edge of the (2r+1)^2 block, sides clipped at the bin grid's edge excluded)
+// away, so the search stops once the 16th key is strictly nearer than that.
 __device__ inline void knn_search(const WSample<2>* __restrict__ ss, const int32_t* __restrict__ sidx,
                                   const int32_t* __restrict__ boff, const WBinGeom& g, const double* x, int jself,
                                   unsigned long long (&key)[KNN]) {
@@ -82,33 +86,35 @@ __device__ inline void knn_search(const WSample<2>* __restrict__ ss, const int32
   for (int q = 0; q < KNN; ++q) key[q] = ~0ull;
   const int b0 = wbin_clamp(x[0], g.kmin[0], g.h, g.nb[0]);
   const int b1 = wbin_clamp(x[1], g.kmin[1], g.h, g.nb[1]);
-  // the 3 x 3 block of bins around the sample first
-  const int lo0 = max(b0 - 1, 0), hi0 = min(b0 + 1, g.nb[0] - 1);
-  const int lo1 = max(b1 - 1, 0), hi1 = min(b1 + 1, g.nb[1] - 1);
-  for (int c0 = lo0; c0 <= hi0; ++c0)
-    for (int c1 = lo1; c1 <= hi1; ++c1) {
-      const int bin = c0 * g.nb[1] + c1;
-      knn_visit_bin(ss, sidx, boff[bin], boff[bin + 1], x, jself, g.R, key);
+  for (int r = 0; r <= g.span; ++r) {
+    const int lo0 = max(b0 - r, 0), hi0 = min(b0 + r, g.nb[0] - 1);
+    const int lo1 = max(b1 - r, 0), hi1 = min(b1 + r, g.nb[1] - 1);
+    for (int c0 = lo0; c0 <= hi0; ++c0) {
+      const bool edge_row = (c0 == b0 - r) || (c0 == b0 + r);
+      if (edge_row) {
+        // the whole row of the ring: one contiguous range of the bin order
+        knn_visit_bin(ss, sidx, boff[c0 * g.nb[1] + lo1], boff[c0 * g.nb[1] + hi1 + 1], x, jself, g.R, key);
+      } else {
+        if (b1 - r >= 0) {
+          const int bin = c0 * g.nb[1] + b1 - r;
+          knn_visit_bin(ss, sidx, boff[bin], boff[bin + 1], x, jself, g.R, key);
+        }
+        if (r > 0 && b1 + r < g.nb[1]) {
+          const int bin = c0 * g.nb[1] + b1 + r;
+          knn_visit_bin(ss, sidx, boff[bin], boff[bin + 1], x, jself, g.R, key);
+        }
+      }
     }
-  if (g.span <= 1) return;
-  // everything outside the block lies at least `reach` away from the sample
-  // (a side clipped at the edge of the bin grid has nothing beyond it)
-  double reach = 1e300;
-  if (lo0 > 0) reach = fmin(reach, x[0] - (g.kmin[0] + lo0 * g.h));
-  if (hi0 < g.nb[0] - 1) reach = fmin(reach, g.kmin[0] + (hi0 + 1) * g.h - x[0]);
-  if (lo1 > 0) reach = fmin(reach, x[1] - (g.kmin[1] + lo1 * g.h));
-  if (hi1 < g.nb[1] - 1) reach = fmin(reach, g.kmin[1] + (hi1 + 1) * g.h - x[1]);
-  const float d16 = __uint_as_float((unsigned)(key[KNN - 1] >> 32));
-  // strictly closer than anything outside (with a margin for float rounding)
-  if (key[KNN - 1] != ~0ull && (double)d16 < reach * reach * (1.0 - 1e-6)) return;
-  const int olo0 = max(b0 - g.span, 0), ohi0 = min(b0 + g.span, g.nb[0] - 1);
-  const int olo1 = max(b1 - g.span, 0), ohi1 = min(b1 + g.span, g.nb[1] - 1);
-  for (int c0 = olo0; c0 <= ohi0; ++c0)
-    for (int c1 = olo1; c1 <= ohi1; ++c1) {
-      if (c0 >= lo0 && c0 <= hi0 && c1 >= lo1 && c1 <= hi1) continue;
-      const int bin = c0 * g.nb[1] + c1;
-      knn_visit_bin(ss, sidx, boff[bin], boff[bin + 1], x, jself, g.R, key);
-    }
+    if (key[KNN - 1] == ~0ull) continue;
+    double reach = 1e300;
+    if (lo0 > 0) reach = fmin(reach, x[0] - (g.kmin[0] + lo0 * g.h));
+    if (hi0 < g.nb[0] - 1) reach = fmin(reach, g.kmin[0] + (hi0 + 1) * g.h - x[0]);
+    if (lo1 > 0) reach = fmin(reach, x[1] - (g.kmin[1] + lo1 * g.h));
+    if (hi1 < g.nb[1] - 1) reach = fmin(reach, g.kmin[1] + (hi1 + 1) * g.h - x[1]);
+    const float d16 = __uint_as_float((unsigned)(key[KNN - 1] >> 32));
+    // strictly closer than anything outside (with a margin for float rounding)
+    if ((double)d16 < reach * reach * (1.0 - 1e-6)) return;
+  }
 }
 
 // features (float32) and the analytic estimate of one sample from its keys

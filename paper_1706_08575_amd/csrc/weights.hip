@@ -190,18 +190,23 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const double* __r
   if (lane == 0) out[w] = 1.0 / acc;
 }
 
-// Bin edge: about 16 samples per bin at the raster's mean density over its
-// bounding box, between R/16 and R/2 (span = ceil(R/h) <= 16 bins each side),
-// and at most 2048 bins per axis in 2D (4M in 1D).
+// Bin edge h = R / span with span in [2, 16] chosen for about BIN_TARGET
+// samples per bin at the raster's mean density over its bounding box, so the
+// 2 span + 1 bins of a row range end at the box of radius R (finer bins waste
+// fewer out-of-box candidates); at most 4096 bins per axis in 2D (4M in 1D).
+constexpr double BIN_TARGET = 6.0;
 static WBinGeom wbin_geom(ftcg_plan p, const double* kmin, const double* kmax) {
   WBinGeom g{};
   g.R = p->R;
   double vol = 1.0;
   for (int a = 0; a < p->dim; ++a) vol *= fmax(kmax[a] - kmin[a], 1e-9);
   const double rho = (double)p->m / vol;
-  double h = p->dim == 2 ? sqrt(16.0 / rho) : 16.0 / rho;
-  h = fmin(fmax(h, p->R / 16.0), p->R / 2.0);
-  const int max_bins = p->dim == 1 ? (1 << 22) : 2048;
+  const double h_target = p->dim == 2 ? sqrt(BIN_TARGET / rho) : BIN_TARGET / rho;
+  // h = R / span exactly, so the 2 span + 1 bins of a row range end on the box
+  int span = (int)lround(p->R / h_target);
+  span = span < 2 ? 2 : (span > 16 ? 16 : span);
+  double h = p->R / span;
+  const int max_bins = p->dim == 1 ? (1 << 22) : 4096;
   for (int a = 0; a < p->dim; ++a) {
     double ext = kmax[a] - kmin[a];
     if (ext / h + 1.0 > (double)max_bins) h = ext / (double)(max_bins - 1);
