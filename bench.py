@@ -76,6 +76,10 @@ def step_bytes(step, m, nrec, n, G, dim, dtype):
     if step == "bin":
         # read k, write one record (2 offsets, cell, index) + weight per record
         return m * 8 * dim + nrec * (16 + rs)
+    if step == "weight_bin":
+        # read k twice (count, scatter), bin id written and read, write the
+        # bin-ordered sample (k, sin, cos), its index and the caller-order sin/cos
+        return m * (2 * 8 * dim + 4 + 4 + 24 * dim + 4 + 16 * dim)
     return None
 
 
@@ -340,8 +344,10 @@ def main():
         del x, y
 
     stage_ms = {s: ms / c for s, (ms, c) in stages.items()}
-    # roofline of the dominant kernel
-    dom = max(stage_ms, key=stage_ms.get)
+    # roofline of the dominant kernel (among the steps with a work model)
+    modelled = [s_ for s_ in stage_ms if s_ == "weights" or
+                step_bytes(s_, m, info["n_records"], n, G, dim, dtype) is not None]
+    dom = max(modelled, key=stage_ms.get)
     roof = None
     if dom == "weights":
         pairs = count_box_pairs(k, 8.0, sample=None if m <= 200_000 else 20000)
@@ -359,7 +365,7 @@ def main():
                 "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": b}
     # every HBM-bound step, for reference
     steps_hbm = {}
-    for s in ("spread", "fft1", "fft2_deapod", "bin"):
+    for s in ("spread", "fft1", "fft2_deapod", "bin", "weight_bin"):
         if s in stage_ms:
             b = step_bytes(s, m, info["n_records"], n, G, dim, dtype)
             steps_hbm[s] = {"ms": stage_ms[s], "GB/s": b / (stage_ms[s] * 1e-3) / 1e9,

@@ -8,17 +8,19 @@
 // (-1)^g H[g] e^{2 pi i g q / G}: a plain unnormalised inverse DFT with sign
 // flips on load and store.
 //
-// One workgroup transforms one row of length G held in LDS (Stockham
-// autosort, one radix-2 stage when log2 G is odd, then radix-4 stages; every
-// stage reads its butterfly inputs into registers, synchronises, and writes
-// in place). Only the n cropped outputs are stored, transposed, so the next
-// pass again reads contiguous rows:
+// One workgroup transforms RB consecutive rows of length G, one after another
+// in LDS (Stockham autosort, one radix-2 stage when log2 G is odd, then
+// radix-4 stages; every stage reads its butterfly inputs into registers,
+// synchronises, and writes in place). Only the n cropped outputs are kept,
+// in registers, and stored transposed once all RB rows are done, so that each
+// store is an RB-element (32-byte) segment and the next pass again reads
+// contiguous rows:
 //   pass 1: rows g0 of H (G x G)  -> T1[q1'][g0]  (n x G)
 //   pass 2: rows q1' of T1         -> image[p0][p1] (n x n), times
 //           1/Phi(x_p0/sigma) / Phi(x_p1/sigma) formed in float64.
-// Rows are assigned so that each of the 8 XCDs (workgroups are dealt to XCDs
-// round-robin) works on a contiguous block of rows; the transposed 8-byte
-// stores of neighbouring rows then meet in that XCD's L2 and leave it as whole
+// Row blocks are assigned so that each of the 8 XCDs (workgroups are dealt to
+// XCDs round-robin) works on a contiguous range of rows; the 32-byte segments
+// of neighbouring blocks then meet in that XCD's L2 and leave it as whole
 // lines.
 #include "ftcg_internal.h"
 #include "batch_internal.h"
@@ -67,13 +69,13 @@ __device__ inline cx cmul_i(cx a) {  // a * (+i)
   return r;
 }
 
-constexpr int FFT_MAXB = 8;  // butterflies per thread per stage (radix-2 stage worst case)
-
-// in-place inverse (positive exponent) FFT of buf[0..L) in LDS, L = 2^log2L
-template <class real>
-__device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L) {
+// in-place inverse (positive exponent) FFT of buf[0..L) in LDS, L = 2^log2L,
+// by threads tid = 0..nth-1, nth >= L / PPT (PPT points per thread per
+// stage); every thread of the workgroup calls it with the same L
+template <class real, int PPT>
+__device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L, int tid, int nth) {
   using cx = typename CxF<real>::t;
-  const int tid = threadIdx.x, nth = blockDim.x;
+  constexpr int FFT_MAXB = PPT / 2;  // radix-2 butterflies per thread
   int Ns = 1;
   if (log2L & 1) {
     // radix 2, Ns = 1: no twiddles
@@ -140,86 +142,206 @@ __device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L) {
   }
 }
 
-__device__ inline int xcd_row(int b, int rows) {
-  // rows % 8 == 0: XCD x (= b % 8) gets rows x*rows/8 .. (x+1)*rows/8 - 1 in order
-  if (rows & 7) return b;
-  return (b & 7) * (rows >> 3) + (b >> 3);
-}
-
-// one row: load (with the (-1)^(row+g) modulation when pre_sign), transform,
-// store the cropped outputs at out[q' * out_stride_q] times (-1)^q * fr * dq[q']
-template <class real>
-__device__ inline void fft_row(const typename CxF<real>::t* __restrict__ src, typename CxF<real>::t* __restrict__ dst,
-                               int64_t out_stride_q, int L, int log2L, int ncrop, int crop_off, int row,
-                               int pre_sign, const double* __restrict__ dq, double fr,
-                               typename CxF<real>::t* buf) {
+// RB consecutive rows r0..r0+RB-1 through one workgroup, RC of them at a
+// time (RC = 1 or RB): the threads form RC slots of blockDim.x / RC threads,
+// slot s owning LDS buf[s L ..) and rows s, s + RC, ... Each row is read from
+// HBM into registers one step ahead (while the previous one is transformed),
+// multiplied by (-1)^(row+g) when pre_sign, transformed in LDS, and its
+// cropped outputs times (-1)^q * drow[row] * dq[q'] are kept in registers.
+// All RB rows of an output q' then leave as one RB-element segment at
+// dst[q' out_stride_q + r0]: through LDS staged q'-major when RC = RB, or
+// straight from registers when RC = 1 (one thread then holds all RB rows).
+template <class real, int RB, int RC, int MAXQ, int PPT>
+__device__ inline void fft_rows_block(const typename CxF<real>::t* __restrict__ src, int64_t in_row_stride,
+                                      typename CxF<real>::t* __restrict__ dst, int64_t out_stride_q, int L,
+                                      int log2L, int ncrop, int crop_off, int r0, int pre_sign,
+                                      const double* __restrict__ dq, const double* __restrict__ drow,
+                                      typename CxF<real>::t* buf) {
+  static_assert(RC == 1 || RC == RB, "rows per workgroup run one at a time or all at once");
   using cx = typename CxF<real>::t;
-  for (int g = threadIdx.x; g < L; g += blockDim.x) {
-    cx v = src[g];
-    if (pre_sign && ((row + g) & 1)) {
-      v.x = -v.x;
-      v.y = -v.y;
-    }
-    buf[g] = v;
+  constexpr int NJ = RB / RC;
+  const int nts = blockDim.x / RC;
+  const int slot = RC == 1 ? 0 : (int)threadIdx.x / nts;
+  const int t = (int)threadIdx.x - slot * nts;
+  cx* sbuf = buf + (size_t)slot * L;
+  cx outv[NJ][MAXQ];
+  cx nxt[PPT];
+  {
+    const cx* s0 = src + (int64_t)slot * in_row_stride;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u)
+      if (t + u * nts < L) nxt[u] = s0[t + u * nts];
   }
-  __syncthreads();
-  lds_ifft<real>(buf, L, log2L);
-  for (int qp = threadIdx.x; qp < ncrop; qp += blockDim.x) {
-    const int q = qp + crop_off;
-    double f = ((q & 1) ? -1.0 : 1.0) * fr;
-    if (dq) f *= dq[qp];
-    const real fs = (real)f;
-    cx v = buf[q];
-    v.x *= fs;
-    v.y *= fs;
-    dst[(int64_t)qp * out_stride_q] = v;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int rr = j * RC + slot;
+    const int row = r0 + rr;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int g = t + u * nts;
+      if (g < L) {
+        cx v = nxt[u];
+        if (pre_sign && ((row + g) & 1)) {
+          v.x = -v.x;
+          v.y = -v.y;
+        }
+        sbuf[g] = v;
+      }
+    }
+    if (j + 1 < NJ) {
+      const cx* s1 = src + (int64_t)(rr + RC) * in_row_stride;
+#pragma unroll
+      for (int u = 0; u < PPT; ++u)
+        if (t + u * nts < L) nxt[u] = s1[t + u * nts];
+    }
+    __syncthreads();
+    lds_ifft<real, PPT>(sbuf, L, log2L, t, nts);
+    const double fr = drow ? drow[row] : 1.0;
+#pragma unroll
+    for (int kq = 0; kq < MAXQ; ++kq) {
+      const int qp = t + kq * nts;
+      if (qp < ncrop) {
+        const int q = qp + crop_off;
+        double f = (q & 1) ? -fr : fr;
+        if (dq) f *= dq[qp];
+        const real fs = (real)f;
+        cx v = sbuf[q];
+        v.x *= fs;
+        v.y *= fs;
+        outv[j][kq] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (RC == 1) {
+#pragma unroll
+    for (int kq = 0; kq < MAXQ; ++kq) {
+      const int qp = t + kq * nts;
+      if (qp < ncrop) {
+        cx* d = dst + (int64_t)qp * out_stride_q;
+#pragma unroll
+        for (int j = 0; j < RB; ++j) d[j] = outv[j][kq];
+      }
+    }
+  } else {
+    // RB * ncrop <= RB * L: the staging fits in the RC = RB row buffers
+#pragma unroll
+    for (int kq = 0; kq < MAXQ; ++kq) {
+      const int qp = t + kq * nts;
+      if (qp < ncrop) buf[qp * RB + slot] = outv[0][kq];
+    }
+    __syncthreads();
+    const int tot = RB * ncrop;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x)
+      dst[(int64_t)(e / RB) * out_stride_q + (e % RB)] = buf[e];
   }
 }
 
-template <class real>
+template <class real, int RB, int RC, int MAXQ, int PPT>
 __global__ void k_fft_rows(const typename CxF<real>::t* __restrict__ in, int64_t in_row_stride,
-                           typename CxF<real>::t* __restrict__ out, int64_t out_stride_q, int64_t out_stride_row,
-                           int L, int log2L, int ncrop, int crop_off, int rows, int pre_sign,
-                           const double* __restrict__ dq, const double* __restrict__ drow) {
+                           typename CxF<real>::t* __restrict__ out, int64_t out_stride_q, int L, int log2L,
+                           int ncrop, int crop_off, int rows, int pre_sign, const double* __restrict__ dq,
+                           const double* __restrict__ drow) {
   using cx = typename CxF<real>::t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx* buf = reinterpret_cast<cx*>(smem_raw);
-  const int row = xcd_row(blockIdx.x, rows);
-  fft_row<real>(in + (int64_t)row * in_row_stride, out + (int64_t)row * out_stride_row, out_stride_q, L, log2L,
-                ncrop, crop_off, row, pre_sign, dq, drow ? drow[row] : 1.0, buf);
+  const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * RB;
+  fft_rows_block<real, RB, RC, MAXQ, PPT>(in + (int64_t)r0 * in_row_stride, in_row_stride, out + r0, out_stride_q,
+                                          L, log2L, ncrop, crop_off, r0, pre_sign, dq, drow, buf);
 }
 
-// batched passes over the items of one grid size G (all with n = G / sigma):
-// pass 1 maps row r to item list[r / G], grid row r % G; pass 2 maps row r to
-// item list[r / n], intermediate row r % n
+// batched passes over the items of one grid size G (all with n = G / sigma),
+// RB rows per workgroup: pass 1 maps row block b to item list[b*RB / G], grid
+// rows b*RB % G ..; pass 2 maps it to item list[b*RB / n], intermediate rows
+template <int RB, int RC, int MAXQ, int PPT>
 __global__ void k_fft_rows_batched(const BatchItem* __restrict__ items, const int* __restrict__ list,
-                                   const BatchArgs* __restrict__ args, int pass, int L, int log2L, int n,
-                                   int rows) {
+                                   const BatchArgs* __restrict__ args, int pass, int L, int log2L, int n) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float2* buf = reinterpret_cast<float2*>(smem_raw);
-  const int r = xcd_row(blockIdx.x, rows);
+  const int r = (int)xcd_block(blockIdx.x, gridDim.x) * RB;
   const int per = pass == 1 ? L : n;
   const BatchItem it = items[list[r / per]];
   const int row = r % per;
   const int crop_off = (L - n) / 2;
   if (pass == 1) {
-    fft_row<float>(args->grid + it.grid_off + (int64_t)row * L, args->tmp + it.tmp_off + row, L, L, log2L, n,
-                   crop_off, row, 1, nullptr, 1.0, buf);
+    fft_rows_block<float, RB, RC, MAXQ, PPT>(args->grid + it.grid_off + (int64_t)row * L, L,
+                                             args->tmp + it.tmp_off + row, L, L, log2L, n, crop_off, row, 1, nullptr,
+                                             nullptr, buf);
   } else {
     const double* d = args->deapod + it.deapod_off;
-    fft_row<float>(args->tmp + it.tmp_off + (int64_t)row * L, args->images + it.img_off + row, n, L, log2L, n,
-                   crop_off, row, 0, d, d[row], buf);
+    fft_rows_block<float, RB, RC, MAXQ, PPT>(args->tmp + it.tmp_off + (int64_t)row * L, L,
+                                             args->images + it.img_off + row, n, L, log2L, n, crop_off, row, 0, d,
+                                             d, buf);
   }
 }
 
-void batch_fft_prepare() {
-  static bool attr_done = false;
-  if (!attr_done) {
-    FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows_batched, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 160 * 1024));
-    attr_done = true;
+// launch shape of a row pass: PPT points per thread (8 while L / 8 threads fit
+// a workgroup, else 16); nts = max(64, L / PPT) threads per row; MAXQ >= the
+// cropped outputs per thread; RB rows per workgroup, as many as make each
+// transposed store a 32-byte segment (4 float2 or 2 double2; 2 float2 at
+// PPT 16, where 4 rows of outputs no longer fit in registers), or 1 when the
+// row count is not a multiple of that; RC = RB rows at a time when RB row
+// slots fit one workgroup (RB * nts <= 1024 threads, RB * L elements in 64 KiB
+// of LDS, so two workgroups share a CU), else RC = 1
+struct FftShape {
+  int nts, ppt, maxq, rb, rc;
+};
+
+static FftShape fft_shape(int64_t L, int64_t ncrop, int64_t rows, int elem_bytes) {
+  FftShape f;
+  f.ppt = L <= 8192 ? 8 : 16;
+  f.nts = (int)std::max<int64_t>(64, L / f.ppt);
+  const int64_t q = (ncrop + f.nts - 1) / f.nts;
+  f.maxq = q <= 4 && f.ppt == 8 ? 4 : 8;
+  f.rb = (elem_bytes == 8 && f.ppt == 8) ? 4 : 2;
+  if (rows % f.rb != 0) f.rb = 1;
+  f.rc = (f.rb * f.nts <= 1024 && f.rb * L * elem_bytes <= 64 * 1024) ? f.rb : 1;
+  return f;
+}
+
+// calls fn.template operator()<RB, RC, MAXQ, PPT>() for the shape f
+template <class Fn>
+static void dispatch_shape(const FftShape& f, Fn&& fn) {
+  const int mq = f.maxq == 4 ? 0 : (f.ppt == 8 ? 1 : 2);
+  const int code = f.rb * 100 + f.rc * 10 + mq;
+  switch (code) {
+    case 440: fn.template operator()<4, 4, 4, 8>(); break;
+    case 441: fn.template operator()<4, 4, 8, 8>(); break;
+    case 410: fn.template operator()<4, 1, 4, 8>(); break;
+    case 411: fn.template operator()<4, 1, 8, 8>(); break;
+    case 220: fn.template operator()<2, 2, 4, 8>(); break;
+    case 221: fn.template operator()<2, 2, 8, 8>(); break;
+    case 210: fn.template operator()<2, 1, 4, 8>(); break;
+    case 211: fn.template operator()<2, 1, 8, 8>(); break;
+    case 212: fn.template operator()<2, 1, 8, 16>(); break;
+    case 110: fn.template operator()<1, 1, 4, 8>(); break;
+    case 111: fn.template operator()<1, 1, 8, 8>(); break;
+    case 112: fn.template operator()<1, 1, 8, 16>(); break;
+    default: throw StatusError{FTCG_EUNSUPPORTED};
   }
 }
+
+struct BatchedLaunch {
+  ftcg_batch_s* b;
+  const int* list;
+  int pass, rows;
+  FftShape f;
+  int L, log2L, n;
+  template <int RB, int RC, int MAXQ, int PPT>
+  void operator()() const {
+    static bool attr_done = false;
+    if (!attr_done) {
+      FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows_batched<RB, RC, MAXQ, PPT>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+      attr_done = true;
+    }
+    const size_t lds = (size_t)RC * L * sizeof(float2);
+    hipLaunchKernelGGL((k_fft_rows_batched<RB, RC, MAXQ, PPT>), dim3((unsigned)(rows / RB)), dim3(f.nts * RC), lds,
+                       b->stream, b->items_dev.as<BatchItem>(), list, b->args_dev.as<BatchArgs>(), pass, L, log2L, n);
+  }
+};
+
+void batch_fft_prepare() {}
 
 void batch_fft(ftcg_batch_s* b) {
   const int* lists = b->group_items.as<int>();
@@ -229,14 +351,13 @@ void batch_fft(ftcg_batch_s* b) {
     const int n = b->items[grp[0]].n;
     int log2L = 0;
     while ((int64_t(1) << log2L) < G) ++log2L;
-    int nth = (int)(G / 16);
-    nth = nth < 64 ? 64 : (nth > 1024 ? 1024 : nth);
-    const size_t lds = (size_t)G * sizeof(float2);
+    const int* list = lists + list_off;
     for (int pass = 1; pass <= 2; ++pass) {
-      const int rows = (int)grp.size() * (pass == 1 ? (int)G : n);
-      hipLaunchKernelGGL(k_fft_rows_batched, dim3((unsigned)rows), dim3(nth), lds, b->stream,
-                         b->items_dev.as<BatchItem>(), lists + list_off, b->args_dev.as<BatchArgs>(), pass, (int)G,
-                         log2L, n, rows);
+      const int per = pass == 1 ? (int)G : n;
+      // row blocks must not straddle items: RB divides the rows of one item
+      const FftShape f = fft_shape(G, n, per, (int)sizeof(float2));
+      const int rows = (int)grp.size() * per;
+      dispatch_shape(f, BatchedLaunch{b, list, pass, rows, f, (int)G, log2L, n});
     }
     list_off += (int64_t)grp.size();
   }
@@ -244,27 +365,43 @@ void batch_fft(ftcg_batch_s* b) {
 }
 
 template <class real>
-static void launch_rows(ftcg_plan p, const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q,
-                        int64_t out_stride_row, int rows, int pre_sign, const double* dq, const double* drow) {
-  using cx = typename CxF<real>::t;
-  const int L = (int)p->G;
-  int log2L = 0;
-  while ((1 << log2L) < L) ++log2L;
-  int nth = L / 16;
-  nth = nth < 64 ? 64 : (nth > 1024 ? 1024 : nth);
-  const size_t lds = (size_t)L * sizeof(cx);
-  static bool attr_done = false;
-  if (!attr_done) {
-    FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows<real>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 160 * 1024));
-    attr_done = true;
+struct RowsLaunch {
+  ftcg_plan p;
+  const void* in;
+  int64_t in_row_stride;
+  void* out;
+  int64_t out_stride_q;
+  int rows, pre_sign;
+  FftShape f;
+  const double* dq;
+  const double* drow;
+  template <int RB, int RC, int MAXQ, int PPT>
+  void operator()() const {
+    using cx = typename CxF<real>::t;
+    const int L = (int)p->G;
+    int log2L = 0;
+    while ((1 << log2L) < L) ++log2L;
+    const size_t lds = (size_t)RC * L * sizeof(cx);
+    static bool attr_done = false;
+    if (!attr_done) {
+      FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows<real, RB, RC, MAXQ, PPT>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+      attr_done = true;
+    }
+    const int ncrop = (int)p->n;
+    const int crop_off = (int)((p->G - p->n) / 2);
+    hipLaunchKernelGGL((k_fft_rows<real, RB, RC, MAXQ, PPT>), dim3((unsigned)(rows / RB)), dim3(f.nts * RC), lds,
+                       p->stream, static_cast<const cx*>(in), in_row_stride, static_cast<cx*>(out), out_stride_q, L,
+                       log2L, ncrop, crop_off, rows, pre_sign, dq, drow);
+    FTCG_HIP(hipGetLastError());
   }
-  const int ncrop = (int)p->n;
-  const int crop_off = (int)((p->G - p->n) / 2);
-  hipLaunchKernelGGL(k_fft_rows<real>, dim3((unsigned)rows), dim3(nth), lds, p->stream,
-                     static_cast<const cx*>(in), in_row_stride, static_cast<cx*>(out), out_stride_q, out_stride_row,
-                     L, log2L, ncrop, crop_off, rows, pre_sign, dq, drow);
-  FTCG_HIP(hipGetLastError());
+};
+
+template <class real>
+static void launch_rows(ftcg_plan p, const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q,
+                        int rows, int pre_sign, const double* dq, const double* drow) {
+  const FftShape f = fft_shape(p->G, p->n, rows, (int)sizeof(typename CxF<real>::t));
+  dispatch_shape(f, RowsLaunch<real>{p, in, in_row_stride, out, out_stride_q, rows, pre_sign, f, dq, drow});
 }
 
 template <class real>
@@ -273,15 +410,15 @@ static void grid_to_image_t(ftcg_plan p, const void* grid, void* image) {
   const int64_t G = p->G, n = p->n;
   if (p->dim == 1) {
     timing_begin(p, STEP_FFT2);
-    launch_rows<real>(p, grid, G, image, 1, 0, 1, 1, d, nullptr);
+    launch_rows<real>(p, grid, G, image, 1, 1, 1, d, nullptr);
     timing_end(p, STEP_FFT2);
     return;
   }
   timing_begin(p, STEP_FFT1);
-  launch_rows<real>(p, grid, G, p->fft_tmp.p, G, 1, (int)G, 1, nullptr, nullptr);
+  launch_rows<real>(p, grid, G, p->fft_tmp.p, G, (int)G, 1, nullptr, nullptr);
   timing_end(p, STEP_FFT1);
   timing_begin(p, STEP_FFT2);
-  launch_rows<real>(p, p->fft_tmp.p, G, image, n, 1, (int)n, 0, d, d);
+  launch_rows<real>(p, p->fft_tmp.p, G, image, n, (int)n, 0, d, d);
   timing_end(p, STEP_FFT2);
 }
 

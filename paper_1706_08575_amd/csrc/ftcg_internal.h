@@ -146,6 +146,23 @@ __device__ inline int agg_atomic_add(int32_t* counters, int key, bool valid) {
   return slot;
 }
 
+// XCD-aware block order. Workgroups are dealt to the 8 XCDs round-robin
+// (block b to XCD b % 8), and each XCD has its own L2. This returns the
+// logical block for hardware block b so that XCD x works through chunks x,
+// x + 8, x + 16, ... of C consecutive logical blocks, C = nblocks / 64 clamped
+// to [1, 64]: blocks that share data run on one L2, and every XCD still sees
+// every part of the range, which keeps the XCDs evenly loaded when the cost of
+// a block varies along it. Blocks past the last whole group of 8 chunks keep
+// the plain order.
+__device__ inline int64_t xcd_block(int64_t b, int64_t nblocks) {
+  int64_t C = nblocks >> 6;
+  C = C < 1 ? 1 : (C > 64 ? 64 : C);
+  const int64_t full = nblocks / (8 * C) * (8 * C);
+  if (b >= full) return b;
+  const int64_t x = b & 7, i = b >> 3;
+  return ((i / C) * 8 + x) * C + (i % C);
+}
+
 }  // namespace ftcg
 
 struct ftcg_plan_s {

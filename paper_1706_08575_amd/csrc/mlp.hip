@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_knn_features(const WSample<2>* __restri
                                                       const double* __restrict__ sc_orig, int64_t m,
                                                       float* __restrict__ feat, double* __restrict__ base,
                                                       const double* __restrict__ alpha, float* __restrict__ target) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t t = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (t >= m) return;
   const int j = sidx[t];
   const double x[2] = {ss[t].k[0], ss[t].k[1]};
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(256) void k_learned_weights(const WSample<2>* __res
   __shared__ _Float16 xs[256 * NF];
   __shared__ float ys[256];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int64_t t = (int64_t)blockIdx.x * 256 + tid;
+  const int64_t t = xcd_block(blockIdx.x, gridDim.x) * 256 + tid;
   double b = 1.0;
   int j = -1;
   if (t < m) {

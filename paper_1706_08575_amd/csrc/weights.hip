@@ -142,7 +142,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights(const WSample<DIM>* 
                                                             const int32_t* __restrict__ sidx,
                                                             const int32_t* __restrict__ boff, int64_t m, WBinGeom g,
                                                             double* __restrict__ alpha) {
-  int64_t t = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
+  const int64_t t = xcd_block(blockIdx.x, gridDim.x) * WB_BLOCK + threadIdx.x;
   if (t >= m) return;
   double x[DIM], sn[DIM], cs[DIM];
   const WSample<DIM> me = ss[t];
