@@ -83,6 +83,18 @@ static ftcg_status guarded(F&& f) {
   }
 }
 
+namespace ftcg {
+int64_t plan_nrec(ftcg_plan p) {
+  if (p->nrec < 0) {
+    FTCG_HIP(hipMemcpyAsync(p->host_flags, p->tile_off.as<int32_t>() + p->ntiles, sizeof(int32_t),
+                            hipMemcpyDeviceToHost, p->stream));
+    FTCG_HIP(hipStreamSynchronize(p->stream));
+    p->nrec = *reinterpret_cast<const int32_t*>(p->host_flags);
+  }
+  return p->nrec;
+}
+}  // namespace ftcg
+
 extern "C" {
 
 const char* ftcg_status_string(ftcg_status s) {
@@ -235,11 +247,8 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     p->tile_off.ensure(sizeof(int32_t) * (p->ntiles + 1));
     p->scan_tmp.ensure(scan_tmp_bytes(p->ntiles));
     bin_points_k(p, k_dev);
-    FTCG_HIP(hipMemcpyAsync(p->host_flags, p->tile_off.as<int32_t>() + p->ntiles, sizeof(int32_t),
-                            hipMemcpyDeviceToHost, p->stream));
-    FTCG_HIP(hipStreamSynchronize(p->stream));
     timing_end(p, STEP_BIN);
-    p->nrec = *reinterpret_cast<const int32_t*>(p->host_flags);
+    p->nrec = -1;  // on the device (tile_off[ntiles]); read only when asked for
     p->have_points = true;
   });
 }
@@ -314,10 +323,21 @@ ftcg_status ftcg_plan_learned_report(ftcg_plan p, double* audit_estimate, int* u
 
 ftcg_status ftcg_plan_info(ftcg_plan p, int64_t* grid_size, int64_t* n_records, int64_t* n_tiles, int* tile) {
   if (!p) return FTCG_EINVAL;
-  if (grid_size) *grid_size = p->G;
-  if (n_records) *n_records = p->nrec;
-  if (n_tiles) *n_tiles = p->ntiles;
-  if (tile) *tile = p->tile;
+  return guarded([&] {
+    if (grid_size) *grid_size = p->G;
+    if (n_records) *n_records = p->have_points && !p->weights_only ? plan_nrec(p) : 0;
+    if (n_tiles) *n_tiles = p->ntiles;
+    if (tile) *tile = p->tile;
+  });
+}
+
+ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan p, int samples_per_group, int lanes_per_group) {
+  if (!p) return FTCG_EINVAL;
+  const int w = samples_per_group, l = lanes_per_group;
+  if (!(w == 0 || w == 1 || w == 2 || w == 4)) return FTCG_EINVAL;
+  if (!(l == 0 || l == 1 || l == 2 || l == 4 || l == 8)) return FTCG_EINVAL;
+  p->w_samples = w;
+  p->w_lanes = l;
   return FTCG_OK;
 }
 

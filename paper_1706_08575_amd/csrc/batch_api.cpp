@@ -352,7 +352,7 @@ ftcg_status ftcg_batch_info(ftcg_batch_s* b, int64_t* n_tasks, int64_t* n_split_
                             int64_t* n_tiles) {
   if (!b) return FTCG_EINVAL;
   int64_t r = 0;
-  for (ftcg_plan p : b->plans) r += p->nrec;
+  for (ftcg_plan p : b->plans) r += plan_nrec(p);
   if (n_tasks) *n_tasks = b->ntasks;
   if (n_split_tiles) *n_split_tiles = b->nsplit;
   if (n_records) *n_records = r;

@@ -26,39 +26,59 @@ __device__ inline unsigned long long ordered_bits(double x) {
 }
 
 // flags layout (unsigned long long): [0] bad flag, [1..2] min per axis, [3..4] max per axis
+// grid-stride pass over the points; each workgroup reduces its bounds with
+// wavefront shuffles and LDS and issues one atomic per bound, and the grid is
+// kept small (CHECK_BLOCKS) so that few atomics meet on the four words
+constexpr int CHECK_BLOCKS = 256;
 __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __restrict__ k, int64_t m, int dim,
                                                             unsigned long long* __restrict__ flags) {
-  __shared__ unsigned long long smin[2][BIN_BLOCK];
-  __shared__ unsigned long long smax[2][BIN_BLOCK];
+  __shared__ unsigned long long sred[4][BIN_BLOCK / 64];
+  __shared__ int sbad;
+  if (threadIdx.x == 0) sbad = 0;
   unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
   bool bad = false;
   for (int64_t j = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; j < m; j += (int64_t)gridDim.x * BIN_BLOCK) {
     for (int a = 0; a < dim; ++a) {
-      double x = k[j * dim + a];
-      if (!isfinite(x)) { bad = true; continue; }
-      unsigned long long o = ordered_bits(x);
+      const double x = k[j * dim + a];
+      if (!isfinite(x)) {
+        bad = true;
+        continue;
+      }
+      const unsigned long long o = ordered_bits(x);
       lo[a] = o < lo[a] ? o : lo[a];
       hi[a] = o > hi[a] ? o : hi[a];
     }
   }
-  if (bad) atomicOr(&flags[0], 1ull);
-  for (int a = 0; a < 2; ++a) { smin[a][threadIdx.x] = lo[a]; smax[a][threadIdx.x] = hi[a]; }
-  __syncthreads();
-  for (int off = BIN_BLOCK / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off) {
-      for (int a = 0; a < 2; ++a) {
-        unsigned long long x = smin[a][threadIdx.x + off];
-        if (x < smin[a][threadIdx.x]) smin[a][threadIdx.x] = x;
-        unsigned long long y = smax[a][threadIdx.x + off];
-        if (y > smax[a][threadIdx.x]) smax[a][threadIdx.x] = y;
-      }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const unsigned long long x = __shfl_xor(lo[a], off, 64);
+      const unsigned long long y = __shfl_xor(hi[a], off, 64);
+      lo[a] = x < lo[a] ? x : lo[a];
+      hi[a] = y > hi[a] ? y : hi[a];
     }
-    __syncthreads();
   }
+  __syncthreads();
+  if (bad) sbad = 1;
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sred[0][w] = lo[0];
+    sred[1][w] = lo[1];
+    sred[2][w] = hi[0];
+    sred[3][w] = hi[1];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    if (sbad) atomicOr(&flags[0], 1ull);
     for (int a = 0; a < dim; ++a) {
-      atomicMin(&flags[1 + a], smin[a][0]);
-      atomicMax(&flags[3 + a], smax[a][0]);
+      unsigned long long l = sred[a][0], h = sred[2 + a][0];
+      for (int v = 1; v < BIN_BLOCK / 64; ++v) {
+        l = sred[a][v] < l ? sred[a][v] : l;
+        h = sred[2 + a][v] > h ? sred[2 + a][v] : h;
+      }
+      atomicMin(&flags[1 + a], l);
+      atomicMax(&flags[3 + a], h);
     }
   }
 }
@@ -74,8 +94,8 @@ __global__ void k_init_flags(unsigned long long* flags) {
 void launch_check_points(ftcg_plan p, const double* k, int64_t m, double* flags_d) {
   auto* f = reinterpret_cast<unsigned long long*>(flags_d);
   hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, p->stream, f);
-  int64_t nb = (m + BIN_BLOCK - 1) / BIN_BLOCK;
-  if (nb > 4096) nb = 4096;
+  int64_t nb = (m + 8 * BIN_BLOCK - 1) / (8 * BIN_BLOCK);  // 8 points per thread at least
+  if (nb > CHECK_BLOCKS) nb = CHECK_BLOCKS;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_check_points, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream, k, m, p->dim, f);
   FTCG_HIP(hipGetLastError());
@@ -213,8 +233,7 @@ static void bin_points_t(ftcg_plan p, const double* k) {
     hipLaunchKernelGGL(k_tile_count<1>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
   else
     hipLaunchKernelGGL(k_tile_count<2>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
-  exclusive_scan_i32(cnt, off, p->ntiles, p->scan_tmp.as<int32_t>(), s);
-  FTCG_HIP(hipMemcpyAsync(cnt, off, sizeof(int32_t) * p->ntiles, hipMemcpyDeviceToDevice, s));
+  exclusive_scan_i32(cnt, off, p->ntiles, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
   const double* alpha = p->have_weights ? p->alpha.as<double>() : nullptr;
   if (p->dim == 1)
     hipLaunchKernelGGL((k_tile_scatter<1, real>), dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, alpha, cnt,
@@ -233,14 +252,15 @@ void bin_points_k(ftcg_plan p, const double* k) {
 }
 
 void refill_alpha(ftcg_plan p) {
-  const unsigned nb = (unsigned)((p->nrec + BIN_BLOCK - 1) / BIN_BLOCK);
-  if (p->nrec == 0) return;
+  const int64_t nrec = plan_nrec(p);
+  const unsigned nb = (unsigned)((nrec + BIN_BLOCK - 1) / BIN_BLOCK);
+  if (nrec == 0) return;
   if (p->dtype == FTCG_F64)
     hipLaunchKernelGGL(k_refill_alpha<double>, dim3(nb), dim3(BIN_BLOCK), 0, p->stream,
-                       p->recs.as<Rec<double>>(), p->nrec, p->alpha.as<double>(), p->alpha_s.as<double>());
+                       p->recs.as<Rec<double>>(), nrec, p->alpha.as<double>(), p->alpha_s.as<double>());
   else
     hipLaunchKernelGGL(k_refill_alpha<float>, dim3(nb), dim3(BIN_BLOCK), 0, p->stream,
-                       p->recs.as<Rec<float>>(), p->nrec, p->alpha.as<double>(), p->alpha_s.as<float>());
+                       p->recs.as<Rec<float>>(), nrec, p->alpha.as<double>(), p->alpha_s.as<float>());
   FTCG_HIP(hipGetLastError());
 }
 

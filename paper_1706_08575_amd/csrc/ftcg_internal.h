@@ -178,6 +178,8 @@ struct ftcg_plan_s {
   int64_t G = 0;       // grid edge
   double beta = 0.0;   // kernel exp(-beta s^2)
   int tile_req = 0;    // requested tile edge (0 = automatic)
+  int w_samples = 0;   // frame-weight kernel: samples per lane group (0 = automatic)
+  int w_lanes = 0;     // frame-weight kernel: lanes per sample group (0 = automatic)
   int lds_copies = 1;
   int accum = 0;       // ftcg::Accum for float32 plans (float64 plans always use ACCUM_F64)
 
@@ -241,7 +243,9 @@ void fill_ones(double* a, int64_t m, hipStream_t s);
 void spread(ftcg_plan p, const void* fhat, void* grid);
 void grid_to_image(ftcg_plan p, const void* grid, void* image);
 void compute_deapod(ftcg_plan p);
-void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s);
+int64_t plan_nrec(ftcg_plan p);  // records of the last set_points (one host sync)
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s,
+                        int32_t* cursor = nullptr);
 size_t scan_tmp_bytes(int64_t n);
 
 void timing_begin(ftcg_plan p, int step);

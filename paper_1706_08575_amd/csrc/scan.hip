@@ -1,8 +1,13 @@
 // Exclusive prefix sum of int32 counts (tile and bin offsets of the counting sorts).
 //
-// Three launches: per-block sums, a single-block scan of the block sums,
-// then a per-block scan that adds its block offset. Each block covers
+// Up to SCAN_SINGLE_MAX entries: one launch of one 1024-thread workgroup that
+// walks the array in chunks of 16384, carrying the running total. Beyond
+// that, three launches: per-block sums, a single-block scan of the block
+// sums, then a per-block scan that adds its block offset, each block covering
 // SCAN_BLOCK * SCAN_ITEMS consecutive entries. out[n] receives the total.
+// When `cursor` is given, out[0..n) is written there too (it may be `in`
+// itself: every entry is read by the thread that later overwrites it), which
+// gives the counting sorts their scatter cursors without another copy.
 #include "ftcg_internal.h"
 
 namespace ftcg {
@@ -64,9 +69,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_sums(int32_t* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __restrict__ in, int64_t n,
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* in, int64_t n,
                                                            const int32_t* __restrict__ sums,
-                                                           int32_t* __restrict__ out) {
+                                                           int32_t* __restrict__ out, int32_t* cursor) {
   __shared__ int32_t lds[SCAN_BLOCK];
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int32_t v[SCAN_ITEMS];
@@ -80,10 +85,86 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __rest
   int32_t run = block_exclusive_scan(s, lds, &tot) + sums[blockIdx.x];
   for (int i = 0; i < SCAN_ITEMS; ++i) {
     int64_t idx = base + i;
-    if (idx < n) out[idx] = run;
+    if (idx < n) {
+      out[idx] = run;
+      if (cursor) cursor[idx] = run;
+    }
     run += v[i];
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BLOCK - 1) out[n] = run;
+}
+
+constexpr int SS_BLOCK = 1024;
+constexpr int SS_ITEMS = 16;
+constexpr int64_t SCAN_SINGLE_MAX = 8 * SS_BLOCK * SS_ITEMS;
+
+__device__ inline int32_t wave_inclusive_scan(int32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(v, off, 64);
+    if (lane >= off) v += y;
+  }
+  return v;
+}
+
+// one chunk of SS_BLOCK * SS_ITEMS entries passes through LDS so that global
+// loads and stores are coalesced while each thread scans SS_ITEMS consecutive
+// entries; entry e sits at LDS word e + e / 16 (conflict-free at stride 16)
+__device__ inline int ss_pad(int e) { return e + (e >> 4); }
+
+__global__ __launch_bounds__(SS_BLOCK) void k_scan_single(const int32_t* in, int64_t n, int32_t* __restrict__ out,
+                                                          int32_t* cursor) {
+  constexpr int CH = SS_BLOCK * SS_ITEMS;
+  __shared__ int32_t buf[CH + CH / 16];
+  __shared__ int32_t wsum[SS_BLOCK / 64];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  int32_t carry = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += CH) {
+    const int64_t len = n - c0 < CH ? n - c0 : CH;
+#pragma unroll
+    for (int i = 0; i < SS_ITEMS; ++i) {
+      const int e = i * SS_BLOCK + t;
+      buf[ss_pad(e)] = e < len ? in[c0 + e] : 0;
+    }
+    __syncthreads();
+    int32_t v[SS_ITEMS];
+    int32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SS_ITEMS; ++i) {
+      v[i] = buf[ss_pad(t * SS_ITEMS + i)];
+      s += v[i];
+    }
+    const int32_t incl = wave_inclusive_scan(s);
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int32_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int j = 0; j < SS_BLOCK / 64; ++j) {
+      const int32_t x = wsum[j];
+      wpre += j < w ? x : 0;
+      tot += x;
+    }
+    int32_t run = carry + wpre + incl - s;
+#pragma unroll
+    for (int i = 0; i < SS_ITEMS; ++i) {
+      buf[ss_pad(t * SS_ITEMS + i)] = run;
+      run += v[i];
+    }
+    carry += tot;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SS_ITEMS; ++i) {
+      const int e = i * SS_BLOCK + t;
+      if (e < len) {
+        const int32_t x = buf[ss_pad(e)];
+        out[c0 + e] = x;
+        if (cursor) cursor[c0 + e] = x;
+      }
+    }
+    __syncthreads();  // buf and wsum are rewritten by the next chunk
+  }
+  if (t == 0) out[n] = carry;
 }
 
 size_t scan_tmp_bytes(int64_t n) {
@@ -91,13 +172,18 @@ size_t scan_tmp_bytes(int64_t n) {
   return (size_t)(nb + 1) * sizeof(int32_t);
 }
 
-void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s) {
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s, int32_t* cursor) {
+  if (n <= SCAN_SINGLE_MAX) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SS_BLOCK), 0, s, in, n, out, cursor);
+    FTCG_HIP(hipGetLastError());
+    return;
+  }
   int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   if (nb < 1) nb = 1;
   if (nb > SCAN_MAX_BLOCKS) throw StatusError{FTCG_EUNSUPPORTED};
   hipLaunchKernelGGL(k_scan_block_sums, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, tmp);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, (int)nb);
-  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, tmp, out);
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, tmp, out, cursor);
   FTCG_HIP(hipGetLastError());
 }
 

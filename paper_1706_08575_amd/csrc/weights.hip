@@ -9,9 +9,10 @@
 // exactly separable).
 //
 // GPU layout: samples are counting-sorted into square neighbour bins of edge
-// h (k units, about 16 samples per bin, R/16 <= h <= R/2), so the box of every
-// sample lies in the (2s+1)^d bins around its own (s = ceil(R/h)); the bins of
-// one row are contiguous in bin order, so each row is one candidate range. Sorted arrays hold k and the
+// h = R / s (k units; s in [2, 16] for about 6 samples per bin), so the box
+// of every sample lies in the (2s+1)^d bins around its own; the bins of one
+// row are contiguous in bin order, so each row is one candidate range. Sorted
+// arrays hold k and the
 // per-sample sin(pi k), cos(pi k), so each pair needs
 // sin(pi (k_i - k_n)) = sin(pi k_i) cos(pi k_n) - cos(pi k_i) sin(pi k_n)
 // instead of a transcendental, and one float64 reciprocal.
@@ -101,57 +102,106 @@ __device__ inline double pair_term(const WSample<DIM>& o, const double* x, const
   return inside ? q * q : 0.0;
 }
 
-// sum over a contiguous candidate range, next candidate loaded ahead
-template <int DIM>
-__device__ inline double range_sum(const WSample<DIM>* __restrict__ ss, int beg, int end, const double* x,
-                                   const double* sn, const double* cs, double R) {
-  double acc = 0.0;
-  if (beg >= end) return acc;
-  WSample<DIM> nxt = ss[beg];
-  for (int i = beg; i < end; ++i) {
-    const WSample<DIM> cur = nxt;
-    if (i + 1 < end) nxt = ss[i + 1];
-    acc += pair_term<DIM>(cur, x, sn, cs, R);
+// Adds to acc[u] the T_in^2 of every candidate i in [beg, end) for the NT
+// samples u (all of them when !MASKED, else those with bit u of `mask`).
+// Candidates alternate between two register sets, each loaded while the
+// other one's pair terms are formed.
+template <int DIM, int NT, bool MASKED>
+__device__ inline void range_sum(const WSample<DIM>* __restrict__ ss, int beg, int end, const double (&x)[NT][DIM],
+                                 const double (&sn)[NT][DIM], const double (&cs)[NT][DIM], double R,
+                                 double (&acc)[NT], unsigned mask) {
+  if (beg >= end) return;
+  WSample<DIM> a = ss[beg];
+  for (int i = beg; i < end; i += 2) {
+    const bool has_b = i + 1 < end;
+    const WSample<DIM> b = ss[has_b ? i + 1 : i];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const double t = pair_term<DIM>(a, x[u], sn[u], cs[u], R);
+      acc[u] += (!MASKED || ((mask >> u) & 1u)) ? t : 0.0;
+    }
+    a = ss[i + 2 < end ? i + 2 : i];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const double t = pair_term<DIM>(b, x[u], sn[u], cs[u], R);
+      acc[u] += (has_b && (!MASKED || ((mask >> u) & 1u))) ? t : 0.0;
+    }
   }
-  return acc;
 }
 
-// sum over the box neighbours i of sample (x, sin, cos) of T_in^2
-template <int DIM>
-__device__ inline double gram_row_sum(const WSample<DIM>* __restrict__ ss, const int32_t* __restrict__ boff,
-                                      const WBinGeom& g, const double* x, const double* sn, const double* cs) {
-  int b[DIM];
-  wbin_of<DIM>(x, g, b);
-  double acc = 0.0;
-  const int lo0 = max(b[0] - g.span, 0), hi0 = min(b[0] + g.span, g.nb[0] - 1);
-  const int lo1 = DIM == 2 ? max(b[DIM - 1] - g.span, 0) : 0;
-  const int hi1 = DIM == 2 ? min(b[DIM - 1] + g.span, g.nb[DIM - 1] - 1) : 0;
-  for (int b0 = lo0; b0 <= hi0; ++b0) {
-    // the bins lo1..hi1 of one row are contiguous in bin order
-    const int first = DIM == 2 ? b0 * g.nb[1] + lo1 : b0;
-    const int last = DIM == 2 ? b0 * g.nb[1] + hi1 : b0;
-    acc += range_sum<DIM>(ss, boff[first], boff[last + 1], x, sn, cs, g.R);
-  }
-  return acc;
-}
-
-// one thread per sorted sample; neighbours of nearby sorted samples are the
-// same bins, so a wavefront walks the same candidate lists together
-template <int DIM>
+// WT consecutive sorted samples per group of S lanes. Sorted samples are
+// bin-major, so the WT samples nearly always share a bin row; then one pass
+// over the union of their candidate ranges (rows b0 - s .. b0 + s, bins
+// min b1 - s .. max b1 + s, which the box test trims back to each sample's own
+// box) feeds every loaded candidate to all WT pair terms. Samples in
+// different bin rows (the ends of rows) take their own ranges one after
+// another. The S lanes of a group split the rows round-robin and add their
+// partial sums by shuffles; S > 1 is for small rasters, where one lane per
+// group would leave most of the GPU idle.
+template <int DIM, int WT, int S>
 __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights(const WSample<DIM>* __restrict__ ss,
                                                             const int32_t* __restrict__ sidx,
                                                             const int32_t* __restrict__ boff, int64_t m, WBinGeom g,
                                                             double* __restrict__ alpha) {
-  const int64_t t = xcd_block(blockIdx.x, gridDim.x) * WB_BLOCK + threadIdx.x;
-  if (t >= m) return;
-  double x[DIM], sn[DIM], cs[DIM];
-  const WSample<DIM> me = ss[t];
-  for (int a = 0; a < DIM; ++a) {
-    x[a] = me.k[a];
-    sn[a] = me.sc[a][0];
-    cs[a] = me.sc[a][1];
+  const int64_t gt = xcd_block(blockIdx.x, gridDim.x) * WB_BLOCK + threadIdx.x;
+  const int ls = (int)(gt % S);
+  const int64_t t0 = (gt / S) * WT;
+  if (t0 >= m) return;   // whole groups leave together (S divides the block)
+  double x[WT][DIM], sn[WT][DIM], cs[WT][DIM], acc[WT];
+  int b[WT][DIM];
+#pragma unroll
+  for (int u = 0; u < WT; ++u) {
+    const int64_t t = t0 + u < m ? t0 + u : m - 1;   // a last odd sample repeats (and is not stored twice)
+    const WSample<DIM> me = ss[t];
+    for (int a = 0; a < DIM; ++a) {
+      x[u][a] = me.k[a];
+      sn[u][a] = me.sc[a][0];
+      cs[u][a] = me.sc[a][1];
+    }
+    wbin_of<DIM>(x[u], g, b[u]);
+    acc[u] = 0.0;
   }
-  alpha[sidx[t]] = 1.0 / gram_row_sum<DIM>(ss, boff, g, x, sn, cs);
+  bool same_row = true;
+  int bmin = b[0][DIM - 1], bmax = b[0][DIM - 1];
+#pragma unroll
+  for (int u = 1; u < WT; ++u) {
+    same_row = same_row && (DIM == 1 || b[u][0] == b[0][0]);
+    bmin = min(bmin, b[u][DIM - 1]);
+    bmax = max(bmax, b[u][DIM - 1]);
+  }
+  if (DIM == 1) {
+    // one candidate range, split into S contiguous pieces
+    const int lo = max(bmin - g.span, 0), hi = min(bmax + g.span, g.nb[0] - 1);
+    const int beg = boff[lo], end = boff[hi + 1];
+    const int len = (end - beg + S - 1) / S;
+    const int pb = beg + ls * len, pe = min(pb + len, end);
+    range_sum<DIM, WT, false>(ss, pb, pe, x, sn, cs, g.R, acc, 0u);
+  } else if (same_row) {
+    const int lo0 = max(b[0][0] - g.span, 0), hi0 = min(b[0][0] + g.span, g.nb[0] - 1);
+    const int lo1 = max(bmin - g.span, 0), hi1 = min(bmax + g.span, g.nb[DIM - 1] - 1);
+    for (int b0 = lo0 + ls; b0 <= hi0; b0 += S) {
+      const int first = b0 * g.nb[DIM - 1];
+      range_sum<DIM, WT, false>(ss, boff[first + lo1], boff[first + hi1 + 1], x, sn, cs, g.R, acc, 0u);
+    }
+  } else {
+    for (int u = 0; u < WT; ++u) {
+      const int lo0 = max(b[u][0] - g.span, 0), hi0 = min(b[u][0] + g.span, g.nb[0] - 1);
+      const int lo1 = max(b[u][DIM - 1] - g.span, 0), hi1 = min(b[u][DIM - 1] + g.span, g.nb[DIM - 1] - 1);
+      for (int b0 = lo0 + ls; b0 <= hi0; b0 += S) {
+        const int first = b0 * g.nb[DIM - 1];
+        range_sum<DIM, WT, true>(ss, boff[first + lo1], boff[first + hi1 + 1], x, sn, cs, g.R, acc, 1u << u);
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < S; off <<= 1)
+#pragma unroll
+    for (int u = 0; u < WT; ++u) acc[u] += __shfl_xor(acc[u], off, 64);
+  if (ls == 0) {
+#pragma unroll
+    for (int u = 0; u < WT; ++u)
+      if (t0 + u < m) alpha[sidx[t0 + u]] = 1.0 / acc[u];
+  }
 }
 
 // the same sum for listed samples (caller indices), for audits and checks:
@@ -243,8 +293,7 @@ void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const d
     hipLaunchKernelGGL(k_wbin_count<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, cnt, p->wb_of.as<int32_t>());
   else
     hipLaunchKernelGGL(k_wbin_count<2>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, cnt, p->wb_of.as<int32_t>());
-  exclusive_scan_i32(cnt, off, nbins, p->scan_tmp.as<int32_t>(), s);
-  FTCG_HIP(hipMemcpyAsync(cnt, off, sizeof(int32_t) * nbins, hipMemcpyDeviceToDevice, s));
+  exclusive_scan_i32(cnt, off, nbins, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
   if (dim == 1)
     hipLaunchKernelGGL(k_wbin_scatter<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
                        p->ws_k.as<WSample<1>>(), p->ws_idx.as<int32_t>(), p->sc_orig.as<double>());
@@ -256,17 +305,46 @@ void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const d
   p->have_wbins = true;
 }
 
+// Launch shape: WT samples per lane group and S lanes per group, from the
+// plan's tuning when set, else S = 1 and WT = 2 from 2^19 samples up (where
+// sharing candidate loads pays) and WT = 1 below (where the GPU is short of
+// wavefronts and longer per-lane chains cost more than they save).
+template <int DIM, int WT, int S>
+static void launch_weights(ftcg_plan p) {
+  const int64_t groups = (p->m + WT - 1) / WT;
+  const unsigned nb = (unsigned)((groups * S + WB_BLOCK - 1) / WB_BLOCK);
+  hipLaunchKernelGGL((k_frame_weights<DIM, WT, S>), dim3(nb), dim3(WB_BLOCK), 0, p->stream,
+                     p->ws_k.as<WSample<DIM>>(), p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), p->m, p->wgeom,
+                     p->alpha.as<double>());
+}
+
+template <int DIM, int WT>
+static void launch_weights_s(ftcg_plan p, int S) {
+  switch (S) {
+    case 1: launch_weights<DIM, WT, 1>(p); break;
+    case 2: launch_weights<DIM, WT, 2>(p); break;
+    case 4: launch_weights<DIM, WT, 4>(p); break;
+    default: launch_weights<DIM, WT, 8>(p); break;
+  }
+}
+
+template <int DIM>
+static void launch_weights_dim(ftcg_plan p) {
+  const int wt = p->w_samples ? p->w_samples : (p->m >= (int64_t(1) << 19) ? 2 : 1);
+  const int S = p->w_lanes ? p->w_lanes : 1;
+  switch (wt) {
+    case 1: launch_weights_s<DIM, 1>(p, S); break;
+    case 2: launch_weights_s<DIM, 2>(p, S); break;
+    default: launch_weights_s<DIM, 4>(p, S); break;
+  }
+}
+
 void run_plain_weights(ftcg_plan p) {
-  const int64_t m = p->m;
-  const unsigned nb = (unsigned)((m + WB_BLOCK - 1) / WB_BLOCK);
-  const int32_t* off = p->wb_off.as<int32_t>();
   timing_begin(p, STEP_WEIGHTS);
   if (p->dim == 1)
-    hipLaunchKernelGGL(k_frame_weights<1>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, p->ws_k.as<WSample<1>>(),
-                       p->ws_idx.as<int32_t>(), off, m, p->wgeom, p->alpha.as<double>());
+    launch_weights_dim<1>(p);
   else
-    hipLaunchKernelGGL(k_frame_weights<2>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, p->ws_k.as<WSample<2>>(),
-                       p->ws_idx.as<int32_t>(), off, m, p->wgeom, p->alpha.as<double>());
+    launch_weights_dim<2>(p);
   FTCG_HIP(hipGetLastError());
   timing_end(p, STEP_WEIGHTS);
 }
