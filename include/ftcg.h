@@ -152,14 +152,10 @@ typedef enum { FTCG_ACCUM_FIXED = 0, FTCG_ACCUM_F64 = 1 } ftcg_accum;
 ftcg_status ftcg_plan_set_tuning(ftcg_plan plan, int tile, int accum, int lds_copies);
 
 /* Launch shape of the frame-weight sum (Sec. III-C, eq:difopt), taking effect
- * at the next weight computation:
- *   samples_per_group : 1, 2 or 4 consecutive bin-sorted samples share every
- *                       candidate load (0 = automatic: 2 from 2^19 samples
- *                       up, else 1);
- *   lanes_per_group   : 1, 2, 4 or 8 lanes split a group's bin rows
- *                       (0 = automatic: 1).
+ * at the next weight computation: samples_per_lane = 1, 2 or 4 consecutive
+ * bin-sorted samples share each lane's candidate loads (0 = automatic: 1).
  * Results agree to rounding for every shape. FTCG_EINVAL for other values. */
-ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan plan, int samples_per_group, int lanes_per_group);
+ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan plan, int samples_per_lane);
 
 /* Per-step timing with HIP events on the plan's stream.
  * enable != 0 records events around every step of later calls; ftcg_plan_timing

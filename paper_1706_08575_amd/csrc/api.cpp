@@ -145,13 +145,13 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
   p->accum = dtype == FTCG_F32 ? ACCUM_FIXED : ACCUM_F64;
   ftcg_status st = guarded([&] {
     setup_tiles(p);
-    p->flags.ensure(128);
+    p->flags.ensure(FLAGS_BYTES);
     p->deapod.ensure(sizeof(double) * n0);
     compute_deapod(p);
     const size_t csz = dtype == FTCG_F64 ? 16 : 8;
     p->grid.ensure(csz * (size_t)(dim == 2 ? G * G : G));
     if (dim == 2) p->fft_tmp.ensure(csz * (size_t)(n0 * G));
-    if (hipHostMalloc((void**)&p->host_flags, 128, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&p->host_flags, FLAGS_BYTES, hipHostMallocDefault) != hipSuccess) {
       p->host_flags = nullptr;
       throw StatusError{FTCG_ENOMEM};
     }
@@ -168,7 +168,7 @@ ftcg_status ftcg_plan_destroy(ftcg_plan p) {
   if (!p) return FTCG_EINVAL;
   (void)hipStreamSynchronize(p->stream);
   DevBuf* bufs[] = {&p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp,
-                    &p->flags,  &p->wb_cnt, &p->wb_off, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->sc_orig, &p->audit_buf,
+                    &p->flags,  &p->wb_cnt, &p->wb_off, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->ws_inv, &p->audit_buf,
                     &p->grid,   &p->fft_tmp, &p->deapod, &p->tile_order};
   for (DevBuf* b : bufs) b->release();
   for (auto& pr : p->timing.pending) {
@@ -189,17 +189,36 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     p->have_points = false;
     p->have_weights = false;
     p->m = m;
-    // 1) finiteness + bounding box (one host synchronisation)
+    // 1) finiteness + bounding box (one host synchronisation); the same
+    //    launch zeroes the tile counters of step 3
     timing_begin(p, STEP_BIN);
-    launch_check_points(p, k_dev, m, p->flags.as<double>());
-    FTCG_HIP(hipMemcpyAsync(p->host_flags, p->flags.p, 40, hipMemcpyDeviceToHost, p->stream));
+    int32_t* zero_ptr = nullptr;
+    int64_t zero_n = 0;
+    if (!p->weights_only) {
+      setup_tiles(p);
+      p->tile_cnt.ensure(sizeof(int32_t) * (p->ntiles + 1));
+      zero_ptr = p->tile_cnt.as<int32_t>();
+      zero_n = p->ntiles + 1;
+    }
+    auto* part = reinterpret_cast<unsigned long long*>(static_cast<char*>(p->flags.p) + FLAGS_PART_OFF);
+    const int nparts = launch_check_points(p, k_dev, m, part, zero_ptr, zero_n);
+    auto* hpart = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(p->host_flags) + FLAGS_PART_OFF);
+    FTCG_HIP(hipMemcpyAsync(hpart, part, sizeof(unsigned long long) * 5 * nparts, hipMemcpyDeviceToHost,
+                            p->stream));
     FTCG_HIP(hipStreamSynchronize(p->stream));
-    const unsigned long long* hf = reinterpret_cast<const unsigned long long*>(p->host_flags);
-    if (hf[0] != 0) throw StatusError{FTCG_EINVAL};
+    unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
+    for (int b = 0; b < nparts; ++b) {
+      const unsigned long long* q = hpart + 5 * b;
+      if (q[0] != 0) throw StatusError{FTCG_EINVAL};
+      for (int a = 0; a < 2; ++a) {
+        lo[a] = q[1 + a] < lo[a] ? q[1 + a] : lo[a];
+        hi[a] = q[3 + a] > hi[a] ? q[3 + a] : hi[a];
+      }
+    }
     double kmin[2] = {0, 0}, kmax[2] = {0, 0};
     for (int a = 0; a < p->dim; ++a) {
-      kmin[a] = decode_ordered(hf[1 + a]);
-      kmax[a] = decode_ordered(hf[3 + a]);
+      kmin[a] = decode_ordered(lo[a]);
+      kmax[a] = decode_ordered(hi[a]);
     }
     // 2) weights (caller order)
     p->alpha.ensure(sizeof(double) * m);
@@ -237,13 +256,11 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
       return;
     }
     // 3) tile binning of spread records (worst case 2^dim records per sample)
-    setup_tiles(p);
     const int64_t cap = m << p->dim;
     const size_t rsz = p->dtype == FTCG_F64 ? sizeof(Rec<double>) : sizeof(Rec<float>);
     const size_t asz = p->dtype == FTCG_F64 ? sizeof(double) : sizeof(float);
     p->recs.ensure(rsz * cap);
     p->alpha_s.ensure(asz * cap);
-    p->tile_cnt.ensure(sizeof(int32_t) * (p->ntiles + 1));
     p->tile_off.ensure(sizeof(int32_t) * (p->ntiles + 1));
     p->scan_tmp.ensure(scan_tmp_bytes(p->ntiles));
     bin_points_k(p, k_dev);
@@ -331,13 +348,11 @@ ftcg_status ftcg_plan_info(ftcg_plan p, int64_t* grid_size, int64_t* n_records, 
   });
 }
 
-ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan p, int samples_per_group, int lanes_per_group) {
+ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan p, int samples_per_lane) {
   if (!p) return FTCG_EINVAL;
-  const int w = samples_per_group, l = lanes_per_group;
+  const int w = samples_per_lane;
   if (!(w == 0 || w == 1 || w == 2 || w == 4)) return FTCG_EINVAL;
-  if (!(l == 0 || l == 1 || l == 2 || l == 4 || l == 8)) return FTCG_EINVAL;
   p->w_samples = w;
-  p->w_lanes = l;
   return FTCG_OK;
 }
 

@@ -25,19 +25,24 @@ __device__ inline unsigned long long ordered_bits(double x) {
   return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
 }
 
-// flags layout (unsigned long long): [0] bad flag, [1..2] min per axis, [3..4] max per axis
-// grid-stride pass over the points; each workgroup reduces its bounds with
-// wavefront shuffles and LDS and issues one atomic per bound, and the grid is
-// kept small (CHECK_BLOCKS) so that few atomics meet on the four words
+// One pass over the points in at most CHECK_BLOCKS workgroups. Workgroup b
+// reduces its points with wavefront shuffles and LDS and writes five words to
+// part[5 b ..]: a non-finite flag, then the per-axis minimum and maximum as
+// order-preserving integers; the host reduces the partials (no atomics, no
+// initialisation pass). The same launch zeroes zero_ptr[0 .. zero_n), the
+// tile counters of the binning that follows.
 constexpr int CHECK_BLOCKS = 256;
 __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __restrict__ k, int64_t m, int dim,
-                                                            unsigned long long* __restrict__ flags) {
+                                                            unsigned long long* __restrict__ part,
+                                                            int32_t* __restrict__ zero_ptr, int64_t zero_n) {
   __shared__ unsigned long long sred[4][BIN_BLOCK / 64];
   __shared__ int sbad;
+  const int64_t gt = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x, gs = (int64_t)gridDim.x * BIN_BLOCK;
+  for (int64_t i = gt; i < zero_n; i += gs) zero_ptr[i] = 0;
   if (threadIdx.x == 0) sbad = 0;
   unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
   bool bad = false;
-  for (int64_t j = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; j < m; j += (int64_t)gridDim.x * BIN_BLOCK) {
+  for (int64_t j = gt; j < m; j += gs) {
     for (int a = 0; a < dim; ++a) {
       const double x = k[j * dim + a];
       if (!isfinite(x)) {
@@ -70,35 +75,29 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __rest
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    if (sbad) atomicOr(&flags[0], 1ull);
-    for (int a = 0; a < dim; ++a) {
+    unsigned long long* o = part + 5 * blockIdx.x;
+    o[0] = sbad ? 1ull : 0ull;
+    for (int a = 0; a < 2; ++a) {
       unsigned long long l = sred[a][0], h = sred[2 + a][0];
       for (int v = 1; v < BIN_BLOCK / 64; ++v) {
         l = sred[a][v] < l ? sred[a][v] : l;
         h = sred[2 + a][v] > h ? sred[2 + a][v] : h;
       }
-      atomicMin(&flags[1 + a], l);
-      atomicMax(&flags[3 + a], h);
+      o[1 + a] = l;
+      o[3 + a] = h;
     }
   }
 }
 
-__global__ void k_init_flags(unsigned long long* flags) {
-  if (threadIdx.x == 0) {
-    flags[0] = 0ull;
-    flags[1] = flags[2] = ~0ull;
-    flags[3] = flags[4] = 0ull;
-  }
-}
-
-void launch_check_points(ftcg_plan p, const double* k, int64_t m, double* flags_d) {
-  auto* f = reinterpret_cast<unsigned long long*>(flags_d);
-  hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, p->stream, f);
+int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long long* part, int32_t* zero_ptr,
+                        int64_t zero_n) {
   int64_t nb = (m + 8 * BIN_BLOCK - 1) / (8 * BIN_BLOCK);  // 8 points per thread at least
   if (nb > CHECK_BLOCKS) nb = CHECK_BLOCKS;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_check_points, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream, k, m, p->dim, f);
+  hipLaunchKernelGGL(k_check_points, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream, k, m, p->dim, part,
+                     zero_ptr, zero_n);
   FTCG_HIP(hipGetLastError());
+  return (int)nb;
 }
 
 // ---------------------------------------------------------------------------
@@ -201,6 +200,87 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tile_scatter(const double* __rest
   }
 }
 
+// The same two steps with the counters privatised in LDS, for up to
+// LDS_TILE_KEYS tiles: a workgroup takes BIN_IPT * BIN_BLOCK consecutive
+// samples (coalesced, all loads issued before the first count), counts their
+// records in LDS (wavefront-aggregated LDS atomics), and only then touches the
+// global counters, once per tile it saw. The scatter claims one range per
+// tile with that count and hands out positions inside it from LDS.
+constexpr int BIN_IPT = 4;
+constexpr int LDS_TILE_KEYS = 4096;
+
+template <int DIM>
+__device__ inline void block_keys(const double* __restrict__ k, int64_t m, const TileGeom& g, int64_t j0,
+                                  double (&u)[BIN_IPT][DIM], int (&c)[BIN_IPT][DIM], int (&key)[BIN_IPT][4],
+                                  int (&l0)[BIN_IPT][4], int (&l1)[BIN_IPT][4]) {
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i)
+    sample_keys<DIM>(k, j0 + (int64_t)i * BIN_BLOCK + threadIdx.x, m, g, u[i], c[i], key[i], l0[i], l1[i]);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(BIN_BLOCK) void k_tile_count_lds(const double* __restrict__ k, int64_t m, TileGeom g,
+                                                              int32_t* __restrict__ cnt, int nkeys) {
+  extern __shared__ int32_t hist[];
+  for (int i = threadIdx.x; i < nkeys; i += BIN_BLOCK) hist[i] = 0;
+  double u[BIN_IPT][DIM];
+  int c[BIN_IPT][DIM], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
+  block_keys<DIM>(k, m, g, (int64_t)blockIdx.x * BIN_IPT * BIN_BLOCK, u, c, key, l0, l1);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i)
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q) agg_atomic_add(hist, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nkeys; i += BIN_BLOCK) {
+    const int v = hist[i];
+    if (v) atomicAdd(&cnt[i], v);
+  }
+}
+
+template <int DIM, class real>
+__global__ __launch_bounds__(BIN_BLOCK) void k_tile_scatter_lds(const double* __restrict__ k, int64_t m, TileGeom g,
+                                                                const double* __restrict__ alpha,
+                                                                int32_t* __restrict__ cursor, int nkeys,
+                                                                Rec<real>* __restrict__ recs,
+                                                                real* __restrict__ alpha_s) {
+  extern __shared__ int32_t base[];
+  for (int i = threadIdx.x; i < nkeys; i += BIN_BLOCK) base[i] = 0;
+  const int64_t j0 = (int64_t)blockIdx.x * BIN_IPT * BIN_BLOCK;
+  double u[BIN_IPT][DIM];
+  int c[BIN_IPT][DIM], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
+  block_keys<DIM>(k, m, g, j0, u, c, key, l0, l1);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i)
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q) agg_atomic_add(base, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nkeys; i += BIN_BLOCK) {
+    const int v = base[i];
+    if (v) base[i] = atomicAdd(&cursor[i], v);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i) {
+    const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
+    const real a = (j < m && alpha) ? (real)alpha[j] : (real)1;
+    Rec<real> r;
+    r.f0 = (real)(u[i][0] - (double)c[i][0]);
+    r.f1 = (DIM == 2) ? (real)(u[i][DIM - 1] - (double)c[i][DIM - 1]) : (real)0;
+    r.src = (int32_t)j;
+#pragma unroll
+    for (int q = 0; q < (1 << DIM); ++q) {
+      const int pos = agg_atomic_add(base, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
+      if (key[i][q] >= 0) {
+        r.c01 = (int32_t)(((uint32_t)l0[i][q] & 0xffffu) | ((uint32_t)l1[i][q] << 16));
+        recs[pos] = r;
+        alpha_s[pos] = a;
+      }
+    }
+  }
+}
+
 template <class real>
 __global__ __launch_bounds__(BIN_BLOCK) void k_refill_alpha(const Rec<real>* __restrict__ recs, int64_t nrec,
                                                             const double* __restrict__ alpha,
@@ -220,27 +300,44 @@ static TileGeom tile_geom(ftcg_plan p) {
   return g;
 }
 
+// tile binning; the tile counters were zeroed by the input check
 template <class real>
 static void bin_points_t(ftcg_plan p, const double* k) {
   const TileGeom g = tile_geom(p);
   hipStream_t s = p->stream;
   const int64_t m = p->m;
-  const unsigned nb = (unsigned)((m + BIN_BLOCK - 1) / BIN_BLOCK);
   int32_t* cnt = p->tile_cnt.as<int32_t>();
   int32_t* off = p->tile_off.as<int32_t>();
-  FTCG_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (p->ntiles + 1), s));
-  if (p->dim == 1)
-    hipLaunchKernelGGL(k_tile_count<1>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
-  else
-    hipLaunchKernelGGL(k_tile_count<2>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
-  exclusive_scan_i32(cnt, off, p->ntiles, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
   const double* alpha = p->have_weights ? p->alpha.as<double>() : nullptr;
-  if (p->dim == 1)
-    hipLaunchKernelGGL((k_tile_scatter<1, real>), dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, alpha, cnt,
-                       p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
-  else
-    hipLaunchKernelGGL((k_tile_scatter<2, real>), dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, alpha, cnt,
-                       p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
+  const int nkeys = (int)p->ntiles;
+  if (nkeys <= LDS_TILE_KEYS) {
+    const unsigned nb = (unsigned)((m + BIN_IPT * BIN_BLOCK - 1) / (BIN_IPT * BIN_BLOCK));
+    const size_t lds = sizeof(int32_t) * nkeys;
+    if (p->dim == 1)
+      hipLaunchKernelGGL(k_tile_count_lds<1>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, cnt, nkeys);
+    else
+      hipLaunchKernelGGL(k_tile_count_lds<2>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, cnt, nkeys);
+    exclusive_scan_i32(cnt, off, p->ntiles, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
+    if (p->dim == 1)
+      hipLaunchKernelGGL((k_tile_scatter_lds<1, real>), dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, alpha, cnt,
+                         nkeys, p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
+    else
+      hipLaunchKernelGGL((k_tile_scatter_lds<2, real>), dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, alpha, cnt,
+                         nkeys, p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
+  } else {
+    const unsigned nb = (unsigned)((m + BIN_BLOCK - 1) / BIN_BLOCK);
+    if (p->dim == 1)
+      hipLaunchKernelGGL(k_tile_count<1>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
+    else
+      hipLaunchKernelGGL(k_tile_count<2>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
+    exclusive_scan_i32(cnt, off, p->ntiles, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
+    if (p->dim == 1)
+      hipLaunchKernelGGL((k_tile_scatter<1, real>), dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, alpha, cnt,
+                         p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
+    else
+      hipLaunchKernelGGL((k_tile_scatter<2, real>), dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, alpha, cnt,
+                         p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
+  }
   FTCG_HIP(hipGetLastError());
 }
 

@@ -178,8 +178,7 @@ struct ftcg_plan_s {
   int64_t G = 0;       // grid edge
   double beta = 0.0;   // kernel exp(-beta s^2)
   int tile_req = 0;    // requested tile edge (0 = automatic)
-  int w_samples = 0;   // frame-weight kernel: samples per lane group (0 = automatic)
-  int w_lanes = 0;     // frame-weight kernel: lanes per sample group (0 = automatic)
+  int w_samples = 0;   // frame-weight kernel: samples per lane (0 = automatic)
   int lds_copies = 1;
   int accum = 0;       // ftcg::Accum for float32 plans (float64 plans always use ACCUM_F64)
 
@@ -199,14 +198,14 @@ struct ftcg_plan_s {
   ftcg::DevBuf tile_cnt;     // ntiles + 1 int32 (count, then cursor)
   ftcg::DevBuf tile_off;     // ntiles + 1 int32
   ftcg::DevBuf scan_tmp;     // scan scratch
-  ftcg::DevBuf flags;        // small device scratch: [0] bad-input flag, doubles for bbox
+  ftcg::DevBuf flags;        // small device scratch: [6] audit estimate; bytes 128.. input-check partials
 
   // weight binning
   ftcg::DevBuf wb_cnt, wb_off;
   ftcg::DevBuf ws_k;         // sorted samples: k, sin(pi k), cos(pi k) (3*dim doubles each)
   ftcg::DevBuf ws_idx;       // sorted original index
   ftcg::DevBuf wb_of;        // weight-bin id per sample (caller order)
-  ftcg::DevBuf sc_orig;      // sin(pi k_a), cos(pi k_a) per sample, caller order (2*dim doubles)
+  ftcg::DevBuf ws_inv;       // sorted position of every sample (caller order)
   ftcg::WBinGeom wgeom{};
   bool have_wbins = false;
   bool weights_only = false;  // internal plans that only compute weights (no tile binning)
@@ -225,13 +224,17 @@ struct ftcg_plan_s {
   ftcg::DevBuf tile_order;   // ntiles int32 (heavy tiles first)
 
   ftcg::Timing timing;
-  double* host_flags = nullptr;  // pinned host mirror of small flags
+  double* host_flags = nullptr;  // pinned host mirror of flags (FLAGS_BYTES)
 };
 
 namespace ftcg {
 
 // launchers (defined in the .hip files); all enqueue on plan->stream
-void launch_check_points(ftcg_plan p, const double* k, int64_t m, double* flags);
+constexpr size_t FLAGS_BYTES = 16384;     // device flags / pinned host mirror
+constexpr size_t FLAGS_PART_OFF = 128;    // byte offset of the input-check partials
+// returns the number of partial records (5 words each) written to part
+int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long long* part, int32_t* zero_ptr,
+                        int64_t zero_n);
 void bin_points_k(ftcg_plan p, const double* k);   // fills recs, alpha_s, tile_off
 void refill_alpha(ftcg_plan p);                     // alpha_s[r] = alpha[recs[r].src]
 void build_weight_bins(ftcg_plan p, const double* k, const double* kmin,

@@ -117,12 +117,14 @@ __device__ inline void knn_search(const WSample<2>* __restrict__ ss, const int32
   }
 }
 
-// features (float32) and the analytic estimate of one sample from its keys
-__device__ inline double knn_features_of(const unsigned long long (&key)[KNN], const double* __restrict__ k,
-                                         const double* __restrict__ sc_orig, int64_t j, float R, float* f) {
+// features (float32) and the analytic estimate of one sample (sorted
+// position t) from its keys (caller indices, found in ss through inv)
+__device__ inline double knn_features_of(const unsigned long long (&key)[KNN], const WSample<2>* __restrict__ ss,
+                                         const int32_t* __restrict__ inv, int64_t t, float R, float* f) {
   const double pi = 3.141592653589793238462643383279502884;
-  const double x0 = k[2 * j], x1 = k[2 * j + 1];
-  const double s0 = sc_orig[4 * j], c0 = sc_orig[4 * j + 1], s1 = sc_orig[4 * j + 2], c1 = sc_orig[4 * j + 3];
+  const WSample<2> me = ss[t];
+  const double x0 = me.k[0], x1 = me.k[1];
+  const double s0 = me.sc[0][0], c0 = me.sc[0][1], s1 = me.sc[1][0], c1 = me.sc[1][1];
   double sum = 0.0;
 #pragma unroll
   for (int q = 0; q < KNN; ++q) {
@@ -131,13 +133,13 @@ __device__ inline double knn_features_of(const unsigned long long (&key)[KNN], c
       f[2 * q + 1] = R;
       continue;
     }
-    const int64_t i = (int64_t)(unsigned)(key[q] & 0xffffffffull);
-    const double dx = k[2 * i] - x0, dy = k[2 * i + 1] - x1;
+    const WSample<2> o = ss[inv[(int64_t)(unsigned)(key[q] & 0xffffffffull)]];
+    const double dx = o.k[0] - x0, dy = o.k[1] - x1;
     f[2 * q] = (float)dx;
     f[2 * q + 1] = (float)dy;
     double g = 1.0;
-    if (dx != 0.0) g *= (sc_orig[4 * i] * c0 - sc_orig[4 * i + 1] * s0) / (pi * dx);
-    if (dy != 0.0) g *= (sc_orig[4 * i + 2] * c1 - sc_orig[4 * i + 3] * s1) / (pi * dy);
+    if (dx != 0.0) g *= (o.sc[0][0] * c0 - o.sc[0][1] * s0) / (pi * dx);
+    if (dy != 0.0) g *= (o.sc[1][0] * c1 - o.sc[1][1] * s1) / (pi * dy);
     sum += g * g;
   }
   return 1.0 / (1.0 + sum);
@@ -148,8 +150,7 @@ __device__ inline double knn_features_of(const unsigned long long (&key)[KNN], c
 __global__ __launch_bounds__(256) void k_knn_features(const WSample<2>* __restrict__ ss,
                                                       const int32_t* __restrict__ sidx,
                                                       const int32_t* __restrict__ boff, WBinGeom g,
-                                                      const double* __restrict__ k,
-                                                      const double* __restrict__ sc_orig, int64_t m,
+                                                      const int32_t* __restrict__ inv, int64_t m,
                                                       float* __restrict__ feat, double* __restrict__ base,
                                                       const double* __restrict__ alpha, float* __restrict__ target) {
   const int64_t t = xcd_block(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(256) void k_knn_features(const WSample<2>* __restri
   unsigned long long key[KNN];
   knn_search(ss, sidx, boff, g, x, j, key);
   float f[NF];
-  const double b = knn_features_of(key, k, sc_orig, j, (float)g.R, f);
+  const double b = knn_features_of(key, ss, inv, t, (float)g.R, f);
 #pragma unroll
   for (int q = 0; q < NF; ++q) feat[(int64_t)j * NF + q] = f[q];
   if (base) base[j] = b;
@@ -267,8 +268,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ f
 __global__ __launch_bounds__(256) void k_learned_weights(const WSample<2>* __restrict__ ss,
                                                          const int32_t* __restrict__ sidx,
                                                          const int32_t* __restrict__ boff, WBinGeom g,
-                                                         const double* __restrict__ k,
-                                                         const double* __restrict__ sc_orig, int64_t m,
+                                                         const int32_t* __restrict__ inv, int64_t m,
                                                          const _Float16* __restrict__ P16,
                                                          const float* __restrict__ P32,
                                                          double* __restrict__ alpha) {
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(256) void k_learned_weights(const WSample<2>* __res
     unsigned long long key[KNN];
     knn_search(ss, sidx, boff, g, x, j, key);
     float f[NF];
-    b = knn_features_of(key, k, sc_orig, j, (float)g.R, f);
+    b = knn_features_of(key, ss, inv, t, (float)g.R, f);
 #pragma unroll
     for (int q = 0; q < NF; ++q) xs[tid * NF + q] = (_Float16)f[q];
   } else {
@@ -500,7 +500,7 @@ void launch_knn_features(ftcg_plan p, const double* k, float* feat, double* base
                          float* target) {
   const unsigned nb = (unsigned)((p->m + 255) / 256);
   hipLaunchKernelGGL(k_knn_features, dim3(nb), dim3(256), 0, p->stream, p->ws_k.as<WSample<2>>(),
-                     p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), p->wgeom, k, p->sc_orig.as<double>(), p->m,
+                     p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), p->wgeom, p->ws_inv.as<int32_t>(), p->m,
                      feat, base, alpha, target);
   FTCG_HIP(hipGetLastError());
 }
@@ -508,7 +508,7 @@ void launch_knn_features(ftcg_plan p, const double* k, float* feat, double* base
 void launch_learned_weights(ftcg_plan p, const double* k, const ftcg_mlp_s* mlp) {
   const unsigned nb = (unsigned)((p->m + 255) / 256);
   hipLaunchKernelGGL(k_learned_weights, dim3(nb), dim3(256), 0, p->stream, p->ws_k.as<WSample<2>>(),
-                     p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), p->wgeom, k, p->sc_orig.as<double>(), p->m,
+                     p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), p->wgeom, p->ws_inv.as<int32_t>(), p->m,
                      mlp->params16.as<_Float16>(), mlp->params.as<float>(), p->alpha.as<double>());
   FTCG_HIP(hipGetLastError());
 }

@@ -9,7 +9,8 @@
 // exactly separable).
 //
 // GPU layout: samples are counting-sorted into square neighbour bins of edge
-// h = R / s (k units; s in [2, 16] for about 6 samples per bin), so the box
+// h = R / s (k units; s in [2, 16] for about 3 samples per bin at the mean
+// density of the bounding box), so the box
 // of every sample lies in the (2s+1)^d bins around its own; the bins of one
 // row are contiguous in bin order, so each row is one candidate range. Sorted
 // arrays hold k and the
@@ -34,6 +35,10 @@ __device__ inline int wbin_of(const double* x, const WBinGeom& g, int* b) {
   return id;
 }
 
+// Counting sort into neighbour bins. Bins hold a few samples each, so the
+// lanes of a wavefront mostly hit different bins: plain per-lane atomics (one
+// instruction for the wavefront) beat aggregating equal keys first, which
+// would serialise one atomic round trip per distinct key.
 template <int DIM>
 __global__ __launch_bounds__(WB_BLOCK) void k_wbin_count(const double* __restrict__ k, int64_t m, WBinGeom g,
                                                          int32_t* __restrict__ cnt, int32_t* __restrict__ bin_of) {
@@ -45,8 +50,8 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wbin_count(const double* __restric
     for (int a = 0; a < DIM; ++a) x[a] = k[j * DIM + a];
     id = wbin_of<DIM>(x, g, b);
     bin_of[j] = id;
+    atomicAdd(&cnt[id], 1);
   }
-  agg_atomic_add(cnt, id, j < m);
 }
 
 template <int DIM>
@@ -54,153 +59,196 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wbin_scatter(const double* __restr
                                                            const int32_t* __restrict__ bin_of,
                                                            int32_t* __restrict__ cursor,
                                                            WSample<DIM>* __restrict__ ss, int32_t* __restrict__ sidx,
-                                                           double* __restrict__ sc_orig) {
+                                                           int32_t* __restrict__ inv) {
   const int64_t j = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
-  const int pos = agg_atomic_add(cursor, j < m ? bin_of[j] : 0, j < m);
   if (j >= m) return;
+  const int pos = atomicAdd(&cursor[bin_of[j]], 1);
   WSample<DIM> w;
   for (int a = 0; a < DIM; ++a) {
     w.k[a] = k[j * DIM + a];
     sincospi(w.k[a], &w.sc[a][0], &w.sc[a][1]);
-    sc_orig[j * 2 * DIM + 2 * a] = w.sc[a][0];
-    sc_orig[j * 2 * DIM + 2 * a + 1] = w.sc[a][1];
   }
   ss[pos] = w;
   sidx[pos] = (int32_t)j;
+  inv[j] = pos;
 }
 
-// 1/x to full float64 precision: hardware reciprocal estimate + two Newton steps
+// 1/x: hardware float64 reciprocal estimate refined by one Newton step, which
+// leaves an error of a few units in the last place
 __device__ inline double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
-// T_in^2 of one candidate i for sample n = (x, sn, cs), 0 outside the box.
-// Branch free: a coordinate difference of exactly 0 gives the factor
-// sinc(0) = 1 through selects, so every operand of the candidate is loaded
-// up front and the loop body has no data-dependent control flow.
+// pi^(2 DIM) T_in^2 of one candidate i for sample n = (x, sn, cs), 0 outside
+// the box (the kernels divide pi^(2 DIM) by the sum). Per axis, T factors into
+// sin(pi d) / (pi d) with d = k_i - k_n; here num = sin(pi d) + pi eps and
+// den = d + eps with eps = 2^-500. For d = 0, sin(pi d) comes out exactly 0
+// (the per-sample sin and cos are equal bit for bit, and the two products are
+// rounded separately, never fused), so num / den = pi: the factor pi * sinc(0)
+// with no compare or select. For |d| >= 2^-447, d + eps == d and
+// sin(pi d) + pi eps == sin(pi d) exactly, so nothing changes; eps^2 and
+// (pi eps)^2 stay normal numbers. This keeps the loop body to plain float64
+// arithmetic.
+constexpr double WEPS = 0x1p-500;
+constexpr double WPI = 3.141592653589793238462643383279502884;
+constexpr double WPI_EPS = WPI * WEPS;
+template <int DIM>
+constexpr double wscale() { return DIM == 1 ? WPI * WPI : WPI * WPI * WPI * WPI; }
+
 template <int DIM>
 __device__ inline double pair_term(const WSample<DIM>& o, const double* x, const double* sn, const double* cs,
                                    double R) {
-  const double pi = 3.141592653589793238462643383279502884;
-  double num = 1.0, den = 1.0;
-  bool inside = true;
+#pragma clang fp contract(off)
+  double num = 1.0, den = 1.0, dmax = 0.0;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const double d = o.k[a] - x[a];
-    inside = inside && (fabs(d) <= R);
-    // sin(pi (k_i - k_n)) from the per-sample sin/cos
-    const double sd = o.sc[a][0] * cs[a] - o.sc[a][1] * sn[a];
-    const bool z = d == 0.0;
-    num *= z ? 1.0 : sd;
-    den *= z ? 1.0 : pi * d;
+    dmax = a == 0 ? fabs(d) : fmax(dmax, fabs(d));
+    // sin(pi (k_i - k_n)) = sin(pi k_i) cos(pi k_n) - cos(pi k_i) sin(pi k_n)
+    const double p1 = o.sc[a][0] * cs[a];
+    const double p2 = o.sc[a][1] * sn[a];
+    num *= (p1 - p2) + WPI_EPS;
+    den *= d + WEPS;
   }
   const double q = num * rcp64(den);
-  return inside ? q * q : 0.0;
+  const double t = q * q;
+  // outside the box: clear the high word, which leaves at most a subnormal
+  // (below 2^-1022), nothing next to a sum that starts at pi^(2 DIM)
+  const int hi = dmax <= R ? __double2hiint(t) : 0;
+  return __hiloint2double(hi, __double2loint(t));
 }
 
-// Adds to acc[u] the T_in^2 of every candidate i in [beg, end) for the NT
-// samples u (all of them when !MASKED, else those with bit u of `mask`).
-// Candidates alternate between two register sets, each loaded while the
-// other one's pair terms are formed.
-template <int DIM, int NT, bool MASKED>
+// Adds to acc[u] the pi^(2 DIM) T_in^2 of every candidate i in [beg, end) for the NT
+// samples u. Candidates alternate between two register sets, each loaded
+// while the other one's pair terms are formed.
+template <int DIM, int NT>
 __device__ inline void range_sum(const WSample<DIM>* __restrict__ ss, int beg, int end, const double (&x)[NT][DIM],
                                  const double (&sn)[NT][DIM], const double (&cs)[NT][DIM], double R,
-                                 double (&acc)[NT], unsigned mask) {
+                                 double (&acc)[NT]) {
   if (beg >= end) return;
   WSample<DIM> a = ss[beg];
   for (int i = beg; i < end; i += 2) {
     const bool has_b = i + 1 < end;
     const WSample<DIM> b = ss[has_b ? i + 1 : i];
 #pragma unroll
-    for (int u = 0; u < NT; ++u) {
-      const double t = pair_term<DIM>(a, x[u], sn[u], cs[u], R);
-      acc[u] += (!MASKED || ((mask >> u) & 1u)) ? t : 0.0;
-    }
+    for (int u = 0; u < NT; ++u) acc[u] += pair_term<DIM>(a, x[u], sn[u], cs[u], R);
     a = ss[i + 2 < end ? i + 2 : i];
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
       const double t = pair_term<DIM>(b, x[u], sn[u], cs[u], R);
-      acc[u] += (has_b && (!MASKED || ((mask >> u) & 1u))) ? t : 0.0;
+      acc[u] += has_b ? t : 0.0;
     }
   }
 }
 
-// WT consecutive sorted samples per group of S lanes. Sorted samples are
-// bin-major, so the WT samples nearly always share a bin row; then one pass
-// over the union of their candidate ranges (rows b0 - s .. b0 + s, bins
-// min b1 - s .. max b1 + s, which the box test trims back to each sample's own
-// box) feeds every loaded candidate to all WT pair terms. Samples in
-// different bin rows (the ends of rows) take their own ranges one after
-// another. The S lanes of a group split the rows round-robin and add their
-// partial sums by shuffles; S > 1 is for small rasters, where one lane per
-// group would leave most of the GPU idle.
-template <int DIM, int WT, int S>
-__global__ __launch_bounds__(WB_BLOCK) void k_frame_weights(const WSample<DIM>* __restrict__ ss,
-                                                            const int32_t* __restrict__ sidx,
-                                                            const int32_t* __restrict__ boff, int64_t m, WBinGeom g,
-                                                            double* __restrict__ alpha) {
-  const int64_t gt = xcd_block(blockIdx.x, gridDim.x) * WB_BLOCK + threadIdx.x;
-  const int ls = (int)(gt % S);
-  const int64_t t0 = (gt / S) * WT;
-  if (t0 >= m) return;   // whole groups leave together (S divides the block)
-  double x[WT][DIM], sn[WT][DIM], cs[WT][DIM], acc[WT];
-  int b[WT][DIM];
+// 1D: WT consecutive sorted samples per lane share one pass over the union
+// of their candidate ranges (bins min b - s .. max b + s, which the box test
+// trims back to each sample's own box).
+template <int WT>
+__global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_1d(const WSample<1>* __restrict__ ss,
+                                                               const int32_t* __restrict__ sidx,
+                                                               const int32_t* __restrict__ boff, int64_t m,
+                                                               WBinGeom g, double* __restrict__ alpha) {
+  const int64_t t0 = ((int64_t)blockIdx.x * WB_BLOCK + threadIdx.x) * WT;
+  if (t0 >= m) return;
+  double x[WT][1], sn[WT][1], cs[WT][1], acc[WT];
+  int bmin = 1 << 30, bmax = -1;
 #pragma unroll
   for (int u = 0; u < WT; ++u) {
-    const int64_t t = t0 + u < m ? t0 + u : m - 1;   // a last odd sample repeats (and is not stored twice)
-    const WSample<DIM> me = ss[t];
-    for (int a = 0; a < DIM; ++a) {
-      x[u][a] = me.k[a];
-      sn[u][a] = me.sc[a][0];
-      cs[u][a] = me.sc[a][1];
-    }
-    wbin_of<DIM>(x[u], g, b[u]);
+    const int64_t t = t0 + u < m ? t0 + u : m - 1;   // a last partial group repeats (and is not stored twice)
+    const WSample<1> me = ss[t];
+    x[u][0] = me.k[0];
+    sn[u][0] = me.sc[0][0];
+    cs[u][0] = me.sc[0][1];
+    int b[1];
+    wbin_of<1>(x[u], g, b);
+    bmin = min(bmin, b[0]);
+    bmax = max(bmax, b[0]);
     acc[u] = 0.0;
   }
-  bool same_row = true;
-  int bmin = b[0][DIM - 1], bmax = b[0][DIM - 1];
+  const int lo = max(bmin - g.span, 0), hi = min(bmax + g.span, g.nb[0] - 1);
+  range_sum<1, WT>(ss, boff[lo], boff[hi + 1], x, sn, cs, g.R, acc);
 #pragma unroll
-  for (int u = 1; u < WT; ++u) {
-    same_row = same_row && (DIM == 1 || b[u][0] == b[0][0]);
-    bmin = min(bmin, b[u][DIM - 1]);
-    bmax = max(bmax, b[u][DIM - 1]);
-  }
-  if (DIM == 1) {
-    // one candidate range, split into S contiguous pieces
-    const int lo = max(bmin - g.span, 0), hi = min(bmax + g.span, g.nb[0] - 1);
-    const int beg = boff[lo], end = boff[hi + 1];
-    const int len = (end - beg + S - 1) / S;
-    const int pb = beg + ls * len, pe = min(pb + len, end);
-    range_sum<DIM, WT, false>(ss, pb, pe, x, sn, cs, g.R, acc, 0u);
-  } else if (same_row) {
-    const int lo0 = max(b[0][0] - g.span, 0), hi0 = min(b[0][0] + g.span, g.nb[0] - 1);
-    const int lo1 = max(bmin - g.span, 0), hi1 = min(bmax + g.span, g.nb[DIM - 1] - 1);
-    for (int b0 = lo0 + ls; b0 <= hi0; b0 += S) {
-      const int first = b0 * g.nb[DIM - 1];
-      range_sum<DIM, WT, false>(ss, boff[first + lo1], boff[first + hi1 + 1], x, sn, cs, g.R, acc, 0u);
-    }
-  } else {
+  for (int u = 0; u < WT; ++u)
+    if (t0 + u < m) alpha[sidx[t0 + u]] = wscale<1>() / acc[u];
+}
+
+// 2D: one workgroup per (bin row b0, run of WB_BLOCK * WT consecutive
+// samples of that row), so a workgroup's samples share their row window and
+// their column window is lo1 .. hi1 (first and last sample's bins, widened by
+// s). Row by row, the window's candidates are staged in LDS in chunks of
+// WCH (coalesced 16-byte copies); every lane then walks its own range inside
+// the chunk from LDS. Candidates are read from global memory once per
+// workgroup instead of once per lane, which takes the vector-memory path off
+// the critical path. Rows with more samples than the grid's x extent covers
+// are walked in steps of gridDim.x runs.
+constexpr int WCH = 512;
+template <int WT>
+__global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_rows(const WSample<2>* __restrict__ ss,
+                                                                 const int32_t* __restrict__ sidx,
+                                                                 const int32_t* __restrict__ boff, WBinGeom g,
+                                                                 int cx, double* __restrict__ alpha) {
+  __shared__ __align__(16) WSample<2> cand[WCH];
+  const int64_t lid = xcd_block(blockIdx.x, gridDim.x);
+  const int b0 = (int)(lid / cx), bx = (int)(lid % cx);
+  const int nb1 = g.nb[1];
+  const int rs = boff[b0 * nb1], re = boff[(b0 + 1) * nb1];
+  const int rlo = max(b0 - g.span, 0), rhi = min(b0 + g.span, g.nb[0] - 1);
+  for (int c0 = rs + bx * WB_BLOCK * WT; c0 < re; c0 += cx * WB_BLOCK * WT) {
+    const int cend = min(c0 + WB_BLOCK * WT, re);
+    const int t0 = c0 + threadIdx.x * WT;
+    double x[WT][2], sn[WT][2], cs[WT][2], acc[WT];
+    int mylo = 1 << 30, myhi = -1;
+#pragma unroll
     for (int u = 0; u < WT; ++u) {
-      const int lo0 = max(b[u][0] - g.span, 0), hi0 = min(b[u][0] + g.span, g.nb[0] - 1);
-      const int lo1 = max(b[u][DIM - 1] - g.span, 0), hi1 = min(b[u][DIM - 1] + g.span, g.nb[DIM - 1] - 1);
-      for (int b0 = lo0 + ls; b0 <= hi0; b0 += S) {
-        const int first = b0 * g.nb[DIM - 1];
-        range_sum<DIM, WT, true>(ss, boff[first + lo1], boff[first + hi1 + 1], x, sn, cs, g.R, acc, 1u << u);
+      const int t = t0 + u < cend ? t0 + u : cend - 1;
+      const WSample<2> me = ss[t];
+      for (int a = 0; a < 2; ++a) {
+        x[u][a] = me.k[a];
+        sn[u][a] = me.sc[a][0];
+        cs[u][a] = me.sc[a][1];
+      }
+      int b[2];
+      wbin_of<2>(x[u], g, b);
+      mylo = min(mylo, b[1]);
+      myhi = max(myhi, b[1]);
+      acc[u] = 0.0;
+    }
+    const bool active = t0 < cend;
+    mylo = max(mylo - g.span, 0);
+    myhi = min(myhi + g.span, nb1 - 1);
+    // the run's column window: bins of its first and last sample (bin order)
+    int lo1, hi1;
+    {
+      int b[2];
+      double xf[2] = {ss[c0].k[0], ss[c0].k[1]};
+      wbin_of<2>(xf, g, b);
+      lo1 = max(b[1] - g.span, 0);
+      double xl[2] = {ss[cend - 1].k[0], ss[cend - 1].k[1]};
+      wbin_of<2>(xl, g, b);
+      hi1 = min(b[1] + g.span, nb1 - 1);
+    }
+    for (int r = rlo; r <= rhi; ++r) {
+      const int gs = boff[r * nb1 + lo1], ge = boff[r * nb1 + hi1 + 1];
+      const int ms = active ? boff[r * nb1 + mylo] : 0, me = active ? boff[r * nb1 + myhi + 1] : 0;
+      for (int q0 = gs; q0 < ge; q0 += WCH) {
+        const int q1 = min(q0 + WCH, ge);
+        __syncthreads();  // the previous chunk has been consumed
+        {
+          const float4* src = reinterpret_cast<const float4*>(ss + q0);
+          float4* dst = reinterpret_cast<float4*>(cand);
+          const int n4 = (q1 - q0) * 3;
+          for (int i = threadIdx.x; i < n4; i += WB_BLOCK) dst[i] = src[i];
+        }
+        __syncthreads();
+        const int a0 = max(ms, q0), a1 = min(me, q1);
+        if (a0 < a1) range_sum<2, WT>(cand, a0 - q0, a1 - q0, x, sn, cs, g.R, acc);
       }
     }
-  }
-#pragma unroll
-  for (int off = 1; off < S; off <<= 1)
-#pragma unroll
-    for (int u = 0; u < WT; ++u) acc[u] += __shfl_xor(acc[u], off, 64);
-  if (ls == 0) {
 #pragma unroll
     for (int u = 0; u < WT; ++u)
-      if (t0 + u < m) alpha[sidx[t0 + u]] = 1.0 / acc[u];
+      if (t0 + u < cend) alpha[sidx[t0 + u]] = wscale<2>() / acc[u];
   }
 }
 
@@ -208,8 +256,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights(const WSample<DIM>* 
 // one wavefront per sample, lanes splitting its candidate ranges (the lists
 // are short, so one thread per sample would leave the GPU idle)
 template <int DIM>
-__global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const double* __restrict__ k,
-                                                               const double* __restrict__ sc_orig,
+__global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const int32_t* __restrict__ inv,
                                                                const int32_t* __restrict__ idx, int64_t n,
                                                                const WSample<DIM>* __restrict__ ss,
                                                                const int32_t* __restrict__ boff, WBinGeom g,
@@ -217,12 +264,12 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const double* __r
   const int64_t w = ((int64_t)blockIdx.x * WB_BLOCK + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (w >= n) return;   // whole wavefront
-  const int64_t j = idx[w];
+  const WSample<DIM> me = ss[inv[idx[w]]];
   double x[DIM], sn[DIM], cs[DIM];
   for (int a = 0; a < DIM; ++a) {
-    x[a] = k[j * DIM + a];
-    sn[a] = sc_orig[j * 2 * DIM + 2 * a];
-    cs[a] = sc_orig[j * 2 * DIM + 2 * a + 1];
+    x[a] = me.k[a];
+    sn[a] = me.sc[a][0];
+    cs[a] = me.sc[a][1];
   }
   int b[DIM];
   wbin_of<DIM>(x, g, b);
@@ -237,14 +284,14 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const double* __r
     for (int i = beg + lane; i < end; i += 64) acc += pair_term<DIM>(ss[i], x, sn, cs, g.R);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) out[w] = 1.0 / acc;
+  if (lane == 0) out[w] = wscale<DIM>() / acc;
 }
 
 // Bin edge h = R / span with span in [2, 16] chosen for about BIN_TARGET
 // samples per bin at the raster's mean density over its bounding box, so the
 // 2 span + 1 bins of a row range end at the box of radius R (finer bins waste
 // fewer out-of-box candidates); at most 4096 bins per axis in 2D (4M in 1D).
-constexpr double BIN_TARGET = 6.0;
+constexpr double BIN_TARGET = 3.0;
 static WBinGeom wbin_geom(ftcg_plan p, const double* kmin, const double* kmax) {
   WBinGeom g{};
   g.R = p->R;
@@ -277,18 +324,19 @@ void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const d
   const int dim = p->dim;
   const int64_t nbins = (int64_t)g.nb[0] * g.nb[1];
   hipStream_t s = p->stream;
-  p->wb_cnt.ensure(sizeof(int32_t) * (nbins + 1));
+  const size_t cnt_bytes = sizeof(int32_t) * ((nbins + 4) & ~int64_t(3));  // 16-byte multiple: one fill
+  p->wb_cnt.ensure(cnt_bytes);
   p->wb_off.ensure(sizeof(int32_t) * (nbins + 1));
   p->wb_of.ensure(sizeof(int32_t) * m);
   p->ws_k.ensure(sizeof(double) * m * dim * 3);
   p->ws_idx.ensure(sizeof(int32_t) * m);
-  p->sc_orig.ensure(sizeof(double) * m * dim * 2);
+  p->ws_inv.ensure(sizeof(int32_t) * m);
   p->scan_tmp.ensure(scan_tmp_bytes(nbins));
   int32_t* cnt = p->wb_cnt.as<int32_t>();
   int32_t* off = p->wb_off.as<int32_t>();
   const unsigned nb = (unsigned)((m + WB_BLOCK - 1) / WB_BLOCK);
   timing_begin(p, STEP_WBIN);
-  FTCG_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (nbins + 1), s));
+  FTCG_HIP(hipMemsetAsync(cnt, 0, cnt_bytes, s));
   if (dim == 1)
     hipLaunchKernelGGL(k_wbin_count<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, cnt, p->wb_of.as<int32_t>());
   else
@@ -296,55 +344,55 @@ void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const d
   exclusive_scan_i32(cnt, off, nbins, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
   if (dim == 1)
     hipLaunchKernelGGL(k_wbin_scatter<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
-                       p->ws_k.as<WSample<1>>(), p->ws_idx.as<int32_t>(), p->sc_orig.as<double>());
+                       p->ws_k.as<WSample<1>>(), p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>());
   else
     hipLaunchKernelGGL(k_wbin_scatter<2>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
-                       p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), p->sc_orig.as<double>());
+                       p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>());
   FTCG_HIP(hipGetLastError());
   timing_end(p, STEP_WBIN);
   p->have_wbins = true;
 }
 
-// Launch shape: WT samples per lane group and S lanes per group, from the
-// plan's tuning when set, else S = 1 and WT = 2 from 2^19 samples up (where
-// sharing candidate loads pays) and WT = 1 below (where the GPU is short of
-// wavefronts and longer per-lane chains cost more than they save).
-template <int DIM, int WT, int S>
-static void launch_weights(ftcg_plan p) {
-  const int64_t groups = (p->m + WT - 1) / WT;
-  const unsigned nb = (unsigned)((groups * S + WB_BLOCK - 1) / WB_BLOCK);
-  hipLaunchKernelGGL((k_frame_weights<DIM, WT, S>), dim3(nb), dim3(WB_BLOCK), 0, p->stream,
-                     p->ws_k.as<WSample<DIM>>(), p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), p->m, p->wgeom,
+template <int WT>
+static void launch_weights_rows(ftcg_plan p) {
+  const WBinGeom& g = p->wgeom;
+  const int64_t runs = (p->m + WB_BLOCK * WT - 1) / (WB_BLOCK * WT);
+  // x extent: twice the mean runs per bin row, so dense rows are covered in
+  // about one step while empty rows cost only idle workgroups
+  const int cx = (int)std::max<int64_t>(1, (2 * runs + g.nb[0] - 1) / g.nb[0]);
+  const int64_t nb = (int64_t)cx * g.nb[0];
+  hipLaunchKernelGGL((k_frame_weights_rows<WT>), dim3((unsigned)nb), dim3(WB_BLOCK), 0, p->stream,
+                     p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), g, cx,
                      p->alpha.as<double>());
 }
 
-template <int DIM, int WT>
-static void launch_weights_s(ftcg_plan p, int S) {
-  switch (S) {
-    case 1: launch_weights<DIM, WT, 1>(p); break;
-    case 2: launch_weights<DIM, WT, 2>(p); break;
-    case 4: launch_weights<DIM, WT, 4>(p); break;
-    default: launch_weights<DIM, WT, 8>(p); break;
-  }
+template <int WT>
+static void launch_weights_1d(ftcg_plan p) {
+  const int64_t groups = (p->m + WT - 1) / WT;
+  const unsigned nb = (unsigned)((groups + WB_BLOCK - 1) / WB_BLOCK);
+  hipLaunchKernelGGL((k_frame_weights_1d<WT>), dim3(nb), dim3(WB_BLOCK), 0, p->stream, p->ws_k.as<WSample<1>>(),
+                     p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), p->m, p->wgeom, p->alpha.as<double>());
 }
 
-template <int DIM>
-static void launch_weights_dim(ftcg_plan p) {
-  const int wt = p->w_samples ? p->w_samples : (p->m >= (int64_t(1) << 19) ? 2 : 1);
-  const int S = p->w_lanes ? p->w_lanes : 1;
-  switch (wt) {
-    case 1: launch_weights_s<DIM, 1>(p, S); break;
-    case 2: launch_weights_s<DIM, 2>(p, S); break;
-    default: launch_weights_s<DIM, 4>(p, S); break;
-  }
-}
-
+// samples per lane: the plan's tuning, else 1 (the staged 2D kernel is bound
+// by its float64 arithmetic, and one sample per lane keeps the most
+// wavefronts resident)
 void run_plain_weights(ftcg_plan p) {
   timing_begin(p, STEP_WEIGHTS);
-  if (p->dim == 1)
-    launch_weights_dim<1>(p);
-  else
-    launch_weights_dim<2>(p);
+  const int wt = p->w_samples ? p->w_samples : 1;
+  if (p->dim == 2) {
+    switch (wt) {
+      case 1: launch_weights_rows<1>(p); break;
+      case 2: launch_weights_rows<2>(p); break;
+      default: launch_weights_rows<4>(p); break;
+    }
+  } else {
+    switch (wt) {
+      case 1: launch_weights_1d<1>(p); break;
+      case 2: launch_weights_1d<2>(p); break;
+      default: launch_weights_1d<4>(p); break;
+    }
+  }
   FTCG_HIP(hipGetLastError());
   timing_end(p, STEP_WEIGHTS);
 }
@@ -354,10 +402,10 @@ void plain_weights_at(ftcg_plan p, const double* k, const int32_t* idx, int64_t 
   const unsigned nb = (unsigned)((n * 64 + WB_BLOCK - 1) / WB_BLOCK);
   const int32_t* off = p->wb_off.as<int32_t>();
   if (p->dim == 1)
-    hipLaunchKernelGGL(k_frame_weights_at<1>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, k, p->sc_orig.as<double>(),
+    hipLaunchKernelGGL(k_frame_weights_at<1>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, p->ws_inv.as<int32_t>(),
                        idx, n, p->ws_k.as<WSample<1>>(), off, p->wgeom, out);
   else
-    hipLaunchKernelGGL(k_frame_weights_at<2>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, k, p->sc_orig.as<double>(),
+    hipLaunchKernelGGL(k_frame_weights_at<2>, dim3(nb), dim3(WB_BLOCK), 0, p->stream, p->ws_inv.as<int32_t>(),
                        idx, n, p->ws_k.as<WSample<2>>(), off, p->wgeom, out);
   FTCG_HIP(hipGetLastError());
 }

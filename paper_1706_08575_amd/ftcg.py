@@ -128,10 +128,10 @@ class Plan:
         a = {"fixed": L.FTCG_ACCUM_FIXED, "f64": L.FTCG_ACCUM_F64}[accum]
         L.check(L.call("ftcg_plan_set_tuning", self._h, int(tile), a, int(lds_copies)), "ftcg_plan_set_tuning")
 
-    def set_weight_tuning(self, samples_per_group: int = 0, lanes_per_group: int = 0) -> None:
-        """Launch shape of the frame-weight kernel (0 = automatic); applies
-        from the next set_points."""
-        L.check(L.call("ftcg_plan_set_weight_tuning", self._h, int(samples_per_group), int(lanes_per_group)),
+    def set_weight_tuning(self, samples_per_lane: int = 0) -> None:
+        """Samples per lane of the frame-weight kernel (0 = automatic); applies
+        from the next weight computation."""
+        L.check(L.call("ftcg_plan_set_weight_tuning", self._h, int(samples_per_lane)),
                 "ftcg_plan_set_weight_tuning")
 
     def set_mlp(self, mlp, audit_threshold: float = 1e-4, audit_samples: int = 4096) -> None:

@@ -224,6 +224,27 @@ def test_weights_none_and_lattice():
     assert O.rel_l2(img, img1) < 1e-13
 
 
+def test_weights_shared_coordinates_and_duplicates():
+    # tensor raster of jittered axes: most pairs share one coordinate exactly
+    # (sinc factor exactly 1 on that axis); 20 points repeated bit for bit
+    rng = np.random.default_rng(12)
+    xa = np.sort(rng.uniform(-20.0, 20.0, 40))
+    ya = np.sort(rng.uniform(-20.0, 20.0, 40))
+    x0, x1 = np.meshgrid(xa, ya, indexing="ij")
+    k = np.stack([x0.ravel(), x1.ravel()], axis=1)
+    k = np.concatenate([k, k[rng.choice(k.shape[0], 20, replace=False)]])
+    f = S.random_values(13, k.shape[0])
+    _, a, _ = run(k, f, 64, "f64")
+    a_ref = O.frame_weights(k, 8.0)
+    assert np.max(np.abs(a - a_ref) / a_ref) < 1e-10
+    # the same in 1D, with repeated values
+    k1 = np.concatenate([xa, xa[:7]])[:, None]
+    f1 = S.random_values(14, k1.shape[0])
+    _, a1, _ = run(k1, f1, 64, "f64")
+    a1_ref = O.frame_weights(k1, 8.0)
+    assert np.max(np.abs(a1 - a1_ref) / a1_ref) < 1e-10
+
+
 def test_nonfinite_points_rejected():
     from paper_1706_08575_amd import _lib as L
     from paper_1706_08575_amd.ftcg import Plan
