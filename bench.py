@@ -31,8 +31,11 @@ if ROOT not in sys.path:
 METRIC = "Msamples/s gridded + images/s at rel L2 <=1e-4 vs FP64 oracle (plain vs batched/learned)"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-# float64 operations per in-box neighbour pair of the weight sum, per axis:
-# difference, sin-difference (mul + fma), pi*d; then num/den, square, add
+# float64 operations per in-box neighbour pair of the weight sum (eq:difopt
+# with the Gram entries as sinc products), per axis: the difference (1),
+# sin(pi d) by the product formula (2 multiplies + 1 subtraction), pi d (1);
+# then per pair: product of the axis numerators and of the denominators in 2D
+# (2), the division (1), the square (1) and the accumulation (1)
 FLOPS_PER_PAIR = {1: 1 * 5 + 3, 2: 2 * 5 + 5}
 
 WORKLOADS = {
@@ -80,6 +83,35 @@ def step_bytes(step, m, nrec, n, G, dim, dtype):
         # read k twice (count, scatter), bin id written and read, write the
         # bin-ordered sample (k, sin, cos), its index and the caller-order sin/cos
         return m * (2 * 8 * dim + 4 + 4 + 24 * dim + 4 + 16 * dim)
+    return None
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    table (profiles/pmc_traffic.md), or None when there is no row for it or the
+    kernel's sources changed since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "pmc_traffic.md")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) != 8 or cells[0] != kernel or cells[2] != workload:
+            continue
+        h = hashlib.sha256()
+        try:
+            for f in cells[7].split():
+                with open(os.path.join(here, f), "rb") as fh:
+                    h.update(fh.read())
+        except OSError:
+            return None
+        if h.hexdigest()[:16] != cells[6]:
+            return None
+        return {"bytes": float(cells[5]), "fetch_kib": float(cells[3]), "write_kib": float(cells[4]),
+                "source": "profiles/pmc_traffic.md"}
     return None
 
 
@@ -361,9 +393,12 @@ def main():
         pairs = count_box_pairs(k, 8.0, sample=None if m <= 200_000 else 20000)
         flops = pairs * FLOPS_PER_PAIR[dim]
         ach = flops / (stage_ms[dom] * 1e-3) / 1e12
-        roof = {"kernel": "k_frame_weights", "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
-                "work_per_launch": f"{pairs} in-box pairs x {FLOPS_PER_PAIR[dim]} FP64 flops"}
+        kname = "k_frame_weights_rows<1>" if dim == 2 else "k_frame_weights_1d<1>"
+        tr = measured_traffic(kname, args.workload)
+        roof = {"kernel": kname, "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": tr["bytes"] if tr else None,
+                "work_per_launch": f"{pairs} in-box pairs x {FLOPS_PER_PAIR[dim]} FP64 flops",
+                "algorithmic_bytes_per_launch": m * (48 + 4 + 8)}
     else:
         b = step_bytes(dom, m, info["n_records"], n, G, dim, dtype)
         ach = b / (stage_ms[dom] * 1e-3) / 1e9
