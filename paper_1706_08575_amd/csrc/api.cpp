@@ -168,7 +168,7 @@ ftcg_status ftcg_plan_destroy(ftcg_plan p) {
   if (!p) return FTCG_EINVAL;
   (void)hipStreamSynchronize(p->stream);
   DevBuf* bufs[] = {&p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp,
-                    &p->flags,  &p->wb_cnt, &p->wb_off, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->ws_inv, &p->audit_buf,
+                    &p->flags,  &p->wb_cnt, &p->wb_off, &p->wb_rowoff, &p->wb_rowbuf, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->ws_inv, &p->audit_buf,
                     &p->grid,   &p->fft_tmp, &p->deapod, &p->tile_order};
   for (DevBuf* b : bufs) b->release();
   for (auto& pr : p->timing.pending) {
@@ -200,8 +200,15 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
       zero_ptr = p->tile_cnt.as<int32_t>();
       zero_n = p->ntiles + 1;
     }
+    int32_t* zero_b = nullptr;
+    int64_t zero_nb = 0;
+    if (p->dim == 2 && (p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED)) {
+      p->wb_cnt.ensure(sizeof(int32_t) * WROW_CNT_ZERO);
+      zero_b = p->wb_cnt.as<int32_t>();
+      zero_nb = WROW_CNT_ZERO;
+    }
     auto* part = reinterpret_cast<unsigned long long*>(static_cast<char*>(p->flags.p) + FLAGS_PART_OFF);
-    const int nparts = launch_check_points(p, k_dev, m, part, zero_ptr, zero_n);
+    const int nparts = launch_check_points(p, k_dev, m, part, zero_ptr, zero_n, zero_b, zero_nb);
     auto* hpart = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(p->host_flags) + FLAGS_PART_OFF);
     FTCG_HIP(hipMemcpyAsync(hpart, part, sizeof(unsigned long long) * 5 * nparts, hipMemcpyDeviceToHost,
                             p->stream));

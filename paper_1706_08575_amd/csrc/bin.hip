@@ -29,16 +29,18 @@ __device__ inline unsigned long long ordered_bits(double x) {
 // reduces its points with wavefront shuffles and LDS and writes five words to
 // part[5 b ..]: a non-finite flag, then the per-axis minimum and maximum as
 // order-preserving integers; the host reduces the partials (no atomics, no
-// initialisation pass). The same launch zeroes zero_ptr[0 .. zero_n), the
-// tile counters of the binning that follows.
+// initialisation pass). The same launch zeroes zero_a[0 .. zero_na) and
+// zero_b[0 .. zero_nb), the counters of the binnings that follow.
 constexpr int CHECK_BLOCKS = 256;
 __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __restrict__ k, int64_t m, int dim,
                                                             unsigned long long* __restrict__ part,
-                                                            int32_t* __restrict__ zero_ptr, int64_t zero_n) {
+                                                            int32_t* __restrict__ zero_a, int64_t zero_na,
+                                                            int32_t* __restrict__ zero_b, int64_t zero_nb) {
   __shared__ unsigned long long sred[4][BIN_BLOCK / 64];
   __shared__ int sbad;
   const int64_t gt = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x, gs = (int64_t)gridDim.x * BIN_BLOCK;
-  for (int64_t i = gt; i < zero_n; i += gs) zero_ptr[i] = 0;
+  for (int64_t i = gt; i < zero_na; i += gs) zero_a[i] = 0;
+  for (int64_t i = gt; i < zero_nb; i += gs) zero_b[i] = 0;
   if (threadIdx.x == 0) sbad = 0;
   unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
   bool bad = false;
@@ -89,13 +91,13 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __rest
   }
 }
 
-int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long long* part, int32_t* zero_ptr,
-                        int64_t zero_n) {
+int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long long* part, int32_t* zero_a,
+                        int64_t zero_na, int32_t* zero_b, int64_t zero_nb) {
   int64_t nb = (m + 8 * BIN_BLOCK - 1) / (8 * BIN_BLOCK);  // 8 points per thread at least
   if (nb > CHECK_BLOCKS) nb = CHECK_BLOCKS;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_check_points, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream, k, m, p->dim, part,
-                     zero_ptr, zero_n);
+                     zero_a, zero_na, zero_b, zero_nb);
   FTCG_HIP(hipGetLastError());
   return (int)nb;
 }

@@ -201,7 +201,8 @@ struct ftcg_plan_s {
   ftcg::DevBuf flags;        // small device scratch: [6] audit estimate; bytes 128.. input-check partials
 
   // weight binning
-  ftcg::DevBuf wb_cnt, wb_off;
+  ftcg::DevBuf wb_cnt, wb_off;  // 2D: wb_cnt holds the bin-row counters (WROW_CNT_ZERO entries)
+  ftcg::DevBuf wb_rowoff, wb_rowbuf;  // 2D: bin-row offsets, sample indices grouped by row
   ftcg::DevBuf ws_k;         // sorted samples: k, sin(pi k), cos(pi k) (3*dim doubles each)
   ftcg::DevBuf ws_idx;       // sorted original index
   ftcg::DevBuf wb_of;        // weight-bin id per sample (caller order)
@@ -231,10 +232,11 @@ namespace ftcg {
 
 // launchers (defined in the .hip files); all enqueue on plan->stream
 constexpr size_t FLAGS_BYTES = 16384;     // device flags / pinned host mirror
+constexpr int64_t WROW_CNT_ZERO = 4100;   // bin-row counters cleared by the input check (>= 4096 + 1)
 constexpr size_t FLAGS_PART_OFF = 128;    // byte offset of the input-check partials
 // returns the number of partial records (5 words each) written to part
-int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long long* part, int32_t* zero_ptr,
-                        int64_t zero_n);
+int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long long* part, int32_t* zero_a,
+                        int64_t zero_na, int32_t* zero_b, int64_t zero_nb);
 void bin_points_k(ftcg_plan p, const double* k);   // fills recs, alpha_s, tile_off
 void refill_alpha(ftcg_plan p);                     // alpha_s[r] = alpha[recs[r].src]
 void build_weight_bins(ftcg_plan p, const double* k, const double* kmin,

@@ -317,6 +317,144 @@ static WBinGeom wbin_geom(ftcg_plan p, const double* kmin, const double* kmax) {
   return g;
 }
 
+// 2D neighbour binning in two levels, so no pass spreads atomics over all
+// nb0 x nb1 bins (they outgrow the L2 on large rasters):
+//  1. k_wrow_count: bin id of every sample (kept in bin_of), counts per bin
+//     row b0 in LDS, one global atomic per row a workgroup saw;
+//  2. exclusive scan over the <= 4096 rows (row_off; the counters become
+//     cursors);
+//  3. k_wrow_scatter: each workgroup claims one range per row and places its
+//     samples' indices there (rowbuf, grouped by row);
+//  4. k_wrow_sort: one workgroup per row counts its samples per bin b1 in LDS,
+//     scans them, writes the bin offsets boff of the whole row and places the
+//     sorted samples (k, sin, cos), their caller index and the inverse map;
+//     every write of this pass stays inside the row's own range.
+// The row counters arrive zeroed (the input check clears them).
+constexpr int WROW_IPT = 4;
+
+__device__ inline int wbin_row_col(const double* __restrict__ k, int64_t j, const WBinGeom& g, int* b1) {
+  double x[2] = {k[2 * j], k[2 * j + 1]};
+  int b[2];
+  wbin_of<2>(x, g, b);
+  *b1 = b[1];
+  return b[0];
+}
+
+__global__ __launch_bounds__(WB_BLOCK) void k_wrow_count(const double* __restrict__ k, int64_t m, WBinGeom g,
+                                                         int32_t* __restrict__ row_cnt,
+                                                         int32_t* __restrict__ bin_of) {
+  __shared__ int32_t hist[4096];
+  const int nrow = g.nb[0];
+  for (int i = threadIdx.x; i < nrow; i += WB_BLOCK) hist[i] = 0;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * WROW_IPT * WB_BLOCK;
+#pragma unroll
+  for (int u = 0; u < WROW_IPT; ++u) {
+    const int64_t j = j0 + (int64_t)u * WB_BLOCK + threadIdx.x;
+    if (j < m) {
+      int b1;
+      const int b0 = wbin_row_col(k, j, g, &b1);
+      bin_of[j] = b0 * g.nb[1] + b1;
+      atomicAdd(&hist[b0], 1);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nrow; i += WB_BLOCK) {
+    const int v = hist[i];
+    if (v) atomicAdd(&row_cnt[i], v);
+  }
+}
+
+__global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(int64_t m, WBinGeom g, const int32_t* __restrict__ bin_of,
+                                                           int32_t* __restrict__ row_cursor,
+                                                           int32_t* __restrict__ rowbuf) {
+  __shared__ int32_t base[4096];
+  const int nrow = g.nb[0], nb1 = g.nb[1];
+  for (int i = threadIdx.x; i < nrow; i += WB_BLOCK) base[i] = 0;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * WROW_IPT * WB_BLOCK;
+  int row[WROW_IPT];
+#pragma unroll
+  for (int u = 0; u < WROW_IPT; ++u) {
+    const int64_t j = j0 + (int64_t)u * WB_BLOCK + threadIdx.x;
+    row[u] = j < m ? bin_of[j] / nb1 : -1;
+    if (row[u] >= 0) atomicAdd(&base[row[u]], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nrow; i += WB_BLOCK) {
+    const int v = base[i];
+    if (v) base[i] = atomicAdd(&row_cursor[i], v);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < WROW_IPT; ++u) {
+    const int64_t j = j0 + (int64_t)u * WB_BLOCK + threadIdx.x;
+    if (row[u] >= 0) rowbuf[atomicAdd(&base[row[u]], 1)] = (int32_t)j;
+  }
+}
+
+__global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(const double* __restrict__ k, WBinGeom g,
+                                                        const int32_t* __restrict__ row_off,
+                                                        const int32_t* __restrict__ rowbuf,
+                                                        const int32_t* __restrict__ bin_of,
+                                                        int32_t* __restrict__ boff, WSample<2>* __restrict__ ss,
+                                                        int32_t* __restrict__ sidx, int32_t* __restrict__ inv) {
+  constexpr int ITEMS = 4096 / WB_BLOCK;
+  __shared__ int32_t cnt[4096];
+  __shared__ int32_t wsum[WB_BLOCK / 64];
+  const int b0 = blockIdx.x, nb1 = g.nb[1];
+  const int rs = row_off[b0], re = row_off[b0 + 1];
+  const int t = threadIdx.x;
+  for (int i = t; i < nb1; i += WB_BLOCK) cnt[i] = 0;
+  __syncthreads();
+  for (int i = rs + t; i < re; i += WB_BLOCK) atomicAdd(&cnt[bin_of[rowbuf[i]] - b0 * nb1], 1);
+  __syncthreads();
+  // exclusive scan of cnt[0 .. nb1): thread t owns entries t*ITEMS .. +ITEMS-1
+  int v[ITEMS];
+  int sum = 0;
+#pragma unroll
+  for (int q = 0; q < ITEMS; ++q) {
+    const int e = t * ITEMS + q;
+    v[q] = e < nb1 ? cnt[e] : 0;
+    sum += v[q];
+  }
+  int incl = sum;
+  const int lane = t & 63, w = t >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int run = incl - sum;
+  for (int q = 0; q < w; ++q) run += wsum[q];
+  run += rs;
+#pragma unroll
+  for (int q = 0; q < ITEMS; ++q) {
+    const int e = t * ITEMS + q;
+    if (e < nb1) {
+      cnt[e] = run;
+      boff[b0 * nb1 + e] = run;
+    }
+    run += v[q];
+  }
+  if (b0 == g.nb[0] - 1 && t == 0) boff[g.nb[0] * nb1] = re;
+  __syncthreads();
+  for (int i = rs + t; i < re; i += WB_BLOCK) {
+    const int j = rowbuf[i];
+    const int pos = atomicAdd(&cnt[bin_of[j] - b0 * nb1], 1);
+    WSample<2> s;
+    for (int a = 0; a < 2; ++a) {
+      s.k[a] = k[2 * (int64_t)j + a];
+      sincospi(s.k[a], &s.sc[a][0], &s.sc[a][1]);
+    }
+    ss[pos] = s;
+    sidx[pos] = j;
+    inv[j] = pos;
+  }
+}
+
 void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const double* kmax) {
   const WBinGeom g = wbin_geom(p, kmin, kmax);
   p->wgeom = g;
@@ -324,30 +462,40 @@ void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const d
   const int dim = p->dim;
   const int64_t nbins = (int64_t)g.nb[0] * g.nb[1];
   hipStream_t s = p->stream;
-  const size_t cnt_bytes = sizeof(int32_t) * ((nbins + 4) & ~int64_t(3));  // 16-byte multiple: one fill
-  p->wb_cnt.ensure(cnt_bytes);
   p->wb_off.ensure(sizeof(int32_t) * (nbins + 1));
   p->wb_of.ensure(sizeof(int32_t) * m);
   p->ws_k.ensure(sizeof(double) * m * dim * 3);
   p->ws_idx.ensure(sizeof(int32_t) * m);
   p->ws_inv.ensure(sizeof(int32_t) * m);
-  p->scan_tmp.ensure(scan_tmp_bytes(nbins));
-  int32_t* cnt = p->wb_cnt.as<int32_t>();
   int32_t* off = p->wb_off.as<int32_t>();
-  const unsigned nb = (unsigned)((m + WB_BLOCK - 1) / WB_BLOCK);
   timing_begin(p, STEP_WBIN);
-  FTCG_HIP(hipMemsetAsync(cnt, 0, cnt_bytes, s));
-  if (dim == 1)
+  if (dim == 2) {
+    // row counters: zeroed by the input check (WROW_CNT_ZERO entries)
+    int32_t* row_cnt = p->wb_cnt.as<int32_t>();
+    p->wb_rowoff.ensure(sizeof(int32_t) * (g.nb[0] + 1));
+    p->wb_rowbuf.ensure(sizeof(int32_t) * m);
+    p->scan_tmp.ensure(scan_tmp_bytes(g.nb[0]));
+    int32_t* row_off = p->wb_rowoff.as<int32_t>();
+    const unsigned nb = (unsigned)((m + WROW_IPT * WB_BLOCK - 1) / (WROW_IPT * WB_BLOCK));
+    hipLaunchKernelGGL(k_wrow_count, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, row_cnt, p->wb_of.as<int32_t>());
+    exclusive_scan_i32(row_cnt, row_off, g.nb[0], p->scan_tmp.as<int32_t>(), s, row_cnt);
+    hipLaunchKernelGGL(k_wrow_scatter, dim3(nb), dim3(WB_BLOCK), 0, s, m, g, p->wb_of.as<int32_t>(), row_cnt,
+                       p->wb_rowbuf.as<int32_t>());
+    hipLaunchKernelGGL(k_wrow_sort, dim3((unsigned)g.nb[0]), dim3(WB_BLOCK), 0, s, k, g, row_off,
+                       p->wb_rowbuf.as<int32_t>(), p->wb_of.as<int32_t>(), off, p->ws_k.as<WSample<2>>(),
+                       p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>());
+  } else {
+    const size_t cnt_bytes = sizeof(int32_t) * ((nbins + 4) & ~int64_t(3));  // 16-byte multiple: one fill
+    p->wb_cnt.ensure(cnt_bytes);
+    p->scan_tmp.ensure(scan_tmp_bytes(nbins));
+    int32_t* cnt = p->wb_cnt.as<int32_t>();
+    const unsigned nb = (unsigned)((m + WB_BLOCK - 1) / WB_BLOCK);
+    FTCG_HIP(hipMemsetAsync(cnt, 0, cnt_bytes, s));
     hipLaunchKernelGGL(k_wbin_count<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, cnt, p->wb_of.as<int32_t>());
-  else
-    hipLaunchKernelGGL(k_wbin_count<2>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, cnt, p->wb_of.as<int32_t>());
-  exclusive_scan_i32(cnt, off, nbins, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
-  if (dim == 1)
+    exclusive_scan_i32(cnt, off, nbins, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
     hipLaunchKernelGGL(k_wbin_scatter<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
                        p->ws_k.as<WSample<1>>(), p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>());
-  else
-    hipLaunchKernelGGL(k_wbin_scatter<2>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
-                       p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>());
+  }
   FTCG_HIP(hipGetLastError());
   timing_end(p, STEP_WBIN);
   p->have_wbins = true;
