@@ -302,7 +302,7 @@ def main():
     ap.add_argument("--workload", default="sas512_plain", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--accum", default=None, choices=["fixed", "f64"])
+    ap.add_argument("--accum", default=None, choices=["fixed", "f64", "mfma"])
     ap.add_argument("--copies", type=int, default=1)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and learned forms")
     ap.add_argument("--copy-calibration", action="store_true",

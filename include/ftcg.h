@@ -138,24 +138,34 @@ ftcg_status ftcg_plan_info(ftcg_plan plan, int64_t* grid_size, int64_t* n_record
  *   FTCG_ACCUM_F64   : taps accumulated with float64 LDS atomics (the default
  *                      and only mode of float64 plans); lds_copies > 1 gives
  *                      each wavefront its own partial tile, combined at the
- *                      flush with compensated (TwoSum) addition. */
-typedef enum { FTCG_ACCUM_FIXED = 0, FTCG_ACCUM_F64 = 1 } ftcg_accum;
+ *                      flush with compensated (TwoSum) addition.
+ *   FTCG_ACCUM_MFMA  : 2D float32 plans, tile 64 only. Every 16 x 16 block of
+ *                      a tile is the sum over its records of (row taps x value)
+ *                      times (column taps), formed four records at a time on
+ *                      the float32 matrix cores with float32 accumulation in
+ *                      registers (no LDS tile, no atomics). */
+typedef enum { FTCG_ACCUM_FIXED = 0, FTCG_ACCUM_F64 = 1, FTCG_ACCUM_MFMA = 2 } ftcg_accum;
 
 /* Tuning knobs (take effect at the next ftcg_set_points; the points must be
  * set again):
  *   tile       : tile edge in grid cells (16, 32, 64, 128; 0 = automatic);
  *                FTCG_ACCUM_F64 supports tile <= 64 and
  *                lds_copies * 16 * tile * (tile + 1) <= 160 KiB.
- *   accum      : ftcg_accum (FTCG_ACCUM_FIXED needs a float32 plan).
+ *   accum      : ftcg_accum (FTCG_ACCUM_FIXED needs a float32 plan,
+ *                FTCG_ACCUM_MFMA a 2D float32 plan with tile 64 and G >= 64).
  *   lds_copies : 1, 2 or 4 (FTCG_ACCUM_F64 only; must be 1 otherwise).
  * Returns FTCG_EUNSUPPORTED for combinations that do not fit LDS. */
 ftcg_status ftcg_plan_set_tuning(ftcg_plan plan, int tile, int accum, int lds_copies);
 
 /* Launch shape of the frame-weight sum (Sec. III-C, eq:difopt), taking effect
- * at the next weight computation: samples_per_lane = 1, 2 or 4 consecutive
- * bin-sorted samples share each lane's candidate loads (0 = automatic: 1).
+ * at the next weight computation:
+ *   samples_per_lane : 1, 2 or 4 consecutive bin-sorted samples share each
+ *                      lane's candidate reads (0 = automatic: 1);
+ *   lanes_per_group  : 1, 2 or 4 lanes split every candidate range of a group
+ *                      of samples and add their partial sums (2D only;
+ *                      0 = automatic: 4 below 2^21 samples, else 2).
  * Results agree to rounding for every shape. FTCG_EINVAL for other values. */
-ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan plan, int samples_per_lane);
+ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan plan, int samples_per_lane, int lanes_per_group);
 
 /* Per-step timing with HIP events on the plan's stream.
  * enable != 0 records events around every step of later calls; ftcg_plan_timing

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libftcg.so")
 FTCG_OK, FTCG_EINVAL, FTCG_ENOMEM, FTCG_EHIP, FTCG_ESTATE, FTCG_EUNSUPPORTED = range(6)
 FTCG_F64, FTCG_F32 = 0, 1
 FTCG_W_PLAIN, FTCG_W_LEARNED, FTCG_W_USER, FTCG_W_NONE = range(4)
-FTCG_ACCUM_FIXED, FTCG_ACCUM_F64 = 0, 1
+FTCG_ACCUM_FIXED, FTCG_ACCUM_F64, FTCG_ACCUM_MFMA = 0, 1, 2
 
 STEP_NAMES = ("bin", "weights", "spread", "fft1", "fft2_deapod", "weight_bin", "learned", "audit")
 
@@ -44,7 +44,7 @@ _SIGS = [
     ("ftcg_plan_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int)]),
     ("ftcg_plan_set_tuning", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
-    ("ftcg_plan_set_weight_tuning", C.c_int, [C.c_void_p, C.c_int]),
+    ("ftcg_plan_set_weight_tuning", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     ("ftcg_plan_enable_timing", C.c_int, [C.c_void_p, C.c_int]),
     ("ftcg_plan_timing", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     ("ftcg_mlp_create", C.c_int, [C.POINTER(C.c_void_p), C.c_void_p]),

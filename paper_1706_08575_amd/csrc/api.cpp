@@ -355,11 +355,13 @@ ftcg_status ftcg_plan_info(ftcg_plan p, int64_t* grid_size, int64_t* n_records, 
   });
 }
 
-ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan p, int samples_per_lane) {
+ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan p, int samples_per_lane, int lanes_per_group) {
   if (!p) return FTCG_EINVAL;
-  const int w = samples_per_lane;
+  const int w = samples_per_lane, l = lanes_per_group;
   if (!(w == 0 || w == 1 || w == 2 || w == 4)) return FTCG_EINVAL;
+  if (!(l == 0 || l == 1 || l == 2 || l == 4)) return FTCG_EINVAL;
   p->w_samples = w;
+  p->w_lanes = l;
   return FTCG_OK;
 }
 
@@ -368,9 +370,12 @@ ftcg_status ftcg_plan_set_tuning(ftcg_plan p, int tile, int accum, int lds_copie
   if (tile != 0 && tile != 16 && tile != 32 && tile != 64 && tile != 128 && !(p->dim == 1 && is_pow2(tile)))
     return FTCG_EINVAL;
   if (tile != 0 && tile < 2 * p->W) return FTCG_EINVAL;
-  if (accum != FTCG_ACCUM_FIXED && accum != FTCG_ACCUM_F64) return FTCG_EINVAL;
+  if (accum != FTCG_ACCUM_FIXED && accum != FTCG_ACCUM_F64 && accum != FTCG_ACCUM_MFMA) return FTCG_EINVAL;
   if (lds_copies != 1 && lds_copies != 2 && lds_copies != 4) return FTCG_EINVAL;
   if (accum == FTCG_ACCUM_FIXED && (p->dtype != FTCG_F32 || lds_copies != 1)) return FTCG_EUNSUPPORTED;
+  if (accum == FTCG_ACCUM_MFMA &&
+      (p->dtype != FTCG_F32 || p->dim != 2 || lds_copies != 1 || (tile != 0 && tile != 64) || p->G < 64))
+    return FTCG_EUNSUPPORTED;
   if (accum == FTCG_ACCUM_F64 && p->dim == 2) {
     const int64_t t = tile ? tile : 64;
     if (t > 64 || (size_t)lds_copies * 2 * t * (t + 1) * sizeof(double) > 160 * 1024) return FTCG_EUNSUPPORTED;

@@ -91,7 +91,7 @@ struct WSample {
 };
 
 // tile accumulation of float32 plans
-enum Accum { ACCUM_FIXED = 0, ACCUM_F64 = 1 };
+enum Accum { ACCUM_FIXED = 0, ACCUM_F64 = 1, ACCUM_MFMA = 2 };
 
 enum Step {
   STEP_BIN = 0,      // input check + tile binning of spread records
@@ -179,6 +179,7 @@ struct ftcg_plan_s {
   double beta = 0.0;   // kernel exp(-beta s^2)
   int tile_req = 0;    // requested tile edge (0 = automatic)
   int w_samples = 0;   // frame-weight kernel: samples per lane (0 = automatic)
+  int w_lanes = 0;     // frame-weight kernel (2D): lanes per sample group (0 = automatic)
   int lds_copies = 1;
   int accum = 0;       // ftcg::Accum for float32 plans (float64 plans always use ACCUM_F64)
 

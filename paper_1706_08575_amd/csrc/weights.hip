@@ -174,30 +174,35 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_1d(const WSample<1>*
     if (t0 + u < m) alpha[sidx[t0 + u]] = wscale<1>() / acc[u];
 }
 
-// 2D: one workgroup per (bin row b0, run of WB_BLOCK * WT consecutive
+// 2D: one workgroup per (bin row b0, run of WB_BLOCK * WT / S consecutive
 // samples of that row), so a workgroup's samples share their row window and
 // their column window is lo1 .. hi1 (first and last sample's bins, widened by
 // s). Row by row, the window's candidates are staged in LDS in chunks of
-// WCH (coalesced 16-byte copies); every lane then walks its own range inside
-// the chunk from LDS. Candidates are read from global memory once per
-// workgroup instead of once per lane, which takes the vector-memory path off
-// the critical path. Rows with more samples than the grid's x extent covers
-// are walked in steps of gridDim.x runs.
+// WCH (coalesced 16-byte copies); every lane then walks its part of its
+// samples' range inside the chunk from LDS. Candidates are read from global
+// memory once per workgroup instead of once per lane, which takes the
+// vector-memory path off the critical path. S lanes share each group of WT
+// samples, splitting every row range into S pieces and adding their partial
+// sums by shuffles at the end (S > 1: more, shorter lanes for small
+// rasters). Rows with more samples than the grid's x extent covers are
+// walked in steps of gridDim.x runs.
 constexpr int WCH = 512;
-template <int WT>
+template <int WT, int S>
 __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_rows(const WSample<2>* __restrict__ ss,
                                                                  const int32_t* __restrict__ sidx,
                                                                  const int32_t* __restrict__ boff, WBinGeom g,
                                                                  int cx, double* __restrict__ alpha) {
+  constexpr int RUN = WB_BLOCK * WT / S;   // samples per workgroup run
   __shared__ __align__(16) WSample<2> cand[WCH];
   const int64_t lid = xcd_block(blockIdx.x, gridDim.x);
   const int b0 = (int)(lid / cx), bx = (int)(lid % cx);
   const int nb1 = g.nb[1];
   const int rs = boff[b0 * nb1], re = boff[(b0 + 1) * nb1];
   const int rlo = max(b0 - g.span, 0), rhi = min(b0 + g.span, g.nb[0] - 1);
-  for (int c0 = rs + bx * WB_BLOCK * WT; c0 < re; c0 += cx * WB_BLOCK * WT) {
-    const int cend = min(c0 + WB_BLOCK * WT, re);
-    const int t0 = c0 + threadIdx.x * WT;
+  const int sub = (int)threadIdx.x % S;
+  for (int c0 = rs + bx * RUN; c0 < re; c0 += cx * RUN) {
+    const int cend = min(c0 + RUN, re);
+    const int t0 = c0 + ((int)threadIdx.x / S) * WT;
     double x[WT][2], sn[WT][2], cs[WT][2], acc[WT];
     int mylo = 1 << 30, myhi = -1;
 #pragma unroll
@@ -231,7 +236,13 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_rows(const WSample<2
     }
     for (int r = rlo; r <= rhi; ++r) {
       const int gs = boff[r * nb1 + lo1], ge = boff[r * nb1 + hi1 + 1];
-      const int ms = active ? boff[r * nb1 + mylo] : 0, me = active ? boff[r * nb1 + myhi + 1] : 0;
+      int ms = 0, me = 0;
+      if (active) {
+        const int fs = boff[r * nb1 + mylo], fe = boff[r * nb1 + myhi + 1];
+        const int part = (fe - fs + S - 1) / S;
+        ms = min(fs + sub * part, fe);
+        me = min(ms + part, fe);
+      }
       for (int q0 = gs; q0 < ge; q0 += WCH) {
         const int q1 = min(q0 + WCH, ge);
         __syncthreads();  // the previous chunk has been consumed
@@ -247,8 +258,14 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_rows(const WSample<2
       }
     }
 #pragma unroll
-    for (int u = 0; u < WT; ++u)
-      if (t0 + u < cend) alpha[sidx[t0 + u]] = wscale<2>() / acc[u];
+    for (int off = 1; off < S; off <<= 1)
+#pragma unroll
+      for (int u = 0; u < WT; ++u) acc[u] += __shfl_xor(acc[u], off, 64);
+    if (sub == 0) {
+#pragma unroll
+      for (int u = 0; u < WT; ++u)
+        if (t0 + u < cend) alpha[sidx[t0 + u]] = wscale<2>() / acc[u];
+    }
   }
 }
 
@@ -501,17 +518,26 @@ void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const d
   p->have_wbins = true;
 }
 
-template <int WT>
+template <int WT, int S>
 static void launch_weights_rows(ftcg_plan p) {
   const WBinGeom& g = p->wgeom;
-  const int64_t runs = (p->m + WB_BLOCK * WT - 1) / (WB_BLOCK * WT);
+  const int64_t runs = (p->m * S + WB_BLOCK * WT - 1) / (WB_BLOCK * WT);
   // x extent: twice the mean runs per bin row, so dense rows are covered in
   // about one step while empty rows cost only idle workgroups
   const int cx = (int)std::max<int64_t>(1, (2 * runs + g.nb[0] - 1) / g.nb[0]);
   const int64_t nb = (int64_t)cx * g.nb[0];
-  hipLaunchKernelGGL((k_frame_weights_rows<WT>), dim3((unsigned)nb), dim3(WB_BLOCK), 0, p->stream,
+  hipLaunchKernelGGL((k_frame_weights_rows<WT, S>), dim3((unsigned)nb), dim3(WB_BLOCK), 0, p->stream,
                      p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), g, cx,
                      p->alpha.as<double>());
+}
+
+template <int WT>
+static void launch_weights_rows_s(ftcg_plan p, int S) {
+  switch (S) {
+    case 1: launch_weights_rows<WT, 1>(p); break;
+    case 2: launch_weights_rows<WT, 2>(p); break;
+    default: launch_weights_rows<WT, 4>(p); break;
+  }
 }
 
 template <int WT>
@@ -529,10 +555,13 @@ void run_plain_weights(ftcg_plan p) {
   timing_begin(p, STEP_WEIGHTS);
   const int wt = p->w_samples ? p->w_samples : 1;
   if (p->dim == 2) {
+    // lanes per sample group: the plan's tuning, else 4 below 2^21 samples
+    // and 2 from there (measured best on 2^17, 2^20 and 2^23-sample rasters)
+    const int S = p->w_lanes ? p->w_lanes : (p->m < (int64_t(1) << 21) ? 4 : 2);
     switch (wt) {
-      case 1: launch_weights_rows<1>(p); break;
-      case 2: launch_weights_rows<2>(p); break;
-      default: launch_weights_rows<4>(p); break;
+      case 1: launch_weights_rows_s<1>(p, S); break;
+      case 2: launch_weights_rows_s<2>(p, S); break;
+      default: launch_weights_rows_s<4>(p, S); break;
     }
   } else {
     switch (wt) {

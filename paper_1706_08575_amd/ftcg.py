@@ -122,16 +122,17 @@ class Plan:
 
     def set_tuning(self, tile: int = 0, accum: str | None = None, lds_copies: int = 1) -> None:
         """tile: 0 (automatic) or 16/32/64/128; accum: "fixed" (float32 plans'
-        default) or "f64"; lds_copies: partial tiles for "f64"."""
+        default), "f64" or "mfma" (2D float32, tile 64); lds_copies: partial
+        tiles for "f64"."""
         if accum is None:
             accum = "fixed" if self.dtype == L.FTCG_F32 else "f64"
-        a = {"fixed": L.FTCG_ACCUM_FIXED, "f64": L.FTCG_ACCUM_F64}[accum]
+        a = {"fixed": L.FTCG_ACCUM_FIXED, "f64": L.FTCG_ACCUM_F64, "mfma": L.FTCG_ACCUM_MFMA}[accum]
         L.check(L.call("ftcg_plan_set_tuning", self._h, int(tile), a, int(lds_copies)), "ftcg_plan_set_tuning")
 
-    def set_weight_tuning(self, samples_per_lane: int = 0) -> None:
-        """Samples per lane of the frame-weight kernel (0 = automatic); applies
+    def set_weight_tuning(self, samples_per_lane: int = 0, lanes_per_group: int = 0) -> None:
+        """Launch shape of the frame-weight kernel (0 = automatic); applies
         from the next weight computation."""
-        L.check(L.call("ftcg_plan_set_weight_tuning", self._h, int(samples_per_lane)),
+        L.check(L.call("ftcg_plan_set_weight_tuning", self._h, int(samples_per_lane), int(lanes_per_group)),
                 "ftcg_plan_set_weight_tuning")
 
     def set_mlp(self, mlp, audit_threshold: float = 1e-4, audit_samples: int = 4096) -> None:

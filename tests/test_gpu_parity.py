@@ -111,7 +111,7 @@ def test_2d_plain_f64_image(sas512):
 
 @pytest.mark.parametrize("tile,accum,copies", [(16, "fixed", 1), (32, "fixed", 1), (64, "fixed", 1),
                                                (128, "fixed", 1), (16, "f64", 1), (32, "f64", 4),
-                                               (64, "f64", 1), (64, "f64", 2)])
+                                               (64, "f64", 1), (64, "f64", 2), (64, "mfma", 1)])
 def test_2d_tilings_agree(sas512, tile, accum, copies):
     k, f, a_ref, ref = sas512
     img, _, info = run(k, f, 512, "f32", tune=(tile, accum, copies))
@@ -123,14 +123,16 @@ def test_tiling_beyond_lds_rejected():
     from paper_1706_08575_amd import _lib as L
     from paper_1706_08575_amd.ftcg import Plan
     with Plan(512, dim=2) as P:
-        for tile, accum, copies in ((128, "f64", 1), (64, "f64", 4), (64, "fixed", 2)):
+        for tile, accum, copies in ((128, "f64", 1), (64, "f64", 4), (64, "fixed", 2), (32, "mfma", 1),
+                                    (64, "mfma", 2)):
             with pytest.raises(L.FtcgError) as e:
                 P.set_tuning(tile, accum, copies)
             assert e.value.status == L.FTCG_EUNSUPPORTED
     with Plan(64, dim=2, dtype="f64") as P:
-        with pytest.raises(L.FtcgError) as e:
-            P.set_tuning(64, "fixed", 1)
-        assert e.value.status == L.FTCG_EUNSUPPORTED
+        for accum in ("fixed", "mfma"):
+            with pytest.raises(L.FtcgError) as e:
+                P.set_tuning(64, accum, 1)
+            assert e.value.status == L.FTCG_EUNSUPPORTED
 
 
 def test_fixed_accumulation_is_bitwise_reproducible(sas512):
@@ -156,6 +158,27 @@ def test_2d_spread_step_vs_oracle():
         H = host(P.spread_only(dev(f)))
     Href = O.spread(k, f, n)
     assert O.rel_l2(H, Href) < TOL_F64
+
+
+def test_2d_spread_step_mfma_vs_oracle():
+    # matrix-core accumulation against the float64 oracle spread, a dense
+    # raster (many records per tile, several LDS chunks) and a sparse one,
+    # with samples on the periodic seam
+    from paper_1706_08575_amd.ftcg import Plan
+    rng = np.random.default_rng(22)
+    for n, m in ((64, 20000), (128, 3000)):
+        k = rng.uniform(-0.75 * n, 0.75 * n, size=(m, 2))
+        k[:40, 0] = n / 2 - 0.01 * rng.random(40)      # u near G - 1 / wraps
+        f = S.random_values(23, m)
+        with Plan(n, dim=2, dtype="f32", weights="none") as P:
+            P.set_tuning(64, "mfma", 1)
+            P.set_points(dev(k))
+            H = host(P.spread_only(dev(f, torch.complex64)))
+        Href = O.spread(k, f, n)
+        # 2W taps per axis (floor(u) - W + 1 .. floor(u) + W) as on the other
+        # float32 paths; float32 taps and float32 accumulation of up to a few
+        # hundred random-phase terms per cell: the benchmark spec's bound
+        assert O.rel_l2(H, Href) < TOL_NORTH_STAR, (n, m)
 
 
 def test_2d_fft_step_vs_oracle():
