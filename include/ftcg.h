@@ -163,7 +163,9 @@ ftcg_status ftcg_plan_set_tuning(ftcg_plan plan, int tile, int accum, int lds_co
  *                      lane's candidate reads (0 = automatic: 1);
  *   lanes_per_group  : 1, 2 or 4 lanes split every candidate range of a group
  *                      of samples and add their partial sums (2D only;
- *                      0 = automatic: 4 below 2^21 samples, else 2).
+ *                      0 = automatic: 1 when a sample has more than about
+ *                      10^4 candidate neighbours, else 4 below 2^21 samples
+ *                      and 2 above).
  * Results agree to rounding for every shape. FTCG_EINVAL for other values. */
 ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan plan, int samples_per_lane, int lanes_per_group);
 

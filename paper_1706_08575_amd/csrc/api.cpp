@@ -148,6 +148,8 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
     p->flags.ensure(FLAGS_BYTES);
     p->deapod.ensure(sizeof(double) * n0);
     compute_deapod(p);
+    p->twiddle.ensure((dtype == FTCG_F64 ? 16 : 8) * (size_t)twiddle_entries(G));
+    compute_twiddles(p->twiddle.p, G, dtype == FTCG_F64, p->stream);
     const size_t csz = dtype == FTCG_F64 ? 16 : 8;
     p->grid.ensure(csz * (size_t)(dim == 2 ? G * G : G));
     if (dim == 2) p->fft_tmp.ensure(csz * (size_t)(n0 * G));
@@ -169,7 +171,7 @@ ftcg_status ftcg_plan_destroy(ftcg_plan p) {
   (void)hipStreamSynchronize(p->stream);
   DevBuf* bufs[] = {&p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp,
                     &p->flags,  &p->wb_cnt, &p->wb_off, &p->wb_rowoff, &p->wb_rowbuf, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->ws_inv, &p->audit_buf,
-                    &p->grid,   &p->fft_tmp, &p->deapod, &p->tile_order};
+                    &p->grid,   &p->fft_tmp, &p->deapod, &p->twiddle, &p->tile_order};
   for (DevBuf* b : bufs) b->release();
   for (auto& pr : p->timing.pending) {
     (void)hipEventDestroy(pr.a);

@@ -187,6 +187,7 @@ ftcg_status ftcg_batch_create(ftcg_batch_s** out, int n_items, const int64_t* n,
     b->tmp.ensure(sizeof(float2) * tmp);
     b->deapod.ensure(sizeof(double) * dp);
     b->img_total = img;
+
     // fft groups by grid size
     std::map<int64_t, std::vector<int>> groups;
     for (int i = 0; i < n_items; ++i) groups[b->plans[i]->G].push_back(i);
@@ -195,6 +196,17 @@ ftcg_status ftcg_batch_create(ftcg_batch_s** out, int n_items, const int64_t* n,
       b->fft_groups.push_back(kv.second);
       flat.insert(flat.end(), kv.second.begin(), kv.second.end());
     }
+    // twiddle tables per grid size, the same as a single plan's (so batch
+    // items stay bitwise equal to single plans)
+    int64_t ntw = 0;
+    for (auto& grp : b->fft_groups) {
+      b->twiddle_off.push_back(ntw);
+      ntw += twiddle_entries(b->plans[grp[0]]->G);
+    }
+    b->twiddle.ensure(sizeof(float2) * ntw);
+    for (size_t gi = 0; gi < b->fft_groups.size(); ++gi)
+      compute_twiddles(b->twiddle.as<float2>() + b->twiddle_off[gi], b->plans[b->fft_groups[gi][0]]->G, false,
+                       b->stream);
     b->group_items.ensure(sizeof(int) * flat.size());
     FTCG_HIP(hipMemcpy(b->group_items.p, flat.data(), sizeof(int) * flat.size(), hipMemcpyHostToDevice));
   });
@@ -212,7 +224,7 @@ ftcg_status ftcg_batch_destroy(ftcg_batch_s* b) {
   drop_graph(b);
   for (ftcg_plan p : b->plans) ftcg_plan_destroy(p);
   DevBuf* bufs[] = {&b->items_dev, &b->tiles, &b->tasks, &b->bounds, &b->scratch, &b->split_tiles, &b->counter,
-                    &b->args_dev, &b->grid, &b->tmp, &b->deapod, &b->group_items};
+                    &b->args_dev, &b->grid, &b->tmp, &b->deapod, &b->group_items, &b->twiddle};
   for (DevBuf* d : bufs) d->release();
   delete b;
   return FTCG_OK;

@@ -60,6 +60,8 @@ struct ftcg_batch_s {
   std::vector<std::vector<int>> fft_groups;  // item lists per distinct grid size
   ftcg::DevBuf items_dev, tiles, tasks, bounds, scratch, split_tiles, counter, args_dev;
   ftcg::DevBuf grid, tmp, deapod, group_items;
+  ftcg::DevBuf twiddle;          // two-level twiddle tables (float2), one per grid size
+  std::vector<int64_t> twiddle_off;  // first entry of each fft group's table
   int64_t ntiles = 0, ntasks = 0, nsplit = 0;
   int64_t m_total = 0, img_total = 0;
   bool have_points = false;

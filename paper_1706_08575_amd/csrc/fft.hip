@@ -71,9 +71,14 @@ __device__ inline cx cmul_i(cx a) {  // a * (+i)
 
 // in-place inverse (positive exponent) FFT of buf[0..L) in LDS, L = 2^log2L,
 // by threads tid = 0..nth-1, nth >= L / PPT (PPT points per thread per
-// stage); every thread of the workgroup calls it with the same L
+// stage); every thread of the workgroup calls it with the same L. Twiddles:
+// with w(j) = e^{2 pi i j / 2^log2T} (2^log2T >= L), e^{2 pi i k / (4 Ns)} =
+// w(k << (log2T - log2(4 Ns))), and w(j) = hi[j >> 6] * lo[j & 63] from the two
+// LDS tables lo[t] = w(t), hi[t] = w(64 t) (both formed in float64); the
+// second and third twiddles of a radix-4 butterfly are its square and cube.
 template <class real, int PPT>
-__device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L, int tid, int nth) {
+__device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L, int tid, int nth,
+                         const typename CxF<real>::t* tw_lo, const typename CxF<real>::t* tw_hi, int log2T) {
   using cx = typename CxF<real>::t;
   constexpr int FFT_MAXB = PPT / 2;  // radix-2 butterflies per thread
   int Ns = 1;
@@ -100,7 +105,9 @@ __device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L, int tid, 
     Ns = 2;
   }
   const int quarter = L >> 2;
-  for (; Ns < L; Ns <<= 2) {
+  int log2Ns = log2L & 1;
+  for (; Ns < L; Ns <<= 2, log2Ns += 2) {
+    const int sh = log2T - log2Ns - 2;
     cx v[FFT_MAXB / 2][4];
 #pragma unroll
     for (int u = 0; u < FFT_MAXB / 2; ++u)
@@ -110,11 +117,8 @@ __device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L, int tid, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[u][r] = buf[b + r * quarter];
         if (Ns > 1) {
-          real s, c;
-          CxF<real>::sincospi_((real)k / (real)(2 * Ns), &s, &c);  // e^{2 pi i k / (4 Ns)}
-          cx w1;
-          w1.x = c;
-          w1.y = s;
+          const int j = k << sh;
+          const cx w1 = cmul(tw_hi[j >> 6], tw_lo[j & 63]);
           const cx w2 = cmul(w1, w1);
           const cx w3 = cmul(w2, w1);
           v[u][1] = cmul(v[u][1], w1);
@@ -156,7 +160,15 @@ __device__ inline void fft_rows_block(const typename CxF<real>::t* __restrict__ 
                                       typename CxF<real>::t* __restrict__ dst, int64_t out_stride_q, int L,
                                       int log2L, int ncrop, int crop_off, int r0, int pre_sign,
                                       const double* __restrict__ dq, const double* __restrict__ drow,
-                                      typename CxF<real>::t* buf) {
+                                      typename CxF<real>::t* buf, const typename CxF<real>::t* __restrict__ tw,
+                                      int log2T) {
+  // twiddle tables behind the RC row buffers: lo (64 entries), hi (2^log2T / 64)
+  typename CxF<real>::t* tw_lo = buf + (size_t)RC * L;
+  typename CxF<real>::t* tw_hi = tw_lo + 64;
+  {
+    const int ntw = 64 + max(1, (1 << log2T) >> 6);
+    for (int i = threadIdx.x; i < ntw; i += blockDim.x) tw_lo[i] = tw[i];
+  }
   static_assert(RC == 1 || RC == RB, "rows per workgroup run one at a time or all at once");
   using cx = typename CxF<real>::t;
   constexpr int NJ = RB / RC;
@@ -195,7 +207,7 @@ __device__ inline void fft_rows_block(const typename CxF<real>::t* __restrict__ 
         if (t + u * nts < L) nxt[u] = s1[t + u * nts];
     }
     __syncthreads();
-    lds_ifft<real, PPT>(sbuf, L, log2L, t, nts);
+    lds_ifft<real, PPT>(sbuf, L, log2L, t, nts, tw_lo, tw_hi, log2T);
     const double fr = drow ? drow[row] : 1.0;
 #pragma unroll
     for (int kq = 0; kq < MAXQ; ++kq) {
@@ -241,13 +253,14 @@ template <class real, int RB, int RC, int MAXQ, int PPT>
 __global__ void k_fft_rows(const typename CxF<real>::t* __restrict__ in, int64_t in_row_stride,
                            typename CxF<real>::t* __restrict__ out, int64_t out_stride_q, int L, int log2L,
                            int ncrop, int crop_off, int rows, int pre_sign, const double* __restrict__ dq,
-                           const double* __restrict__ drow) {
+                           const double* __restrict__ drow, const typename CxF<real>::t* __restrict__ tw,
+                           int log2T) {
   using cx = typename CxF<real>::t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx* buf = reinterpret_cast<cx*>(smem_raw);
   const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * RB;
   fft_rows_block<real, RB, RC, MAXQ, PPT>(in + (int64_t)r0 * in_row_stride, in_row_stride, out + r0, out_stride_q,
-                                          L, log2L, ncrop, crop_off, r0, pre_sign, dq, drow, buf);
+                                          L, log2L, ncrop, crop_off, r0, pre_sign, dq, drow, buf, tw, log2T);
 }
 
 // batched passes over the items of one grid size G (all with n = G / sigma),
@@ -255,7 +268,8 @@ __global__ void k_fft_rows(const typename CxF<real>::t* __restrict__ in, int64_t
 // rows b*RB % G ..; pass 2 maps it to item list[b*RB / n], intermediate rows
 template <int RB, int RC, int MAXQ, int PPT>
 __global__ void k_fft_rows_batched(const BatchItem* __restrict__ items, const int* __restrict__ list,
-                                   const BatchArgs* __restrict__ args, int pass, int L, int log2L, int n) {
+                                   const BatchArgs* __restrict__ args, int pass, int L, int log2L, int n,
+                                   const float2* __restrict__ tw, int log2T) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float2* buf = reinterpret_cast<float2*>(smem_raw);
   const int r = (int)xcd_block(blockIdx.x, gridDim.x) * RB;
@@ -266,12 +280,12 @@ __global__ void k_fft_rows_batched(const BatchItem* __restrict__ items, const in
   if (pass == 1) {
     fft_rows_block<float, RB, RC, MAXQ, PPT>(args->grid + it.grid_off + (int64_t)row * L, L,
                                              args->tmp + it.tmp_off + row, L, L, log2L, n, crop_off, row, 1, nullptr,
-                                             nullptr, buf);
+                                             nullptr, buf, tw, log2T);
   } else {
     const double* d = args->deapod + it.deapod_off;
     fft_rows_block<float, RB, RC, MAXQ, PPT>(args->tmp + it.tmp_off + (int64_t)row * L, L,
                                              args->images + it.img_off + row, n, L, log2L, n, crop_off, row, 0, d,
-                                             d, buf);
+                                             d, buf, tw, log2T);
   }
 }
 
@@ -327,6 +341,7 @@ struct BatchedLaunch {
   int pass, rows;
   FftShape f;
   int L, log2L, n;
+  const float2* tw;
   template <int RB, int RC, int MAXQ, int PPT>
   void operator()() const {
     static bool attr_done = false;
@@ -335,9 +350,10 @@ struct BatchedLaunch {
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
       attr_done = true;
     }
-    const size_t lds = (size_t)RC * L * sizeof(float2);
+    const size_t lds = ((size_t)RC * L + 64 + std::max(1, L >> 6)) * sizeof(float2);
     hipLaunchKernelGGL((k_fft_rows_batched<RB, RC, MAXQ, PPT>), dim3((unsigned)(rows / RB)), dim3(f.nts * RC), lds,
-                       b->stream, b->items_dev.as<BatchItem>(), list, b->args_dev.as<BatchArgs>(), pass, L, log2L, n);
+                       b->stream, b->items_dev.as<BatchItem>(), list, b->args_dev.as<BatchArgs>(), pass, L, log2L, n,
+                       tw, log2L);
   }
 };
 
@@ -346,7 +362,9 @@ void batch_fft_prepare() {}
 void batch_fft(ftcg_batch_s* b) {
   const int* lists = b->group_items.as<int>();
   int64_t list_off = 0;
+  size_t gi = 0;
   for (const auto& grp : b->fft_groups) {
+    const float2* tw = b->twiddle.as<float2>() + b->twiddle_off[gi++];
     const int64_t G = b->items[grp[0]].G;
     const int n = b->items[grp[0]].n;
     int log2L = 0;
@@ -357,7 +375,7 @@ void batch_fft(ftcg_batch_s* b) {
       // row blocks must not straddle items: RB divides the rows of one item
       const FftShape f = fft_shape(G, n, per, (int)sizeof(float2));
       const int rows = (int)grp.size() * per;
-      dispatch_shape(f, BatchedLaunch{b, list, pass, rows, f, (int)G, log2L, n});
+      dispatch_shape(f, BatchedLaunch{b, list, pass, rows, f, (int)G, log2L, n, tw});
     }
     list_off += (int64_t)grp.size();
   }
@@ -381,7 +399,7 @@ struct RowsLaunch {
     const int L = (int)p->G;
     int log2L = 0;
     while ((1 << log2L) < L) ++log2L;
-    const size_t lds = (size_t)RC * L * sizeof(cx);
+    const size_t lds = ((size_t)RC * L + 64 + std::max(1, L >> 6)) * sizeof(cx);
     static bool attr_done = false;
     if (!attr_done) {
       FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows<real, RB, RC, MAXQ, PPT>,
@@ -392,7 +410,7 @@ struct RowsLaunch {
     const int crop_off = (int)((p->G - p->n) / 2);
     hipLaunchKernelGGL((k_fft_rows<real, RB, RC, MAXQ, PPT>), dim3((unsigned)(rows / RB)), dim3(f.nts * RC), lds,
                        p->stream, static_cast<const cx*>(in), in_row_stride, static_cast<cx*>(out), out_stride_q, L,
-                       log2L, ncrop, crop_off, rows, pre_sign, dq, drow);
+                       log2L, ncrop, crop_off, rows, pre_sign, dq, drow, p->twiddle.as<cx>(), log2L);
     FTCG_HIP(hipGetLastError());
   }
 };
@@ -436,6 +454,31 @@ __global__ void k_deapod(double* d, int64_t n, double sigma, double beta) {
   const double pi = 3.141592653589793238462643383279502884;
   const double t = ((double)p - (double)(n / 2)) / (double)n / sigma;
   d[p] = 1.0 / (sqrt(pi / beta) * exp(-pi * pi * t * t / beta));
+}
+
+// two-level twiddle tables for w(j) = e^{2 pi i j / L}: tw[t] = w(t) for
+// t < 64, then tw[64 + t] = w(64 t) for t < max(1, L / 64); float64, rounded once
+template <class cx>
+__global__ void k_twiddles(cx* tw, int L) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nhi = L >= 64 ? L / 64 : 1;
+  if (i >= 64 + nhi) return;
+  const double j = i < 64 ? (double)i : 64.0 * (double)(i - 64);
+  double s, c;
+  sincospi(2.0 * j / (double)L, &s, &c);
+  tw[i].x = c;
+  tw[i].y = s;
+}
+
+int64_t twiddle_entries(int64_t L) { return 64 + (L >= 64 ? L / 64 : 1); }
+
+void compute_twiddles(void* tw, int64_t L, bool f64, hipStream_t s) {
+  const unsigned nb = (unsigned)((twiddle_entries(L) + 255) / 256);
+  if (f64)
+    hipLaunchKernelGGL(k_twiddles<double2>, dim3(nb), dim3(256), 0, s, static_cast<double2*>(tw), (int)L);
+  else
+    hipLaunchKernelGGL(k_twiddles<float2>, dim3(nb), dim3(256), 0, s, static_cast<float2*>(tw), (int)L);
+  FTCG_HIP(hipGetLastError());
 }
 
 void compute_deapod(ftcg_plan p) {

@@ -221,6 +221,7 @@ struct ftcg_plan_s {
 
   // execute workspace
   ftcg::DevBuf grid;         // G^dim complex
+  ftcg::DevBuf twiddle;      // two-level tables of e^{2 pi i j / G} (plan precision)
   ftcg::DevBuf fft_tmp;      // n x G complex (2D)
   ftcg::DevBuf deapod;       // n float64
   ftcg::DevBuf tile_order;   // ntiles int32 (heavy tiles first)
@@ -249,6 +250,9 @@ void fill_ones(double* a, int64_t m, hipStream_t s);
 void spread(ftcg_plan p, const void* fhat, void* grid);
 void grid_to_image(ftcg_plan p, const void* grid, void* image);
 void compute_deapod(ftcg_plan p);
+// two-level twiddle tables of the L-th roots of unity (float2, or double2 when f64)
+int64_t twiddle_entries(int64_t L);
+void compute_twiddles(void* tw, int64_t L, bool f64, hipStream_t s);
 int64_t plan_nrec(ftcg_plan p);  // records of the last set_points (one host sync)
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s,
                         int32_t* cursor = nullptr);

@@ -556,8 +556,13 @@ void run_plain_weights(ftcg_plan p) {
   const int wt = p->w_samples ? p->w_samples : 1;
   if (p->dim == 2) {
     // lanes per sample group: the plan's tuning, else 4 below 2^21 samples
-    // and 2 from there (measured best on 2^17, 2^20 and 2^23-sample rasters)
-    const int S = p->w_lanes ? p->w_lanes : (p->m < (int64_t(1) << 21) ? 4 : 2);
+    // and 2 from there, but 1 when a sample has more than about 10^4
+    // candidates (measured on SAS rasters of 2^16 .. 2^23 samples at
+    // 0.002 .. 13 samples per grid cell: long lists already fill the lanes,
+    // and more lanes per sample only multiply the LDS staging per sample)
+    const WBinGeom& g = p->wgeom;
+    const double cand = (double)p->m / ((double)g.nb[0] * g.nb[1]) * (2 * g.span + 1) * (2 * g.span + 1);
+    const int S = p->w_lanes ? p->w_lanes : (cand > 1e4 ? 1 : (p->m < (int64_t(1) << 21) ? 4 : 2));
     switch (wt) {
       case 1: launch_weights_rows_s<1>(p, S); break;
       case 2: launch_weights_rows_s<2>(p, S); break;
