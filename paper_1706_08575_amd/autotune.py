@@ -1,6 +1,7 @@
-"""Autotuner for the spreading launch: tile edge (and, for batches, records
-per task) chosen by timing candidates on the caller's own data, remembered in
-a JSON cache keyed by the workload's shape.
+"""Autotuner for the spreading launch: tile edge and accumulation (LDS
+integers or matrix cores; for batches, tile and records per task) chosen by
+timing candidates on the caller's own data, remembered in a JSON cache keyed
+by the workload's shape.
 
 Keys: single plans by (precision, W, sigma, n, log2 of samples per grid cell
 rounded to half steps); batches by the same key over the batch's item mix.
@@ -77,34 +78,38 @@ def _spread_ms(obj, run, reps: int) -> float:
 
 
 def tune_plan(plan, k: torch.Tensor, fhat: torch.Tensor, tiles=PLAN_TILES, reps: int = 3, use_cache: bool = True):
-    """Pick the tile edge of `plan` (a float32 Plan) for raster k, values fhat.
-    Leaves the plan tuned and with its points set. Returns (tile, {tile: ms})."""
+    """Pick the spreading launch of `plan` for raster k, values fhat: the tile
+    edge with the plan's LDS accumulation, and for 2D float32 plans also the
+    matrix-core accumulation (tile 64). Leaves the plan tuned and with its
+    points set. Returns ((tile, accum), {"tile/accum": ms})."""
     dtype = "f32" if plan.cdtype == torch.complex64 else "f64"
     key = plan_key(dtype, plan.W, plan.sigma, plan.n, int(k.shape[0]))
     cache = _load() if use_cache else {}
-    if use_cache and key in cache:
-        tile = int(cache[key]["tile"])
-        plan.set_tuning(tile)
+    if use_cache and key in cache and "accum" in cache[key]:
+        tile, accum = int(cache[key]["tile"]), cache[key]["accum"]
+        plan.set_tuning(tile, accum, 1)
         plan.set_points(k)
-        return tile, cache[key].get("ms", {})
+        return (tile, accum), cache[key].get("ms", {})
+    base = "fixed" if dtype == "f32" else "f64"
+    cands = [(t, base) for t in tiles if t >= 2 * plan.W]
+    if dtype == "f32" and plan.dim == 2:
+        cands.append((64, "mfma"))
     times = {}
-    accum = "fixed" if dtype == "f32" else "f64"
-    for t in tiles:
-        if t < 2 * plan.W:
-            continue
+    for t, accum in cands:
         try:
             plan.set_tuning(t, accum, 1)
         except Exception:
             continue
         plan.set_points(k)
-        times[t] = _spread_ms(plan, lambda: plan.execute(fhat), reps)
-    tile = min(times, key=times.get)
-    plan.set_tuning(tile, accum, 1)
+        times[(t, accum)] = _spread_ms(plan, lambda: plan.execute(fhat), reps)
+    best = min(times, key=times.get)
+    plan.set_tuning(best[0], best[1], 1)
     plan.set_points(k)
+    ms = {f"{a}/{b}": v for (a, b), v in times.items()}
     if use_cache:
-        cache[key] = {"tile": tile, "ms": {str(a): b for a, b in times.items()}, "when": time.time()}
+        cache[key] = {"tile": best[0], "accum": best[1], "ms": ms, "when": time.time()}
         _store(cache)
-    return tile, times
+    return best, ms
 
 
 def tune_batch(batch, m, k: torch.Tensor, fhat: torch.Tensor, tiles=BATCH_TILES, chunks=BATCH_CHUNKS,

@@ -31,7 +31,7 @@ __device__ inline unsigned long long ordered_bits(double x) {
 // order-preserving integers; the host reduces the partials (no atomics, no
 // initialisation pass). The same launch zeroes zero_a[0 .. zero_na) and
 // zero_b[0 .. zero_nb), the counters of the binnings that follow.
-constexpr int CHECK_BLOCKS = 256;
+constexpr int CHECK_BLOCKS = 1024;
 __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __restrict__ k, int64_t m, int dim,
                                                             unsigned long long* __restrict__ part,
                                                             int32_t* __restrict__ zero_a, int64_t zero_na,
@@ -44,16 +44,28 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __rest
   if (threadIdx.x == 0) sbad = 0;
   unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
   bool bad = false;
-  for (int64_t j = gt; j < m; j += gs) {
-    for (int a = 0; a < dim; ++a) {
-      const double x = k[j * dim + a];
-      if (!isfinite(x)) {
-        bad = true;
-        continue;
+  // CHECK_UNROLL points per thread per step, all loaded before any is used
+  constexpr int CHECK_UNROLL = 4;
+  for (int64_t j0 = gt; j0 < m; j0 += CHECK_UNROLL * gs) {
+    double x[CHECK_UNROLL][2];
+#pragma unroll
+    for (int u = 0; u < CHECK_UNROLL; ++u) {
+      const int64_t j = j0 + u * gs;
+      x[u][0] = j < m ? k[j * dim] : 0.0;
+      x[u][1] = (j < m && dim == 2) ? k[j * dim + 1] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < CHECK_UNROLL; ++u) {
+      if (j0 + u * gs >= m) continue;
+      for (int a = 0; a < dim; ++a) {
+        if (!isfinite(x[u][a])) {
+          bad = true;
+          continue;
+        }
+        const unsigned long long o = ordered_bits(x[u][a]);
+        lo[a] = o < lo[a] ? o : lo[a];
+        hi[a] = o > hi[a] ? o : hi[a];
       }
-      const unsigned long long o = ordered_bits(x);
-      lo[a] = o < lo[a] ? o : lo[a];
-      hi[a] = o > hi[a] ? o : hi[a];
     }
   }
 #pragma unroll

@@ -233,7 +233,7 @@ struct ftcg_plan_s {
 namespace ftcg {
 
 // launchers (defined in the .hip files); all enqueue on plan->stream
-constexpr size_t FLAGS_BYTES = 16384;     // device flags / pinned host mirror
+constexpr size_t FLAGS_BYTES = 65536;     // device flags / pinned host mirror
 constexpr int64_t WROW_CNT_ZERO = 4100;   // bin-row counters cleared by the input check (>= 4096 + 1)
 constexpr size_t FLAGS_PART_OFF = 128;    // byte offset of the input-check partials
 // returns the number of partial records (5 words each) written to part

@@ -335,22 +335,33 @@ static WBinGeom wbin_geom(ftcg_plan p, const double* kmin, const double* kmax) {
 }
 
 // 2D neighbour binning in two levels, so no pass spreads atomics over all
-// nb0 x nb1 bins (they outgrow the L2 on large rasters):
-//  1. k_wrow_count: bin id of every sample (kept in bin_of), counts per bin
-//     row b0 in LDS, one global atomic per row a workgroup saw;
+// nb0 x nb1 bins (they outgrow the L2 on large rasters) and no pass gathers
+// at random:
+//  1. k_wrow_count: counts per bin row b0 in LDS, one global atomic per row a
+//     workgroup saw;
 //  2. exclusive scan over the <= 4096 rows (row_off; the counters become
 //     cursors);
 //  3. k_wrow_scatter: each workgroup claims one range per row and places its
-//     samples' indices there (rowbuf, grouped by row);
-//  4. k_wrow_sort: one workgroup per row counts its samples per bin b1 in LDS,
-//     scans them, writes the bin offsets boff of the whole row and places the
-//     sorted samples (k, sin, cos), their caller index and the inverse map;
-//     every write of this pass stays inside the row's own range.
+//     samples there as {k, caller index, bin column} (rowbuf, grouped by row);
+//  4. k_wrow_sort: one workgroup per row reads its range in order, counts the
+//     samples per bin column in LDS, scans them, writes the bin offsets boff
+//     of the whole row, orders the row in LDS (rows of up to WROW_LMAX
+//     samples) and writes the sorted samples (k, sin, cos) and their caller
+//     index coalesced, and (when asked) the inverse map; longer rows place
+//     their samples directly. Every write stays inside the row's own range.
 // The row counters arrive zeroed (the input check clears them).
 constexpr int WROW_IPT = 4;
+constexpr int WROW_LMAX = 16384;   // rows up to this many samples are ordered in LDS
 
-__device__ inline int wbin_row_col(const double* __restrict__ k, int64_t j, const WBinGeom& g, int* b1) {
-  double x[2] = {k[2 * j], k[2 * j + 1]};
+struct RowRec {
+  double k0, k1;
+  int32_t j, b1;
+};
+
+__device__ inline int wbin_row_col(const double* __restrict__ k, int64_t j, const WBinGeom& g, int* b1,
+                                   double* x) {
+  x[0] = k[2 * j];
+  x[1] = k[2 * j + 1];
   int b[2];
   wbin_of<2>(x, g, b);
   *b1 = b[1];
@@ -358,8 +369,7 @@ __device__ inline int wbin_row_col(const double* __restrict__ k, int64_t j, cons
 }
 
 __global__ __launch_bounds__(WB_BLOCK) void k_wrow_count(const double* __restrict__ k, int64_t m, WBinGeom g,
-                                                         int32_t* __restrict__ row_cnt,
-                                                         int32_t* __restrict__ bin_of) {
+                                                         int32_t* __restrict__ row_cnt) {
   __shared__ int32_t hist[4096];
   const int nrow = g.nb[0];
   for (int i = threadIdx.x; i < nrow; i += WB_BLOCK) hist[i] = 0;
@@ -370,9 +380,8 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_count(const double* __restric
     const int64_t j = j0 + (int64_t)u * WB_BLOCK + threadIdx.x;
     if (j < m) {
       int b1;
-      const int b0 = wbin_row_col(k, j, g, &b1);
-      bin_of[j] = b0 * g.nb[1] + b1;
-      atomicAdd(&hist[b0], 1);
+      double x[2];
+      atomicAdd(&hist[wbin_row_col(k, j, g, &b1, x)], 1);
     }
   }
   __syncthreads();
@@ -382,20 +391,24 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_count(const double* __restric
   }
 }
 
-__global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(int64_t m, WBinGeom g, const int32_t* __restrict__ bin_of,
+__global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(const double* __restrict__ k, int64_t m, WBinGeom g,
                                                            int32_t* __restrict__ row_cursor,
-                                                           int32_t* __restrict__ rowbuf) {
+                                                           RowRec* __restrict__ rowbuf) {
   __shared__ int32_t base[4096];
-  const int nrow = g.nb[0], nb1 = g.nb[1];
+  const int nrow = g.nb[0];
   for (int i = threadIdx.x; i < nrow; i += WB_BLOCK) base[i] = 0;
   __syncthreads();
   const int64_t j0 = (int64_t)blockIdx.x * WROW_IPT * WB_BLOCK;
-  int row[WROW_IPT];
+  int row[WROW_IPT], col[WROW_IPT];
+  double x[WROW_IPT][2];
 #pragma unroll
   for (int u = 0; u < WROW_IPT; ++u) {
     const int64_t j = j0 + (int64_t)u * WB_BLOCK + threadIdx.x;
-    row[u] = j < m ? bin_of[j] / nb1 : -1;
-    if (row[u] >= 0) atomicAdd(&base[row[u]], 1);
+    row[u] = -1;
+    if (j < m) {
+      row[u] = wbin_row_col(k, j, g, &col[u], x[u]);
+      atomicAdd(&base[row[u]], 1);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nrow; i += WB_BLOCK) {
@@ -406,25 +419,31 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(int64_t m, WBinGeom g
 #pragma unroll
   for (int u = 0; u < WROW_IPT; ++u) {
     const int64_t j = j0 + (int64_t)u * WB_BLOCK + threadIdx.x;
-    if (row[u] >= 0) rowbuf[atomicAdd(&base[row[u]], 1)] = (int32_t)j;
+    if (row[u] >= 0) {
+      RowRec r;
+      r.k0 = x[u][0];
+      r.k1 = x[u][1];
+      r.j = (int32_t)j;
+      r.b1 = col[u];
+      rowbuf[atomicAdd(&base[row[u]], 1)] = r;
+    }
   }
 }
 
-__global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(const double* __restrict__ k, WBinGeom g,
-                                                        const int32_t* __restrict__ row_off,
-                                                        const int32_t* __restrict__ rowbuf,
-                                                        const int32_t* __restrict__ bin_of,
+__global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_t* __restrict__ row_off,
+                                                        const RowRec* __restrict__ rowbuf,
                                                         int32_t* __restrict__ boff, WSample<2>* __restrict__ ss,
                                                         int32_t* __restrict__ sidx, int32_t* __restrict__ inv) {
   constexpr int ITEMS = 4096 / WB_BLOCK;
   __shared__ int32_t cnt[4096];
   __shared__ int32_t wsum[WB_BLOCK / 64];
+  __shared__ uint16_t perm[WROW_LMAX];
   const int b0 = blockIdx.x, nb1 = g.nb[1];
   const int rs = row_off[b0], re = row_off[b0 + 1];
   const int t = threadIdx.x;
   for (int i = t; i < nb1; i += WB_BLOCK) cnt[i] = 0;
   __syncthreads();
-  for (int i = rs + t; i < re; i += WB_BLOCK) atomicAdd(&cnt[bin_of[rowbuf[i]] - b0 * nb1], 1);
+  for (int i = rs + t; i < re; i += WB_BLOCK) atomicAdd(&cnt[rowbuf[i].b1], 1);
   __syncthreads();
   // exclusive scan of cnt[0 .. nb1): thread t owns entries t*ITEMS .. +ITEMS-1
   int v[ITEMS];
@@ -458,17 +477,35 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(const double* __restrict
   }
   if (b0 == g.nb[0] - 1 && t == 0) boff[g.nb[0] * nb1] = re;
   __syncthreads();
-  for (int i = rs + t; i < re; i += WB_BLOCK) {
-    const int j = rowbuf[i];
-    const int pos = atomicAdd(&cnt[bin_of[j] - b0 * nb1], 1);
-    WSample<2> s;
-    for (int a = 0; a < 2; ++a) {
-      s.k[a] = k[2 * (int64_t)j + a];
-      sincospi(s.k[a], &s.sc[a][0], &s.sc[a][1]);
+  if (re - rs <= WROW_LMAX) {
+    // rows that fit: the sorted order is built in LDS first (perm[pos] = the
+    // row entry placed at pos), so the sorted arrays are written coalesced
+    for (int i = rs + t; i < re; i += WB_BLOCK) perm[atomicAdd(&cnt[rowbuf[i].b1], 1) - rs] = (uint16_t)(i - rs);
+    __syncthreads();
+    for (int q = t; q < re - rs; q += WB_BLOCK) {
+      const RowRec r = rowbuf[rs + perm[q]];
+      WSample<2> smp;
+      smp.k[0] = r.k0;
+      smp.k[1] = r.k1;
+      sincospi(r.k0, &smp.sc[0][0], &smp.sc[0][1]);
+      sincospi(r.k1, &smp.sc[1][0], &smp.sc[1][1]);
+      ss[rs + q] = smp;
+      sidx[rs + q] = r.j;
+      if (inv) inv[r.j] = rs + q;
     }
-    ss[pos] = s;
-    sidx[pos] = j;
-    inv[j] = pos;
+    return;
+  }
+  for (int i = rs + t; i < re; i += WB_BLOCK) {
+    const RowRec r = rowbuf[i];
+    const int pos = atomicAdd(&cnt[r.b1], 1);
+    WSample<2> smp;
+    smp.k[0] = r.k0;
+    smp.k[1] = r.k1;
+    sincospi(r.k0, &smp.sc[0][0], &smp.sc[0][1]);
+    sincospi(r.k1, &smp.sc[1][0], &smp.sc[1][1]);
+    ss[pos] = smp;
+    sidx[pos] = r.j;
+    if (inv) inv[r.j] = pos;
   }
 }
 
@@ -490,17 +527,19 @@ void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const d
     // row counters: zeroed by the input check (WROW_CNT_ZERO entries)
     int32_t* row_cnt = p->wb_cnt.as<int32_t>();
     p->wb_rowoff.ensure(sizeof(int32_t) * (g.nb[0] + 1));
-    p->wb_rowbuf.ensure(sizeof(int32_t) * m);
+    p->wb_rowbuf.ensure(sizeof(RowRec) * m);
     p->scan_tmp.ensure(scan_tmp_bytes(g.nb[0]));
     int32_t* row_off = p->wb_rowoff.as<int32_t>();
     const unsigned nb = (unsigned)((m + WROW_IPT * WB_BLOCK - 1) / (WROW_IPT * WB_BLOCK));
-    hipLaunchKernelGGL(k_wrow_count, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, row_cnt, p->wb_of.as<int32_t>());
+    hipLaunchKernelGGL(k_wrow_count, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, row_cnt);
     exclusive_scan_i32(row_cnt, row_off, g.nb[0], p->scan_tmp.as<int32_t>(), s, row_cnt);
-    hipLaunchKernelGGL(k_wrow_scatter, dim3(nb), dim3(WB_BLOCK), 0, s, m, g, p->wb_of.as<int32_t>(), row_cnt,
-                       p->wb_rowbuf.as<int32_t>());
-    hipLaunchKernelGGL(k_wrow_sort, dim3((unsigned)g.nb[0]), dim3(WB_BLOCK), 0, s, k, g, row_off,
-                       p->wb_rowbuf.as<int32_t>(), p->wb_of.as<int32_t>(), off, p->ws_k.as<WSample<2>>(),
-                       p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>());
+    hipLaunchKernelGGL(k_wrow_scatter, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, row_cnt,
+                       p->wb_rowbuf.as<RowRec>());
+    // the inverse map serves the learned features and the audit only
+    const bool need_inv = p->wmode == FTCG_W_LEARNED || p->weights_only;
+    hipLaunchKernelGGL(k_wrow_sort, dim3((unsigned)g.nb[0]), dim3(WB_BLOCK), 0, s, g, row_off,
+                       p->wb_rowbuf.as<RowRec>(), off, p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(),
+                       need_inv ? p->ws_inv.as<int32_t>() : nullptr);
   } else {
     const size_t cnt_bytes = sizeof(int32_t) * ((nbins + 4) & ~int64_t(3));  // 16-byte multiple: one fill
     p->wb_cnt.ensure(cnt_bytes);

@@ -181,6 +181,24 @@ def test_2d_spread_step_mfma_vs_oracle():
         assert O.rel_l2(H, Href) < TOL_NORTH_STAR, (n, m)
 
 
+def test_plan_autotuner(tmp_path, monkeypatch):
+    # the tuner times every candidate launch on the caller's data, leaves the
+    # plan on the fastest, and the result stays within the float32 bar
+    monkeypatch.setenv("FTCG_TUNING_CACHE", str(tmp_path / "tune.json"))
+    from paper_1706_08575_amd import autotune
+    from paper_1706_08575_amd.ftcg import Plan
+    k, f, _ = S.make_sas(41, 128, 64, 256)
+    with Plan(128, dim=2) as P:
+        best, ms = autotune.tune_plan(P, dev(k), dev(f, torch.complex64), reps=1)
+        assert "64/mfma" in ms and "64/fixed" in ms
+        assert best in {tuple([int(a.split("/")[0]), a.split("/")[1]]) for a in ms}
+        img = host(P.execute(dev(f, torch.complex64)))
+        again, _ = autotune.tune_plan(P, dev(k), dev(f, torch.complex64))   # from the cache
+        assert again == best
+    ref = O.ftcg_image(k, f, O.frame_weights(k, 8.0), 128)
+    assert O.rel_l2(img, ref) < TOL_F32
+
+
 def test_2d_fft_step_vs_oracle():
     rng = np.random.default_rng(3)
     n, G = 64, 128
