@@ -47,15 +47,18 @@ static double decode_ordered(unsigned long long o) {
 
 static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
+// 2D: tile 64 while that still gives at least 1024 tiles (four per CU),
+// else 32, so that small grids keep enough spreading workgroups in flight
+// (measured on the 512^2 SAS raster: 64 -> 0.044 ms, 32 -> 0.022 ms spread)
 static int auto_tile(ftcg_plan p) {
   if (p->dim == 1) return (int)(p->G < 1024 ? p->G : 1024);
-  int t = 64;
+  int t = (p->G / 64) * (p->G / 64) >= 1024 ? 64 : 32;
   if (t > p->G) t = (int)p->G;
   return t;
 }
 
 static void setup_tiles(ftcg_plan p) {
-  int t = p->tile_req ? p->tile_req : auto_tile(p);
+  int t = p->tile_req ? p->tile_req : (p->accum == ACCUM_MFMA ? 64 : auto_tile(p));
   if (t > p->G) t = (int)p->G;
   p->tile = t;
   p->nt = p->G / t;
