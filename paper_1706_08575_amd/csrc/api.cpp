@@ -98,6 +98,24 @@ int64_t plan_nrec(ftcg_plan p) {
 }
 }  // namespace ftcg
 
+// learned weights, then their audit against the plain weights on a subset of
+// samples (one host synchronisation to read its estimate) and the plain
+// weights where it fails
+static void run_learned_with_audit(ftcg_plan p, const double* k_dev) {
+  timing_begin(p, STEP_LEARNED);
+  launch_learned_weights(p, k_dev, p->mlp);
+  timing_end(p, STEP_LEARNED);
+  timing_begin(p, STEP_AUDIT);
+  double* est_dev = p->flags.as<double>() + 6;
+  launch_audit(p, k_dev, est_dev);
+  FTCG_HIP(hipMemcpyAsync(p->host_flags + 6, est_dev, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  FTCG_HIP(hipStreamSynchronize(p->stream));
+  timing_end(p, STEP_AUDIT);
+  p->audit_estimate = p->host_flags[6];
+  p->used_fallback = !(p->audit_estimate <= p->audit_threshold);
+  if (p->used_fallback) run_plain_weights(p);
+}
+
 extern "C" {
 
 const char* ftcg_status_string(ftcg_status s) {
@@ -234,6 +252,36 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     }
     // 2) weights (caller order)
     p->alpha.ensure(sizeof(double) * m);
+    const int64_t cap = m << p->dim;  // worst case 2^dim tile records per sample
+    const size_t rsz = p->dtype == FTCG_F64 ? sizeof(Rec<double>) : sizeof(Rec<float>);
+    const size_t asz = p->dtype == FTCG_F64 ? sizeof(double) : sizeof(float);
+    if (fused_binning_ok(p)) {
+      // tile records and the bin-row sort of the weight sum from the same
+      // passes over the samples; the records get their weights afterwards
+      setup_weight_bins(p, kmin, kmax);
+      p->recs.ensure(rsz * cap);
+      p->alpha_s.ensure(asz * cap);
+      p->tile_off.ensure(sizeof(int32_t) * (p->ntiles + 1));
+      bin_points_fused(p, k_dev);
+      timing_end(p, STEP_BIN);
+      timing_begin(p, STEP_WBIN);
+      sort_weight_rows(p);
+      timing_end(p, STEP_WBIN);
+      p->have_wbins = true;
+      if (p->wmode == FTCG_W_PLAIN) {
+        run_plain_weights(p);
+      } else {
+        if (!p->mlp) throw StatusError{FTCG_ESTATE};
+        run_learned_with_audit(p, k_dev);
+      }
+      p->have_weights = true;
+      timing_begin(p, STEP_BIN);
+      refill_alpha_dev(p);
+      timing_end(p, STEP_BIN);
+      p->nrec = -1;
+      p->have_points = true;
+      return;
+    }
     if (p->wmode == FTCG_W_PLAIN) {
       timing_end(p, STEP_BIN);
       build_weight_bins(p, k_dev, kmin, kmax);
@@ -244,18 +292,7 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
       if (!p->mlp) throw StatusError{FTCG_ESTATE};
       timing_end(p, STEP_BIN);
       build_weight_bins(p, k_dev, kmin, kmax);
-      timing_begin(p, STEP_LEARNED);
-      launch_learned_weights(p, k_dev, p->mlp);
-      timing_end(p, STEP_LEARNED);
-      timing_begin(p, STEP_AUDIT);
-      double* est_dev = p->flags.as<double>() + 6;
-      launch_audit(p, k_dev, est_dev);
-      FTCG_HIP(hipMemcpyAsync(p->host_flags + 6, est_dev, sizeof(double), hipMemcpyDeviceToHost, p->stream));
-      FTCG_HIP(hipStreamSynchronize(p->stream));
-      timing_end(p, STEP_AUDIT);
-      p->audit_estimate = p->host_flags[6];
-      p->used_fallback = !(p->audit_estimate <= p->audit_threshold);
-      if (p->used_fallback) run_plain_weights(p);
+      run_learned_with_audit(p, k_dev);
       timing_begin(p, STEP_BIN);
       p->have_weights = true;
     } else if (p->wmode == FTCG_W_NONE) {
@@ -267,10 +304,7 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
       p->have_points = true;
       return;
     }
-    // 3) tile binning of spread records (worst case 2^dim records per sample)
-    const int64_t cap = m << p->dim;
-    const size_t rsz = p->dtype == FTCG_F64 ? sizeof(Rec<double>) : sizeof(Rec<float>);
-    const size_t asz = p->dtype == FTCG_F64 ? sizeof(double) : sizeof(float);
+    // 3) tile binning of spread records
     p->recs.ensure(rsz * cap);
     p->alpha_s.ensure(asz * cap);
     p->tile_off.ensure(sizeof(int32_t) * (p->ntiles + 1));

@@ -11,6 +11,7 @@
 // once to the spread precision), so the float32 path never handles absolute
 // grid coordinates.
 #include "ftcg_internal.h"
+#include "wbins.h"
 
 namespace ftcg {
 
@@ -295,6 +296,127 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tile_scatter_lds(const double* __
   }
 }
 
+// Tile binning fused with the first steps of the 2D neighbour binning (the
+// bin-row counting sort of the weight sum): one pass counts each sample's
+// tile records and its bin row in two LDS histograms, one launch scans both
+// counter arrays, and one pass claims ranges for both and writes the tile
+// records (without weights: the weights are computed after this pass) and
+// the row-grouped samples. Samples are read once per pass instead of twice.
+template <class real>
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin2_count(const double* __restrict__ k, int64_t m, TileGeom tg,
+                                                          WBinGeom wg, int32_t* __restrict__ tile_cnt, int ntiles,
+                                                          int32_t* __restrict__ row_cnt) {
+  __shared__ int32_t ht[LDS_TILE_KEYS];
+  __shared__ int32_t hr[4096];
+  const int nrow = wg.nb[0];
+  for (int i = threadIdx.x; i < ntiles; i += BIN_BLOCK) ht[i] = 0;
+  for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) hr[i] = 0;
+  const int64_t j0 = (int64_t)blockIdx.x * BIN_IPT * BIN_BLOCK;
+  double u[BIN_IPT][2];
+  int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
+  block_keys<2>(k, m, tg, j0, u, c, key, l0, l1);
+  int row[BIN_IPT];
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i) {
+    const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
+    int b1;
+    double x[2];
+    row[i] = j < m ? wbin_row_col(k, j, wg, &b1, x) : -1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) agg_atomic_add(ht, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
+    if (row[i] >= 0) atomicAdd(&hr[row[i]], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ntiles; i += BIN_BLOCK) {
+    const int v = ht[i];
+    if (v) atomicAdd(&tile_cnt[i], v);
+  }
+  for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) {
+    const int v = hr[i];
+    if (v) atomicAdd(&row_cnt[i], v);
+  }
+}
+
+template <class real>
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin2_scatter(const double* __restrict__ k, int64_t m, TileGeom tg,
+                                                            WBinGeom wg, int32_t* __restrict__ tile_cursor,
+                                                            int ntiles, int32_t* __restrict__ row_cursor,
+                                                            Rec<real>* __restrict__ recs,
+                                                            RowRec* __restrict__ rowbuf) {
+  __shared__ int32_t bt[LDS_TILE_KEYS];
+  __shared__ int32_t br[4096];
+  const int nrow = wg.nb[0];
+  for (int i = threadIdx.x; i < ntiles; i += BIN_BLOCK) bt[i] = 0;
+  for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) br[i] = 0;
+  const int64_t j0 = (int64_t)blockIdx.x * BIN_IPT * BIN_BLOCK;
+  double u[BIN_IPT][2];
+  int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
+  block_keys<2>(k, m, tg, j0, u, c, key, l0, l1);
+  int row[BIN_IPT], col[BIN_IPT];
+  double x[BIN_IPT][2];
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i) {
+    const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
+    row[i] = j < m ? wbin_row_col(k, j, wg, &col[i], x[i]) : -1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) agg_atomic_add(bt, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
+    if (row[i] >= 0) atomicAdd(&br[row[i]], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ntiles; i += BIN_BLOCK) {
+    const int v = bt[i];
+    if (v) bt[i] = atomicAdd(&tile_cursor[i], v);
+  }
+  for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) {
+    const int v = br[i];
+    if (v) br[i] = atomicAdd(&row_cursor[i], v);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i) {
+    const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
+    Rec<real> r;
+    r.f0 = (real)(u[i][0] - (double)c[i][0]);
+    r.f1 = (real)(u[i][1] - (double)c[i][1]);
+    r.src = (int32_t)j;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int pos = agg_atomic_add(bt, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
+      if (key[i][q] >= 0) {
+        r.c01 = (int32_t)(((uint32_t)l0[i][q] & 0xffffu) | ((uint32_t)l1[i][q] << 16));
+        recs[pos] = r;
+      }
+    }
+    if (row[i] >= 0) {
+      RowRec rr;
+      rr.k0 = x[i][0];
+      rr.k1 = x[i][1];
+      rr.j = (int32_t)j;
+      rr.b1 = col[i];
+      rowbuf[atomicAdd(&br[row[i]], 1)] = rr;
+    }
+  }
+}
+
+// record-order weights, record count read on the device
+template <class real>
+__global__ __launch_bounds__(BIN_BLOCK) void k_refill_alpha_dev(const Rec<real>* __restrict__ recs,
+                                                                const int32_t* __restrict__ nrec_dev,
+                                                                const double* __restrict__ alpha,
+                                                                real* __restrict__ alpha_s) {
+  const int64_t nrec = *nrec_dev;
+  for (int64_t r = (int64_t)blockIdx.x * BIN_BLOCK + threadIdx.x; r < nrec; r += (int64_t)gridDim.x * BIN_BLOCK)
+    alpha_s[r] = (real)alpha[recs[r].src];
+}
+
 template <class real>
 __global__ __launch_bounds__(BIN_BLOCK) void k_refill_alpha(const Rec<real>* __restrict__ recs, int64_t nrec,
                                                             const double* __restrict__ alpha,
@@ -352,6 +474,48 @@ static void bin_points_t(ftcg_plan p, const double* k) {
       hipLaunchKernelGGL((k_tile_scatter<2, real>), dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, alpha, cnt,
                          p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
   }
+  FTCG_HIP(hipGetLastError());
+}
+
+bool fused_binning_ok(ftcg_plan p) {
+  return p->dim == 2 && (p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED) && !p->weights_only &&
+         p->ntiles <= LDS_TILE_KEYS;
+}
+
+template <class real>
+static void bin_points_fused_t(ftcg_plan p, const double* k) {
+  const TileGeom tg = tile_geom(p);
+  const WBinGeom& wg = p->wgeom;
+  hipStream_t s = p->stream;
+  const int64_t m = p->m;
+  int32_t* tcnt = p->tile_cnt.as<int32_t>();   // zeroed by the input check
+  int32_t* rcnt = p->wb_cnt.as<int32_t>();     // zeroed by the input check
+  const unsigned nb = (unsigned)((m + BIN_IPT * BIN_BLOCK - 1) / (BIN_IPT * BIN_BLOCK));
+  hipLaunchKernelGGL(k_bin2_count<real>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, tg, wg, tcnt, (int)p->ntiles, rcnt);
+  exclusive_scan_pair_i32(tcnt, p->tile_off.as<int32_t>(), p->ntiles, tcnt, rcnt, p->wb_rowoff.as<int32_t>(),
+                          wg.nb[0], rcnt, s);
+  hipLaunchKernelGGL(k_bin2_scatter<real>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, tg, wg, tcnt, (int)p->ntiles,
+                     rcnt, p->recs.as<Rec<real>>(), p->wb_rowbuf.as<RowRec>());
+  FTCG_HIP(hipGetLastError());
+}
+
+void bin_points_fused(ftcg_plan p, const double* k) {
+  if (p->dtype == FTCG_F64)
+    bin_points_fused_t<double>(p, k);
+  else
+    bin_points_fused_t<float>(p, k);
+}
+
+void refill_alpha_dev(ftcg_plan p) {
+  int64_t nb = ((p->m << p->dim) + BIN_BLOCK - 1) / BIN_BLOCK;
+  if (nb > 2048) nb = 2048;
+  const int32_t* nrec = p->tile_off.as<int32_t>() + p->ntiles;
+  if (p->dtype == FTCG_F64)
+    hipLaunchKernelGGL(k_refill_alpha_dev<double>, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream,
+                       p->recs.as<Rec<double>>(), nrec, p->alpha.as<double>(), p->alpha_s.as<double>());
+  else
+    hipLaunchKernelGGL(k_refill_alpha_dev<float>, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream,
+                       p->recs.as<Rec<float>>(), nrec, p->alpha.as<double>(), p->alpha_s.as<float>());
   FTCG_HIP(hipGetLastError());
 }
 

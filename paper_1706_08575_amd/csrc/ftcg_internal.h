@@ -241,6 +241,13 @@ int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long l
                         int64_t zero_na, int32_t* zero_b, int64_t zero_nb);
 void bin_points_k(ftcg_plan p, const double* k);   // fills recs, alpha_s, tile_off
 void refill_alpha(ftcg_plan p);                     // alpha_s[r] = alpha[recs[r].src]
+void refill_alpha_dev(ftcg_plan p);  // the same, record count read on the device (no host sync)
+// 2D, <= LDS_TILE_KEYS tiles: tile records and weight-bin rows from one
+// counting pass, one paired scan and one scatter pass
+bool fused_binning_ok(ftcg_plan p);
+void bin_points_fused(ftcg_plan p, const double* k);
+void setup_weight_bins(ftcg_plan p, const double* kmin, const double* kmax);
+void sort_weight_rows(ftcg_plan p);
 void build_weight_bins(ftcg_plan p, const double* k, const double* kmin,
                        const double* kmax);         // sorted neighbour bins (+ sin/cos)
 void run_plain_weights(ftcg_plan p);                // alpha (caller order) from the bins
@@ -254,6 +261,9 @@ void compute_deapod(ftcg_plan p);
 int64_t twiddle_entries(int64_t L);
 void compute_twiddles(void* tw, int64_t L, bool f64, hipStream_t s);
 int64_t plan_nrec(ftcg_plan p);  // records of the last set_points (one host sync)
+// two scans of up to 131072 entries each in one launch
+void exclusive_scan_pair_i32(const int32_t* in0, int32_t* out0, int64_t n0, int32_t* cursor0, const int32_t* in1,
+                             int32_t* out1, int64_t n1, int32_t* cursor1, hipStream_t s);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s,
                         int32_t* cursor = nullptr);
 size_t scan_tmp_bytes(int64_t n);

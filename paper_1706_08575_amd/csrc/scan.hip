@@ -113,8 +113,7 @@ __device__ inline int32_t wave_inclusive_scan(int32_t v) {
 // entries; entry e sits at LDS word e + e / 16 (conflict-free at stride 16)
 __device__ inline int ss_pad(int e) { return e + (e >> 4); }
 
-__global__ __launch_bounds__(SS_BLOCK) void k_scan_single(const int32_t* in, int64_t n, int32_t* __restrict__ out,
-                                                          int32_t* cursor) {
+__device__ void scan_single_block(const int32_t* in, int64_t n, int32_t* __restrict__ out, int32_t* cursor) {
   constexpr int CH = SS_BLOCK * SS_ITEMS;
   __shared__ int32_t buf[CH + CH / 16];
   __shared__ int32_t wsum[SS_BLOCK / 64];
@@ -165,6 +164,29 @@ __global__ __launch_bounds__(SS_BLOCK) void k_scan_single(const int32_t* in, int
     __syncthreads();  // buf and wsum are rewritten by the next chunk
   }
   if (t == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(SS_BLOCK) void k_scan_single(const int32_t* in, int64_t n, int32_t* __restrict__ out,
+                                                          int32_t* cursor) {
+  scan_single_block(in, n, out, cursor);
+}
+
+// two independent single-workgroup scans in one launch (workgroup b scans
+// array b)
+__global__ __launch_bounds__(SS_BLOCK) void k_scan_pair(const int32_t* in0, int64_t n0, int32_t* __restrict__ out0,
+                                                        int32_t* cursor0, const int32_t* in1, int64_t n1,
+                                                        int32_t* __restrict__ out1, int32_t* cursor1) {
+  if (blockIdx.x == 0)
+    scan_single_block(in0, n0, out0, cursor0);
+  else
+    scan_single_block(in1, n1, out1, cursor1);
+}
+
+void exclusive_scan_pair_i32(const int32_t* in0, int32_t* out0, int64_t n0, int32_t* cursor0, const int32_t* in1,
+                             int32_t* out1, int64_t n1, int32_t* cursor1, hipStream_t s) {
+  if (n0 > SCAN_SINGLE_MAX || n1 > SCAN_SINGLE_MAX) throw StatusError{FTCG_EUNSUPPORTED};
+  hipLaunchKernelGGL(k_scan_pair, dim3(2), dim3(SS_BLOCK), 0, s, in0, n0, out0, cursor0, in1, n1, out1, cursor1);
+  FTCG_HIP(hipGetLastError());
 }
 
 size_t scan_tmp_bytes(int64_t n) {

@@ -18,22 +18,12 @@
 // sin(pi (k_i - k_n)) = sin(pi k_i) cos(pi k_n) - cos(pi k_i) sin(pi k_n)
 // instead of a transcendental, and one float64 reciprocal.
 #include "ftcg_internal.h"
+#include "wbins.h"
 
 namespace ftcg {
 
 constexpr int WB_BLOCK = 256;
 
-template <int DIM>
-__device__ inline int wbin_of(const double* x, const WBinGeom& g, int* b) {
-  int id = 0;
-  for (int a = 0; a < DIM; ++a) {
-    int v = (int)floor((x[a] - g.kmin[a]) / g.h);
-    v = v < 0 ? 0 : (v >= g.nb[a] ? g.nb[a] - 1 : v);
-    b[a] = v;
-    id = id * g.nb[a] + v;
-  }
-  return id;
-}
 
 // Counting sort into neighbour bins. Bins hold a few samples each, so the
 // lanes of a wavefront mostly hit different bins: plain per-lane atomics (one
@@ -353,20 +343,6 @@ static WBinGeom wbin_geom(ftcg_plan p, const double* kmin, const double* kmax) {
 constexpr int WROW_IPT = 4;
 constexpr int WROW_LMAX = 16384;   // rows up to this many samples are ordered in LDS
 
-struct RowRec {
-  double k0, k1;
-  int32_t j, b1;
-};
-
-__device__ inline int wbin_row_col(const double* __restrict__ k, int64_t j, const WBinGeom& g, int* b1,
-                                   double* x) {
-  x[0] = k[2 * j];
-  x[1] = k[2 * j + 1];
-  int b[2];
-  wbin_of<2>(x, g, b);
-  *b1 = b[1];
-  return b[0];
-}
 
 __global__ __launch_bounds__(WB_BLOCK) void k_wrow_count(const double* __restrict__ k, int64_t m, WBinGeom g,
                                                          int32_t* __restrict__ row_cnt) {
@@ -509,25 +485,46 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_
   }
 }
 
-void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const double* kmax) {
+void setup_weight_bins(ftcg_plan p, const double* kmin, const double* kmax) {
   const WBinGeom g = wbin_geom(p, kmin, kmax);
   p->wgeom = g;
+  const int64_t m = p->m;
+  const int64_t nbins = (int64_t)g.nb[0] * g.nb[1];
+  p->wb_off.ensure(sizeof(int32_t) * (nbins + 1));
+  p->wb_of.ensure(sizeof(int32_t) * m);
+  p->ws_k.ensure(sizeof(double) * m * p->dim * 3);
+  p->ws_idx.ensure(sizeof(int32_t) * m);
+  p->ws_inv.ensure(sizeof(int32_t) * m);
+  if (p->dim == 2) {
+    p->wb_rowoff.ensure(sizeof(int32_t) * (g.nb[0] + 1));
+    p->wb_rowbuf.ensure(sizeof(RowRec) * m);
+  }
+}
+
+// step 4 of the 2D binning (rows placed by steps 1-3, here or fused with the
+// tile binning)
+void sort_weight_rows(ftcg_plan p) {
+  const WBinGeom& g = p->wgeom;
+  // the inverse map serves the learned features and the audit only
+  const bool need_inv = p->wmode == FTCG_W_LEARNED || p->weights_only;
+  hipLaunchKernelGGL(k_wrow_sort, dim3((unsigned)g.nb[0]), dim3(WB_BLOCK), 0, p->stream, g,
+                     p->wb_rowoff.as<int32_t>(), p->wb_rowbuf.as<RowRec>(), p->wb_off.as<int32_t>(),
+                     p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), need_inv ? p->ws_inv.as<int32_t>() : nullptr);
+  FTCG_HIP(hipGetLastError());
+}
+
+void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const double* kmax) {
+  setup_weight_bins(p, kmin, kmax);
+  const WBinGeom g = p->wgeom;
   const int64_t m = p->m;
   const int dim = p->dim;
   const int64_t nbins = (int64_t)g.nb[0] * g.nb[1];
   hipStream_t s = p->stream;
-  p->wb_off.ensure(sizeof(int32_t) * (nbins + 1));
-  p->wb_of.ensure(sizeof(int32_t) * m);
-  p->ws_k.ensure(sizeof(double) * m * dim * 3);
-  p->ws_idx.ensure(sizeof(int32_t) * m);
-  p->ws_inv.ensure(sizeof(int32_t) * m);
   int32_t* off = p->wb_off.as<int32_t>();
   timing_begin(p, STEP_WBIN);
   if (dim == 2) {
     // row counters: zeroed by the input check (WROW_CNT_ZERO entries)
     int32_t* row_cnt = p->wb_cnt.as<int32_t>();
-    p->wb_rowoff.ensure(sizeof(int32_t) * (g.nb[0] + 1));
-    p->wb_rowbuf.ensure(sizeof(RowRec) * m);
     p->scan_tmp.ensure(scan_tmp_bytes(g.nb[0]));
     int32_t* row_off = p->wb_rowoff.as<int32_t>();
     const unsigned nb = (unsigned)((m + WROW_IPT * WB_BLOCK - 1) / (WROW_IPT * WB_BLOCK));
@@ -535,11 +532,7 @@ void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const d
     exclusive_scan_i32(row_cnt, row_off, g.nb[0], p->scan_tmp.as<int32_t>(), s, row_cnt);
     hipLaunchKernelGGL(k_wrow_scatter, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, row_cnt,
                        p->wb_rowbuf.as<RowRec>());
-    // the inverse map serves the learned features and the audit only
-    const bool need_inv = p->wmode == FTCG_W_LEARNED || p->weights_only;
-    hipLaunchKernelGGL(k_wrow_sort, dim3((unsigned)g.nb[0]), dim3(WB_BLOCK), 0, s, g, row_off,
-                       p->wb_rowbuf.as<RowRec>(), off, p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(),
-                       need_inv ? p->ws_inv.as<int32_t>() : nullptr);
+    sort_weight_rows(p);
   } else {
     const size_t cnt_bytes = sizeof(int32_t) * ((nbins + 4) & ~int64_t(3));  // 16-byte multiple: one fill
     p->wb_cnt.ensure(cnt_bytes);
