@@ -89,7 +89,8 @@ def step_bytes(step, m, nrec, n, G, dim, dtype):
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` on `workload` from the committed counter
     table (profiles/pmc_traffic.md), or None when there is no row for it or the
-    kernel's sources changed since the counters were taken."""
+    kernel's sources changed since the counters were taken. A name ending in
+    '<' matches the one instantiation of that template the workload ran."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "pmc_traffic.md")
@@ -99,7 +100,9 @@ def measured_traffic(kernel: str, workload: str):
         return None
     for line in lines:
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) != 8 or cells[0] != kernel or cells[2] != workload:
+        if len(cells) != 8 or cells[2] != workload:
+            continue
+        if not (cells[0] == kernel or (kernel.endswith("<") and cells[0].startswith(kernel))):
             continue
         h = hashlib.sha256()
         try:
@@ -111,7 +114,7 @@ def measured_traffic(kernel: str, workload: str):
         if h.hexdigest()[:16] != cells[6]:
             return None
         return {"bytes": float(cells[5]), "fetch_kib": float(cells[3]), "write_kib": float(cells[4]),
-                "source": "profiles/pmc_traffic.md"}
+                "kernel": cells[0], "source": "profiles/pmc_traffic.md"}
     return None
 
 
@@ -393,8 +396,9 @@ def main():
         pairs = count_box_pairs(k, 8.0, sample=None if m <= 200_000 else 20000)
         flops = pairs * FLOPS_PER_PAIR[dim]
         ach = flops / (stage_ms[dom] * 1e-3) / 1e12
-        kname = "k_frame_weights_rows<1>" if dim == 2 else "k_frame_weights_1d<1>"
+        kname = "k_frame_weights_rows<" if dim == 2 else "k_frame_weights_1d<"
         tr = measured_traffic(kname, args.workload)
+        kname = tr["kernel"] if tr else kname + "...>"
         roof = {"kernel": kname, "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": tr["bytes"] if tr else None,
                 "work_per_launch": f"{pairs} in-box pairs x {FLOPS_PER_PAIR[dim]} FP64 flops",

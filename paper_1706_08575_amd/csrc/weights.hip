@@ -109,26 +109,49 @@ __device__ inline double pair_term(const WSample<DIM>& o, const double* x, const
   return __hiloint2double(hi, __double2loint(t));
 }
 
+// a candidate record; 2D records (48 bytes) sit in 16-byte aligned arrays
+// and are read as three 16-byte words
+template <int DIM>
+__device__ inline WSample<DIM> ld_wsample(const WSample<DIM>* p) {
+  if constexpr (DIM == 2) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    const double2 v0 = q[0], v1 = q[1], v2 = q[2];
+    WSample<2> w;
+    w.k[0] = v0.x;
+    w.k[1] = v0.y;
+    w.sc[0][0] = v1.x;
+    w.sc[0][1] = v1.y;
+    w.sc[1][0] = v2.x;
+    w.sc[1][1] = v2.y;
+    return w;
+  } else {
+    return *p;
+  }
+}
+
 // Adds to acc[u] the pi^(2 DIM) T_in^2 of every candidate i in [beg, end) for the NT
-// samples u. Candidates alternate between two register sets, each loaded
-// while the other one's pair terms are formed.
+// samples u: two candidates per step (both loaded before either pair term
+// is formed), then at most one more.
 template <int DIM, int NT>
 __device__ inline void range_sum(const WSample<DIM>* __restrict__ ss, int beg, int end, const double (&x)[NT][DIM],
                                  const double (&sn)[NT][DIM], const double (&cs)[NT][DIM], double R,
                                  double (&acc)[NT]) {
-  if (beg >= end) return;
-  WSample<DIM> a = ss[beg];
-  for (int i = beg; i < end; i += 2) {
-    const bool has_b = i + 1 < end;
-    const WSample<DIM> b = ss[has_b ? i + 1 : i];
-#pragma unroll
-    for (int u = 0; u < NT; ++u) acc[u] += pair_term<DIM>(a, x[u], sn[u], cs[u], R);
-    a = ss[i + 2 < end ? i + 2 : i];
+  const WSample<DIM>* p = ss + beg;
+  const WSample<DIM>* const pe = ss + end;
+  for (; p + 1 < pe; p += 2) {
+    const WSample<DIM> a = ld_wsample(p);
+    const WSample<DIM> b = ld_wsample(p + 1);
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
-      const double t = pair_term<DIM>(b, x[u], sn[u], cs[u], R);
-      acc[u] += has_b ? t : 0.0;
+      const double ta = pair_term<DIM>(a, x[u], sn[u], cs[u], R);
+      const double tb = pair_term<DIM>(b, x[u], sn[u], cs[u], R);
+      acc[u] += ta + tb;
     }
+  }
+  if (p < pe) {
+    const WSample<DIM> a = ld_wsample(p);
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[u] += pair_term<DIM>(a, x[u], sn[u], cs[u], R);
   }
 }
 
