@@ -154,13 +154,18 @@ __device__ inline int agg_atomic_add(int32_t* counters, int key, bool valid) {
 // every part of the range, which keeps the XCDs evenly loaded when the cost of
 // a block varies along it. Blocks past the last whole group of 8 chunks keep
 // the plain order.
-__device__ inline int64_t xcd_block(int64_t b, int64_t nblocks) {
-  int64_t C = nblocks >> 6;
-  C = C < 1 ? 1 : (C > 64 ? 64 : C);
+// The same with a chunk length chosen by the caller (C >= 1).
+__device__ inline int64_t xcd_block_chunk(int64_t b, int64_t nblocks, int64_t C) {
   const int64_t full = nblocks / (8 * C) * (8 * C);
   if (b >= full) return b;
   const int64_t x = b & 7, i = b >> 3;
   return ((i / C) * 8 + x) * C + (i % C);
+}
+
+__device__ inline int64_t xcd_block(int64_t b, int64_t nblocks) {
+  int64_t C = nblocks >> 6;
+  C = C < 1 ? 1 : (C > 64 ? 64 : C);
+  return xcd_block_chunk(b, nblocks, C);
 }
 
 }  // namespace ftcg

@@ -204,10 +204,10 @@ template <int WT, int S>
 __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_rows(const WSample<2>* __restrict__ ss,
                                                                  const int32_t* __restrict__ sidx,
                                                                  const int32_t* __restrict__ boff, WBinGeom g,
-                                                                 int cx, double* __restrict__ alpha) {
+                                                                 int cx, int chunk, double* __restrict__ alpha) {
   constexpr int RUN = WB_BLOCK * WT / S;   // samples per workgroup run
   __shared__ __align__(16) WSample<2> cand[WCH];
-  const int64_t lid = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t lid = xcd_block_chunk(blockIdx.x, gridDim.x, chunk);
   const int b0 = (int)(lid / cx), bx = (int)(lid % cx);
   const int nb1 = g.nb[1];
   const int rs = boff[b0 * nb1], re = boff[(b0 + 1) * nb1];
@@ -581,8 +581,12 @@ static void launch_weights_rows(ftcg_plan p) {
   // about one step while empty rows cost only idle workgroups
   const int cx = (int)std::max<int64_t>(1, (2 * runs + g.nb[0] - 1) / g.nb[0]);
   const int64_t nb = (int64_t)cx * g.nb[0];
+  // XCD chunks of whole bands of nb0 / 64 bin rows: the rows a band stages
+  // (its own and s more on each side) stay in one XCD's L2, and every XCD
+  // still gets 8 bands spread over the raster
+  const int chunk = cx * std::max(1, g.nb[0] / 64);
   hipLaunchKernelGGL((k_frame_weights_rows<WT, S>), dim3((unsigned)nb), dim3(WB_BLOCK), 0, p->stream,
-                     p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), g, cx,
+                     p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), g, cx, chunk,
                      p->alpha.as<double>());
 }
 
