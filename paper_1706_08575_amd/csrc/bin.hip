@@ -218,11 +218,30 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tile_scatter(const double* __rest
 // The same two steps with the counters privatised in LDS, for up to
 // LDS_TILE_KEYS tiles: a workgroup takes BIN_IPT * BIN_BLOCK consecutive
 // samples (coalesced, all loads issued before the first count), counts their
-// records in LDS (wavefront-aggregated LDS atomics), and only then touches the
-// global counters, once per tile it saw. The scatter claims one range per
-// tile with that count and hands out positions inside it from LDS.
+// records in LDS, and only then touches the global counters, once per tile
+// it saw. The scatter claims one range per tile with that count and hands
+// out positions inside it from LDS. The LDS counters take one atomic per
+// lane: lanes of a wavefront that hit the same counter are serialised inside
+// that one instruction, and the atomics of all of a thread's records are in
+// flight together (a wavefront-aggregated increment would wait for each
+// distinct key's result in turn).
 constexpr int BIN_IPT = 4;
-constexpr int LDS_TILE_KEYS = 4096;
+constexpr int LDS_TILE_KEYS = 4096;   // 16 KiB of int32 counters (larger tables cost more LDS
+                                      // occupancy than the global counters they replace)
+
+// Slot claims take no branch (so all of them are issued before the first
+// result is used): a lane without a key adds to its own spare counter in the
+// 64 words past the live ones, at index spare + lane.
+constexpr int LDS_SPARE = 64;
+__device__ inline int lds_claim(int32_t* cnt, int key, int spare) {
+  return atomicAdd(&cnt[key >= 0 ? key : spare + (int)__lane_id()], 1);
+}
+
+// rounds of BIN_IPT * BIN_BLOCK samples per workgroup: about one sample per
+// LDS counter cleared and flushed, at most 8 rounds
+static int bin_rounds(int64_t ncounters) {
+  return (int)std::min<int64_t>(8, std::max<int64_t>(1, ncounters / (BIN_IPT * BIN_BLOCK)));
+}
 
 template <int DIM>
 __device__ inline void block_keys(const double* __restrict__ k, int64_t m, const TileGeom& g, int64_t j0,
@@ -233,19 +252,25 @@ __device__ inline void block_keys(const double* __restrict__ k, int64_t m, const
     sample_keys<DIM>(k, j0 + (int64_t)i * BIN_BLOCK + threadIdx.x, m, g, u[i], c[i], key[i], l0[i], l1[i]);
 }
 
+// A workgroup takes `rounds` consecutive groups of BIN_IPT * BIN_BLOCK
+// samples, so the clearing and flushing of its LDS counters is spread over
+// rounds * BIN_IPT * BIN_BLOCK samples (rounds > 1 for large key counts).
 template <int DIM>
 __global__ __launch_bounds__(BIN_BLOCK) void k_tile_count_lds(const double* __restrict__ k, int64_t m, TileGeom g,
-                                                              int32_t* __restrict__ cnt, int nkeys) {
+                                                              int32_t* __restrict__ cnt, int nkeys, int rounds) {
   extern __shared__ int32_t hist[];
   for (int i = threadIdx.x; i < nkeys; i += BIN_BLOCK) hist[i] = 0;
-  double u[BIN_IPT][DIM];
-  int c[BIN_IPT][DIM], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
-  block_keys<DIM>(k, m, g, (int64_t)blockIdx.x * BIN_IPT * BIN_BLOCK, u, c, key, l0, l1);
   __syncthreads();
+  for (int rd = 0; rd < rounds; ++rd) {
+    double u[BIN_IPT][DIM];
+    int c[BIN_IPT][DIM], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
+    block_keys<DIM>(k, m, g, ((int64_t)blockIdx.x * rounds + rd) * BIN_IPT * BIN_BLOCK, u, c, key, l0, l1);
 #pragma unroll
-  for (int i = 0; i < BIN_IPT; ++i)
+    for (int i = 0; i < BIN_IPT; ++i)
 #pragma unroll
-    for (int q = 0; q < (1 << DIM); ++q) agg_atomic_add(hist, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
+      for (int q = 0; q < (1 << DIM); ++q)
+        if (key[i][q] >= 0) atomicAdd(&hist[key[i][q]], 1);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < nkeys; i += BIN_BLOCK) {
     const int v = hist[i];
@@ -256,41 +281,53 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tile_count_lds(const double* __re
 template <int DIM, class real>
 __global__ __launch_bounds__(BIN_BLOCK) void k_tile_scatter_lds(const double* __restrict__ k, int64_t m, TileGeom g,
                                                                 const double* __restrict__ alpha,
-                                                                int32_t* __restrict__ cursor, int nkeys,
+                                                                int32_t* __restrict__ cursor, int nkeys, int rounds,
                                                                 Rec<real>* __restrict__ recs,
                                                                 real* __restrict__ alpha_s) {
-  extern __shared__ int32_t base[];
+  extern __shared__ int32_t base[];   // nkeys counters, then LDS_SPARE spare words
   for (int i = threadIdx.x; i < nkeys; i += BIN_BLOCK) base[i] = 0;
-  const int64_t j0 = (int64_t)blockIdx.x * BIN_IPT * BIN_BLOCK;
-  double u[BIN_IPT][DIM];
-  int c[BIN_IPT][DIM], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
-  block_keys<DIM>(k, m, g, j0, u, c, key, l0, l1);
   __syncthreads();
+  for (int rd = 0; rd < rounds; ++rd) {
+    double u[BIN_IPT][DIM];
+    int c[BIN_IPT][DIM], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
+    block_keys<DIM>(k, m, g, ((int64_t)blockIdx.x * rounds + rd) * BIN_IPT * BIN_BLOCK, u, c, key, l0, l1);
 #pragma unroll
-  for (int i = 0; i < BIN_IPT; ++i)
+    for (int i = 0; i < BIN_IPT; ++i)
 #pragma unroll
-    for (int q = 0; q < (1 << DIM); ++q) agg_atomic_add(base, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
+      for (int q = 0; q < (1 << DIM); ++q)
+        if (key[i][q] >= 0) atomicAdd(&base[key[i][q]], 1);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < nkeys; i += BIN_BLOCK) {
     const int v = base[i];
     if (v) base[i] = atomicAdd(&cursor[i], v);
   }
   __syncthreads();
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int64_t j0 = ((int64_t)blockIdx.x * rounds + rd) * BIN_IPT * BIN_BLOCK;
+    double u[BIN_IPT][DIM];
+    int c[BIN_IPT][DIM], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
+    block_keys<DIM>(k, m, g, j0, u, c, key, l0, l1);
+    int pos[BIN_IPT][4];
 #pragma unroll
-  for (int i = 0; i < BIN_IPT; ++i) {
-    const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
-    const real a = (j < m && alpha) ? (real)alpha[j] : (real)1;
-    Rec<real> r;
-    r.f0 = (real)(u[i][0] - (double)c[i][0]);
-    r.f1 = (DIM == 2) ? (real)(u[i][DIM - 1] - (double)c[i][DIM - 1]) : (real)0;
-    r.src = (int32_t)j;
+    for (int i = 0; i < BIN_IPT; ++i)
 #pragma unroll
-    for (int q = 0; q < (1 << DIM); ++q) {
-      const int pos = agg_atomic_add(base, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
-      if (key[i][q] >= 0) {
-        r.c01 = (int32_t)(((uint32_t)l0[i][q] & 0xffffu) | ((uint32_t)l1[i][q] << 16));
-        recs[pos] = r;
-        alpha_s[pos] = a;
+      for (int q = 0; q < (1 << DIM); ++q) pos[i][q] = lds_claim(base, key[i][q], nkeys);
+#pragma unroll
+    for (int i = 0; i < BIN_IPT; ++i) {
+      const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
+      const real a = (j < m && alpha) ? (real)alpha[j] : (real)1;
+      Rec<real> r;
+      r.f0 = (real)(u[i][0] - (double)c[i][0]);
+      r.f1 = (DIM == 2) ? (real)(u[i][DIM - 1] - (double)c[i][DIM - 1]) : (real)0;
+      r.src = (int32_t)j;
+#pragma unroll
+      for (int q = 0; q < (1 << DIM); ++q) {
+        if (key[i][q] >= 0) {
+          r.c01 = (int32_t)(((uint32_t)l0[i][q] & 0xffffu) | ((uint32_t)l1[i][q] << 16));
+          recs[pos[i][q]] = r;
+          alpha_s[pos[i][q]] = a;
+        }
       }
     }
   }
@@ -298,37 +335,45 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tile_scatter_lds(const double* __
 
 // Tile binning fused with the first steps of the 2D neighbour binning (the
 // bin-row counting sort of the weight sum): one pass counts each sample's
-// tile records and its bin row in two LDS histograms, one launch scans both
-// counter arrays, and one pass claims ranges for both and writes the tile
-// records (without weights: the weights are computed after this pass) and
-// the row-grouped samples. Samples are read once per pass instead of twice.
-template <class real>
-__global__ __launch_bounds__(BIN_BLOCK) void k_bin2_count(const double* __restrict__ k, int64_t m, TileGeom tg,
-                                                          WBinGeom wg, int32_t* __restrict__ tile_cnt, int ntiles,
-                                                          int32_t* __restrict__ row_cnt) {
-  __shared__ int32_t ht[LDS_TILE_KEYS];
-  __shared__ int32_t hr[4096];
-  const int nrow = wg.nb[0];
-  for (int i = threadIdx.x; i < ntiles; i += BIN_BLOCK) ht[i] = 0;
-  for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) hr[i] = 0;
-  const int64_t j0 = (int64_t)blockIdx.x * BIN_IPT * BIN_BLOCK;
-  double u[BIN_IPT][2];
-  int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
+// tile records and its bin row in two LDS histograms (tiles first, then the
+// <= 4096 rows), one launch scans both counter arrays, and one pass claims
+// ranges for both and writes the tile records (without weights: the weights
+// are computed after this pass) and the row-grouped samples. Samples are
+// read once per pass instead of twice.
+__device__ inline void bin2_keys(const double* __restrict__ k, int64_t m, const TileGeom& tg, const WBinGeom& wg,
+                                 int64_t j0, double (&u)[BIN_IPT][2], int (&c)[BIN_IPT][2], int (&key)[BIN_IPT][4],
+                                 int (&l0)[BIN_IPT][4], int (&l1)[BIN_IPT][4], int (&row)[BIN_IPT],
+                                 int (&col)[BIN_IPT], double (&x)[BIN_IPT][2]) {
   block_keys<2>(k, m, tg, j0, u, c, key, l0, l1);
-  int row[BIN_IPT];
 #pragma unroll
   for (int i = 0; i < BIN_IPT; ++i) {
     const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
-    int b1;
-    double x[2];
-    row[i] = j < m ? wbin_row_col(k, j, wg, &b1, x) : -1;
+    row[i] = j < m ? wbin_row_col(k, j, wg, &col[i], x[i]) : -1;
   }
+}
+
+template <class real>
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin2_count(const double* __restrict__ k, int64_t m, TileGeom tg,
+                                                          WBinGeom wg, int32_t* __restrict__ tile_cnt, int ntiles,
+                                                          int32_t* __restrict__ row_cnt, int rounds) {
+  extern __shared__ int32_t sm[];
+  int32_t* ht = sm;
+  int32_t* hr = sm + ntiles;
+  const int nrow = wg.nb[0];
+  for (int i = threadIdx.x; i < ntiles + nrow; i += BIN_BLOCK) sm[i] = 0;
   __syncthreads();
+  for (int rd = 0; rd < rounds; ++rd) {
+    double u[BIN_IPT][2], x[BIN_IPT][2];
+    int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4], row[BIN_IPT], col[BIN_IPT];
+    bin2_keys(k, m, tg, wg, ((int64_t)blockIdx.x * rounds + rd) * BIN_IPT * BIN_BLOCK, u, c, key, l0, l1, row, col,
+              x);
 #pragma unroll
-  for (int i = 0; i < BIN_IPT; ++i) {
+    for (int i = 0; i < BIN_IPT; ++i) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) agg_atomic_add(ht, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
-    if (row[i] >= 0) atomicAdd(&hr[row[i]], 1);
+      for (int q = 0; q < 4; ++q)
+        if (key[i][q] >= 0) atomicAdd(&ht[key[i][q]], 1);
+      if (row[i] >= 0) atomicAdd(&hr[row[i]], 1);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < ntiles; i += BIN_BLOCK) {
@@ -345,30 +390,26 @@ template <class real>
 __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_scatter(const double* __restrict__ k, int64_t m, TileGeom tg,
                                                             WBinGeom wg, int32_t* __restrict__ tile_cursor,
                                                             int ntiles, int32_t* __restrict__ row_cursor,
-                                                            Rec<real>* __restrict__ recs,
+                                                            int rounds, Rec<real>* __restrict__ recs,
                                                             RowRec* __restrict__ rowbuf) {
-  __shared__ int32_t bt[LDS_TILE_KEYS];
-  __shared__ int32_t br[4096];
+  extern __shared__ int32_t sm[];   // ntiles + nrow counters, then LDS_SPARE spare words
+  int32_t* bt = sm;
+  int32_t* br = sm + ntiles;
   const int nrow = wg.nb[0];
-  for (int i = threadIdx.x; i < ntiles; i += BIN_BLOCK) bt[i] = 0;
-  for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) br[i] = 0;
-  const int64_t j0 = (int64_t)blockIdx.x * BIN_IPT * BIN_BLOCK;
-  double u[BIN_IPT][2];
-  int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4];
-  block_keys<2>(k, m, tg, j0, u, c, key, l0, l1);
-  int row[BIN_IPT], col[BIN_IPT];
-  double x[BIN_IPT][2];
-#pragma unroll
-  for (int i = 0; i < BIN_IPT; ++i) {
-    const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
-    row[i] = j < m ? wbin_row_col(k, j, wg, &col[i], x[i]) : -1;
-  }
+  for (int i = threadIdx.x; i < ntiles + nrow; i += BIN_BLOCK) sm[i] = 0;
   __syncthreads();
+  for (int rd = 0; rd < rounds; ++rd) {
+    double u[BIN_IPT][2], x[BIN_IPT][2];
+    int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4], row[BIN_IPT], col[BIN_IPT];
+    bin2_keys(k, m, tg, wg, ((int64_t)blockIdx.x * rounds + rd) * BIN_IPT * BIN_BLOCK, u, c, key, l0, l1, row, col,
+              x);
 #pragma unroll
-  for (int i = 0; i < BIN_IPT; ++i) {
+    for (int i = 0; i < BIN_IPT; ++i) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) agg_atomic_add(bt, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
-    if (row[i] >= 0) atomicAdd(&br[row[i]], 1);
+      for (int q = 0; q < 4; ++q)
+        if (key[i][q] >= 0) atomicAdd(&bt[key[i][q]], 1);
+      if (row[i] >= 0) atomicAdd(&br[row[i]], 1);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < ntiles; i += BIN_BLOCK) {
@@ -380,28 +421,40 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_scatter(const double* __rest
     if (v) br[i] = atomicAdd(&row_cursor[i], v);
   }
   __syncthreads();
+  for (int rd = 0; rd < rounds; ++rd) {
+    const int64_t j0 = ((int64_t)blockIdx.x * rounds + rd) * BIN_IPT * BIN_BLOCK;
+    double u[BIN_IPT][2], x[BIN_IPT][2];
+    int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4], row[BIN_IPT], col[BIN_IPT];
+    bin2_keys(k, m, tg, wg, j0, u, c, key, l0, l1, row, col, x);
+    int pos[BIN_IPT][4], rpos[BIN_IPT];
 #pragma unroll
-  for (int i = 0; i < BIN_IPT; ++i) {
-    const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
-    Rec<real> r;
-    r.f0 = (real)(u[i][0] - (double)c[i][0]);
-    r.f1 = (real)(u[i][1] - (double)c[i][1]);
-    r.src = (int32_t)j;
+    for (int i = 0; i < BIN_IPT; ++i) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int pos = agg_atomic_add(bt, key[i][q] < 0 ? 0 : key[i][q], key[i][q] >= 0);
-      if (key[i][q] >= 0) {
-        r.c01 = (int32_t)(((uint32_t)l0[i][q] & 0xffffu) | ((uint32_t)l1[i][q] << 16));
-        recs[pos] = r;
-      }
+      for (int q = 0; q < 4; ++q) pos[i][q] = lds_claim(bt, key[i][q], ntiles + nrow);
+      rpos[i] = lds_claim(br, row[i], nrow);
     }
-    if (row[i] >= 0) {
-      RowRec rr;
-      rr.k0 = x[i][0];
-      rr.k1 = x[i][1];
-      rr.j = (int32_t)j;
-      rr.b1 = col[i];
-      rowbuf[atomicAdd(&br[row[i]], 1)] = rr;
+#pragma unroll
+    for (int i = 0; i < BIN_IPT; ++i) {
+      const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
+      Rec<real> r;
+      r.f0 = (real)(u[i][0] - (double)c[i][0]);
+      r.f1 = (real)(u[i][1] - (double)c[i][1]);
+      r.src = (int32_t)j;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (key[i][q] >= 0) {
+          r.c01 = (int32_t)(((uint32_t)l0[i][q] & 0xffffu) | ((uint32_t)l1[i][q] << 16));
+          recs[pos[i][q]] = r;
+        }
+      }
+      if (row[i] >= 0) {
+        RowRec rr;
+        rr.k0 = x[i][0];
+        rr.k1 = x[i][1];
+        rr.j = (int32_t)j;
+        rr.b1 = col[i];
+        rowbuf[rpos[i]] = rr;
+      }
     }
   }
 }
@@ -447,19 +500,21 @@ static void bin_points_t(ftcg_plan p, const double* k) {
   const double* alpha = p->have_weights ? p->alpha.as<double>() : nullptr;
   const int nkeys = (int)p->ntiles;
   if (nkeys <= LDS_TILE_KEYS) {
-    const unsigned nb = (unsigned)((m + BIN_IPT * BIN_BLOCK - 1) / (BIN_IPT * BIN_BLOCK));
-    const size_t lds = sizeof(int32_t) * nkeys;
+    const int rounds = bin_rounds(nkeys);
+    const int64_t per = (int64_t)rounds * BIN_IPT * BIN_BLOCK;
+    const unsigned nb = (unsigned)((m + per - 1) / per);
+    const size_t lds = sizeof(int32_t) * (nkeys + LDS_SPARE);
     if (p->dim == 1)
-      hipLaunchKernelGGL(k_tile_count_lds<1>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, cnt, nkeys);
+      hipLaunchKernelGGL(k_tile_count_lds<1>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, cnt, nkeys, rounds);
     else
-      hipLaunchKernelGGL(k_tile_count_lds<2>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, cnt, nkeys);
+      hipLaunchKernelGGL(k_tile_count_lds<2>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, cnt, nkeys, rounds);
     exclusive_scan_i32(cnt, off, p->ntiles, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
     if (p->dim == 1)
       hipLaunchKernelGGL((k_tile_scatter_lds<1, real>), dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, alpha, cnt,
-                         nkeys, p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
+                         nkeys, rounds, p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
     else
       hipLaunchKernelGGL((k_tile_scatter_lds<2, real>), dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, alpha, cnt,
-                         nkeys, p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
+                         nkeys, rounds, p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
   } else {
     const unsigned nb = (unsigned)((m + BIN_BLOCK - 1) / BIN_BLOCK);
     if (p->dim == 1)
@@ -490,12 +545,16 @@ static void bin_points_fused_t(ftcg_plan p, const double* k) {
   const int64_t m = p->m;
   int32_t* tcnt = p->tile_cnt.as<int32_t>();   // zeroed by the input check
   int32_t* rcnt = p->wb_cnt.as<int32_t>();     // zeroed by the input check
-  const unsigned nb = (unsigned)((m + BIN_IPT * BIN_BLOCK - 1) / (BIN_IPT * BIN_BLOCK));
-  hipLaunchKernelGGL(k_bin2_count<real>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, tg, wg, tcnt, (int)p->ntiles, rcnt);
+  const int rounds = bin_rounds(p->ntiles + wg.nb[0]);
+  const int64_t per = (int64_t)rounds * BIN_IPT * BIN_BLOCK;
+  const unsigned nb = (unsigned)((m + per - 1) / per);
+  const size_t lds = sizeof(int32_t) * (size_t)(p->ntiles + wg.nb[0] + LDS_SPARE);   // <= 32.25 KiB
+  hipLaunchKernelGGL(k_bin2_count<real>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, tg, wg, tcnt, (int)p->ntiles,
+                     rcnt, rounds);
   exclusive_scan_pair_i32(tcnt, p->tile_off.as<int32_t>(), p->ntiles, tcnt, rcnt, p->wb_rowoff.as<int32_t>(),
                           wg.nb[0], rcnt, s);
-  hipLaunchKernelGGL(k_bin2_scatter<real>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, tg, wg, tcnt, (int)p->ntiles,
-                     rcnt, p->recs.as<Rec<real>>(), p->wb_rowbuf.as<RowRec>());
+  hipLaunchKernelGGL(k_bin2_scatter<real>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, tg, wg, tcnt, (int)p->ntiles,
+                     rcnt, rounds, p->recs.as<Rec<real>>(), p->wb_rowbuf.as<RowRec>());
   FTCG_HIP(hipGetLastError());
 }
 
