@@ -393,7 +393,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_count(const double* __restric
 __global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(const double* __restrict__ k, int64_t m, WBinGeom g,
                                                            int32_t* __restrict__ row_cursor,
                                                            RowRec* __restrict__ rowbuf) {
-  __shared__ int32_t base[4096];
+  __shared__ int32_t base[4096 + 64];   // row counters, then one spare word per lane
   const int nrow = g.nb[0];
   for (int i = threadIdx.x; i < nrow; i += WB_BLOCK) base[i] = 0;
   __syncthreads();
@@ -415,6 +415,11 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(const double* __restr
     if (v) base[i] = atomicAdd(&row_cursor[i], v);
   }
   __syncthreads();
+  // slots claimed without branches (a lane past the end adds to its spare
+  // word), so all claims are in flight before the first is used
+  int pos[WROW_IPT];
+#pragma unroll
+  for (int u = 0; u < WROW_IPT; ++u) pos[u] = atomicAdd(&base[row[u] >= 0 ? row[u] : 4096 + (int)__lane_id()], 1);
 #pragma unroll
   for (int u = 0; u < WROW_IPT; ++u) {
     const int64_t j = j0 + (int64_t)u * WB_BLOCK + threadIdx.x;
@@ -424,7 +429,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(const double* __restr
       r.k1 = x[u][1];
       r.j = (int32_t)j;
       r.b1 = col[u];
-      rowbuf[atomicAdd(&base[row[u]], 1)] = r;
+      rowbuf[pos[u]] = r;
     }
   }
 }
@@ -434,7 +439,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_
                                                         int32_t* __restrict__ boff, WSample<2>* __restrict__ ss,
                                                         int32_t* __restrict__ sidx, int32_t* __restrict__ inv) {
   constexpr int ITEMS = 4096 / WB_BLOCK;
-  __shared__ int32_t cnt[4096];
+  __shared__ int32_t cnt[4096 + 64];   // bin counters, then one spare word per lane
   __shared__ int32_t wsum[WB_BLOCK / 64];
   __shared__ uint16_t perm[WROW_LMAX];
   const int b0 = blockIdx.x, nb1 = g.nb[1];
@@ -442,7 +447,16 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_
   const int t = threadIdx.x;
   for (int i = t; i < nb1; i += WB_BLOCK) cnt[i] = 0;
   __syncthreads();
-  for (int i = rs + t; i < re; i += WB_BLOCK) atomicAdd(&cnt[rowbuf[i].b1], 1);
+  // (SU entries per thread per step: their loads are in flight together)
+  constexpr int SU = 4;
+  for (int i0 = rs + t; i0 < re; i0 += SU * WB_BLOCK) {
+    int b[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) b[u] = i0 + u * WB_BLOCK < re ? rowbuf[i0 + u * WB_BLOCK].b1 : -1;
+#pragma unroll
+    for (int u = 0; u < SU; ++u)
+      if (b[u] >= 0) atomicAdd(&cnt[b[u]], 1);
+  }
   __syncthreads();
   // exclusive scan of cnt[0 .. nb1): thread t owns entries t*ITEMS .. +ITEMS-1
   int v[ITEMS];
@@ -479,18 +493,39 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_
   if (re - rs <= WROW_LMAX) {
     // rows that fit: the sorted order is built in LDS first (perm[pos] = the
     // row entry placed at pos), so the sorted arrays are written coalesced
-    for (int i = rs + t; i < re; i += WB_BLOCK) perm[atomicAdd(&cnt[rowbuf[i].b1], 1) - rs] = (uint16_t)(i - rs);
+    for (int i0 = rs + t; i0 < re; i0 += SU * WB_BLOCK) {
+      int b[SU], pos[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) b[u] = i0 + u * WB_BLOCK < re ? rowbuf[i0 + u * WB_BLOCK].b1 : -1;
+      // branch-free claims (entries past the end add to a spare word per lane)
+#pragma unroll
+      for (int u = 0; u < SU; ++u) pos[u] = atomicAdd(&cnt[b[u] >= 0 ? b[u] : 4096 + (int)__lane_id()], 1);
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+        if (b[u] >= 0) perm[pos[u] - rs] = (uint16_t)(i0 + u * WB_BLOCK - rs);
+    }
     __syncthreads();
-    for (int q = t; q < re - rs; q += WB_BLOCK) {
-      const RowRec r = rowbuf[rs + perm[q]];
-      WSample<2> smp;
-      smp.k[0] = r.k0;
-      smp.k[1] = r.k1;
-      sincospi(r.k0, &smp.sc[0][0], &smp.sc[0][1]);
-      sincospi(r.k1, &smp.sc[1][0], &smp.sc[1][1]);
-      ss[rs + q] = smp;
-      sidx[rs + q] = r.j;
-      if (inv) inv[r.j] = rs + q;
+    for (int q0 = t; q0 < re - rs; q0 += SU * WB_BLOCK) {
+      RowRec r[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int q = q0 + u * WB_BLOCK;
+        if (q < re - rs) r[u] = rowbuf[rs + perm[q]];
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int q = q0 + u * WB_BLOCK;
+        if (q < re - rs) {
+          WSample<2> smp;
+          smp.k[0] = r[u].k0;
+          smp.k[1] = r[u].k1;
+          sincospi(r[u].k0, &smp.sc[0][0], &smp.sc[0][1]);
+          sincospi(r[u].k1, &smp.sc[1][0], &smp.sc[1][1]);
+          ss[rs + q] = smp;
+          sidx[rs + q] = r[u].j;
+          if (inv) inv[r[u].j] = rs + q;
+        }
+      }
     }
     return;
   }
