@@ -148,7 +148,8 @@ typedef enum { FTCG_ACCUM_FIXED = 0, FTCG_ACCUM_F64 = 1, FTCG_ACCUM_MFMA = 2 } f
 
 /* Tuning knobs (take effect at the next ftcg_set_points; the points must be
  * set again):
- *   tile       : tile edge in grid cells (16, 32, 64, 128; 0 = automatic);
+ *   tile       : tile edge in grid cells (16, 32, 64, 128; 0 = automatic:
+ *                32 in 2D (64 with FTCG_ACCUM_MFMA), min(G, 1024) in 1D);
  *                FTCG_ACCUM_F64 supports tile <= 64 and
  *                lds_copies * 16 * tile * (tile + 1) <= 160 KiB.
  *   accum      : ftcg_accum (FTCG_ACCUM_FIXED needs a float32 plan,

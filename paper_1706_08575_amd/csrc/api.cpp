@@ -47,14 +47,14 @@ static double decode_ordered(unsigned long long o) {
 
 static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
-// 2D: tile 64 while that still gives at least 1024 tiles (four per CU),
-// else 32, so that small grids keep enough spreading workgroups in flight
-// (measured on the 512^2 SAS raster: 64 -> 0.044 ms, 32 -> 0.022 ms spread)
+// 2D: tile 32. Measured whole steps (binning + spread) on SAS rasters, tile
+// 64 / 32 / 16: 2^17 samples at 512^2 0.183 / 0.158 / 0.238 ms, 2^20 at
+// 1024^2 0.905 / 0.840 / 0.859 ms, 2^23 at 4096^2 4.75 / 4.57 / 5.26 ms: the
+// extra records of the smaller tile (footprints cut by more tile edges) cost
+// less than the larger LDS tile's lower occupancy saves.
 static int auto_tile(ftcg_plan p) {
   if (p->dim == 1) return (int)(p->G < 1024 ? p->G : 1024);
-  int t = (p->G / 64) * (p->G / 64) >= 1024 ? 64 : 32;
-  if (t > p->G) t = (int)p->G;
-  return t;
+  return (int)(p->G < 32 ? p->G : 32);
 }
 
 static void setup_tiles(ftcg_plan p) {
