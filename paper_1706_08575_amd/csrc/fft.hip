@@ -9,9 +9,9 @@
 // flips on load and store.
 //
 // One workgroup transforms RB consecutive rows of length G, one after another
-// in LDS (Stockham autosort, one radix-2 stage when log2 G is odd, then
-// radix-4 stages; every stage reads its butterfly inputs into registers,
-// synchronises, and writes in place). Only the n cropped outputs are kept,
+// in LDS (Stockham autosort, one radix-2 or radix-4 stage when log2 G is not
+// a multiple of 3, then radix-8 stages; every stage reads its butterfly
+// inputs into registers, synchronises, and writes in place). Only the n cropped outputs are kept,
 // in registers, and stored transposed once all RB rows are done, so that each
 // store is an RB-element (32-byte) segment and the next pass again reads
 // contiguous rows:
@@ -69,25 +69,67 @@ __device__ inline cx cmul_i(cx a) {  // a * (+i)
   return r;
 }
 
+// inverse (positive exponent) DFT of 4 and of 8 points in registers
+template <class cx>
+__device__ inline void idft4(cx& a0, cx& a1, cx& a2, cx& a3) {
+  const cx s0 = cadd(a0, a2), s1 = csub(a0, a2), s2 = cadd(a1, a3), s3 = cmul_i(csub(a1, a3));
+  a0 = cadd(s0, s2);
+  a1 = cadd(s1, s3);
+  a2 = csub(s0, s2);
+  a3 = csub(s1, s3);
+}
+
+template <class cx>
+__device__ inline void idft8(cx (&v)[8]) {
+  using real = decltype(v[0].x);
+  // even and odd halves, then V[m] = E[m] + e^{i pi m / 4} O[m], V[m + 4] = E[m] - ...
+  idft4(v[0], v[2], v[4], v[6]);
+  idft4(v[1], v[3], v[5], v[7]);
+  const real c = (real)0.70710678118654752440;
+  cx o1, o2, o3;
+  o1.x = (v[3].x - v[3].y) * c;
+  o1.y = (v[3].x + v[3].y) * c;
+  o2 = cmul_i(v[5]);
+  o3.x = -(v[7].x + v[7].y) * c;
+  o3.y = (v[7].x - v[7].y) * c;
+  const cx e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6], od0 = v[1];
+  v[0] = cadd(e0, od0);
+  v[4] = csub(e0, od0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
 // in-place inverse (positive exponent) FFT of buf[0..L) in LDS, L = 2^log2L,
 // by threads tid = 0..nth-1, nth >= L / PPT (PPT points per thread per
-// stage); every thread of the workgroup calls it with the same L. Twiddles:
-// with w(j) = e^{2 pi i j / 2^log2T} (2^log2T >= L), e^{2 pi i k / (4 Ns)} =
-// w(k << (log2T - log2(4 Ns))), and w(j) = hi[j >> 6] * lo[j & 63] from the two
-// LDS tables lo[t] = w(t), hi[t] = w(64 t) (both formed in float64); the
-// second and third twiddles of a radix-4 butterfly are its square and cube.
+// stage, a multiple of 8); every thread of the workgroup calls it with the
+// same L. Stockham autosort: one radix-2 or radix-4 stage when log2 L is not
+// a multiple of 3, then radix-8 stages; a radix-R stage over spans Ns reads
+// the R inputs b + r L/R of butterfly b into registers, multiplies input r by
+// e^{2 pi i r k / (R Ns)} (k = b mod Ns), synchronises, and writes the R
+// outputs to (b - k) R + k + m Ns. Twiddles: with w(j) = e^{2 pi i j /
+// 2^log2T} (2^log2T >= L), e^{2 pi i k / (8 Ns)} = w(k << (log2T - log2(8
+// Ns))), and w(j) = hi[j >> 6] * lo[j & 63] from the two LDS tables lo[t] =
+// w(t), hi[t] = w(64 t) (both formed in float64); the other six twiddles of
+// a radix-8 butterfly are its powers 2 .. 7, each at most three products
+// from the first.
 template <class real, int PPT>
-__device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L, int tid, int nth,
+__device__ __attribute__((always_inline)) inline void lds_ifft(typename CxF<real>::t* buf, int L, int log2L, int tid, int nth,
                          const typename CxF<real>::t* tw_lo, const typename CxF<real>::t* tw_hi, int log2T) {
   using cx = typename CxF<real>::t;
-  constexpr int FFT_MAXB = PPT / 2;  // radix-2 butterflies per thread
-  int Ns = 1;
-  if (log2L & 1) {
+  static_assert(PPT % 8 == 0, "radix-8 stages take 8 points per butterfly");
+  int Ns = 1, log2Ns = 0;
+  const int pre = log2L % 3;
+  if (pre == 1) {
     // radix 2, Ns = 1: no twiddles
-    cx v0[FFT_MAXB], v1[FFT_MAXB];
+    constexpr int NB = PPT / 2;
+    cx v0[NB], v1[NB];
     const int half = L >> 1;
 #pragma unroll
-    for (int u = 0; u < FFT_MAXB; ++u)
+    for (int u = 0; u < NB; ++u)
       if (tid + u * nth < half) {
         const int b = tid + u * nth;
         v0[u] = buf[b];
@@ -95,7 +137,7 @@ __device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L, int tid, 
       }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < FFT_MAXB; ++u)
+    for (int u = 0; u < NB; ++u)
       if (tid + u * nth < half) {
         const int b = tid + u * nth;
         buf[2 * b] = cadd(v0[u], v1[u]);
@@ -103,44 +145,69 @@ __device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L, int tid, 
       }
     __syncthreads();
     Ns = 2;
-  }
-  const int quarter = L >> 2;
-  int log2Ns = log2L & 1;
-  for (; Ns < L; Ns <<= 2, log2Ns += 2) {
-    const int sh = log2T - log2Ns - 2;
-    cx v[FFT_MAXB / 2][4];
+    log2Ns = 1;
+  } else if (pre == 2) {
+    // radix 4, Ns = 1: no twiddles
+    constexpr int NB = PPT / 4;
+    cx v[NB][4];
+    const int quarter = L >> 2;
 #pragma unroll
-    for (int u = 0; u < FFT_MAXB / 2; ++u)
+    for (int u = 0; u < NB; ++u)
       if (tid + u * nth < quarter) {
+        const int b = tid + u * nth;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[u][r] = buf[b + r * quarter];
+      }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (tid + u * nth < quarter) {
+        const int b = tid + u * nth;
+        idft4(v[u][0], v[u][1], v[u][2], v[u][3]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) buf[4 * b + r] = v[u][r];
+      }
+    __syncthreads();
+    Ns = 4;
+    log2Ns = 2;
+  }
+  constexpr int NB8 = PPT / 8;
+  const int eighth = L >> 3;
+  for (; Ns < L; Ns <<= 3, log2Ns += 3) {
+    const int sh = log2T - log2Ns - 3;
+    cx v[NB8][8];
+#pragma unroll
+    for (int u = 0; u < NB8; ++u)
+      if (tid + u * nth < eighth) {
         const int b = tid + u * nth;
         const int k = b & (Ns - 1);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[u][r] = buf[b + r * quarter];
+        for (int r = 0; r < 8; ++r) v[u][r] = buf[b + r * eighth];
         if (Ns > 1) {
           const int j = k << sh;
           const cx w1 = cmul(tw_hi[j >> 6], tw_lo[j & 63]);
           const cx w2 = cmul(w1, w1);
           const cx w3 = cmul(w2, w1);
+          const cx w4 = cmul(w2, w2);
           v[u][1] = cmul(v[u][1], w1);
           v[u][2] = cmul(v[u][2], w2);
           v[u][3] = cmul(v[u][3], w3);
+          v[u][4] = cmul(v[u][4], w4);
+          v[u][5] = cmul(v[u][5], cmul(w4, w1));
+          v[u][6] = cmul(v[u][6], cmul(w4, w2));
+          v[u][7] = cmul(v[u][7], cmul(w4, w3));
         }
       }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < FFT_MAXB / 2; ++u)
-      if (tid + u * nth < quarter) {
+    for (int u = 0; u < NB8; ++u)
+      if (tid + u * nth < eighth) {
         const int b = tid + u * nth;
         const int k = b & (Ns - 1);
-        const cx a0 = cadd(v[u][0], v[u][2]);
-        const cx a1 = csub(v[u][0], v[u][2]);
-        const cx a2 = cadd(v[u][1], v[u][3]);
-        const cx a3 = cmul_i(csub(v[u][1], v[u][3]));
-        const int d = (b - k) * 4 + k;  // (b / Ns) * 4 Ns + k
-        buf[d] = cadd(a0, a2);
-        buf[d + Ns] = cadd(a1, a3);
-        buf[d + 2 * Ns] = csub(a0, a2);
-        buf[d + 3 * Ns] = csub(a1, a3);
+        idft8(v[u]);
+        const int d = (b - k) * 8 + k;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) buf[d + r * Ns] = v[u][r];
       }
     __syncthreads();
   }
@@ -156,7 +223,7 @@ __device__ void lds_ifft(typename CxF<real>::t* buf, int L, int log2L, int tid, 
 // dst[q' out_stride_q + r0]: through LDS staged q'-major when RC = RB, or
 // straight from registers when RC = 1 (one thread then holds all RB rows).
 template <class real, int RB, int RC, int MAXQ, int PPT>
-__device__ inline void fft_rows_block(const typename CxF<real>::t* __restrict__ src, int64_t in_row_stride,
+__device__ __attribute__((always_inline)) inline void fft_rows_block(const typename CxF<real>::t* __restrict__ src, int64_t in_row_stride,
                                       typename CxF<real>::t* __restrict__ dst, int64_t out_stride_q, int L,
                                       int log2L, int ncrop, int crop_off, int r0, int pre_sign,
                                       const double* __restrict__ dq, const double* __restrict__ drow,
