@@ -86,6 +86,8 @@ constexpr double WPI_EPS = WPI * WEPS;
 template <int DIM>
 constexpr double wscale() { return DIM == 1 ? WPI * WPI : WPI * WPI * WPI * WPI; }
 
+// pi^DIM T_in by the select-free form, or a value whose square is 0 when
+// ||k_i - k_n||_inf > R
 template <int DIM>
 __device__ inline double pair_term(const WSample<DIM>& o, const double* x, const double* sn, const double* cs,
                                    double R) {
@@ -102,11 +104,18 @@ __device__ inline double pair_term(const WSample<DIM>& o, const double* x, const
     den *= d + WEPS;
   }
   const double q = num * rcp64(den);
-  const double t = q * q;
-  // outside the box: clear the high word, which leaves at most a subnormal
-  // (below 2^-1022), nothing next to a sum that starts at pi^(2 DIM)
-  const int hi = dmax <= R ? __double2hiint(t) : 0;
-  return __hiloint2double(hi, __double2loint(t));
+  // outside the box: clear the high word, which leaves at most 2^-1042, whose
+  // square is 0
+  const int hi = dmax <= R ? __double2hiint(q) : 0;
+  return __hiloint2double(hi, __double2loint(q));
+}
+
+// acc + (pi^DIM T_in)^2, the square fused into the sum
+template <int DIM>
+__device__ inline double pair_add(double acc, const WSample<DIM>& o, const double* x, const double* sn,
+                                  const double* cs, double R) {
+  const double q = pair_term<DIM>(o, x, sn, cs, R);
+  return fma(q, q, acc);
 }
 
 // a candidate record; 2D records (48 bytes) sit in 16-byte aligned arrays
@@ -143,15 +152,14 @@ __device__ inline void range_sum(const WSample<DIM>* __restrict__ ss, int beg, i
     const WSample<DIM> b = ld_wsample(p + 1);
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
-      const double ta = pair_term<DIM>(a, x[u], sn[u], cs[u], R);
-      const double tb = pair_term<DIM>(b, x[u], sn[u], cs[u], R);
-      acc[u] += ta + tb;
+      acc[u] = pair_add<DIM>(acc[u], a, x[u], sn[u], cs[u], R);
+      acc[u] = pair_add<DIM>(acc[u], b, x[u], sn[u], cs[u], R);
     }
   }
   if (p < pe) {
     const WSample<DIM> a = ld_wsample(p);
 #pragma unroll
-    for (int u = 0; u < NT; ++u) acc[u] += pair_term<DIM>(a, x[u], sn[u], cs[u], R);
+    for (int u = 0; u < NT; ++u) acc[u] = pair_add<DIM>(acc[u], a, x[u], sn[u], cs[u], R);
   }
 }
 
@@ -311,7 +319,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const int32_t* __
     const int first = DIM == 2 ? b0 * g.nb[1] + lo1 : b0;
     const int last = DIM == 2 ? b0 * g.nb[1] + hi1 : b0;
     const int beg = boff[first], end = boff[last + 1];
-    for (int i = beg + lane; i < end; i += 64) acc += pair_term<DIM>(ss[i], x, sn, cs, g.R);
+    for (int i = beg + lane; i < end; i += 64) acc = pair_add<DIM>(acc, ss[i], x, sn, cs, g.R);
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (lane == 0) out[w] = wscale<DIM>() / acc;
