@@ -191,7 +191,7 @@ ftcg_status ftcg_plan_destroy(ftcg_plan p) {
   if (!p) return FTCG_EINVAL;
   (void)hipStreamSynchronize(p->stream);
   DevBuf* bufs[] = {&p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp,
-                    &p->flags,  &p->wb_cnt, &p->wb_off, &p->wb_rowoff, &p->wb_rowbuf, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->ws_inv, &p->audit_buf,
+                    &p->flags,  &p->wb_cnt, &p->wb_off, &p->wb_rowoff, &p->wb_rowbuf, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->ws_inv, &p->ws_sum, &p->audit_buf,
                     &p->grid,   &p->fft_tmp, &p->deapod, &p->twiddle, &p->tile_order};
   for (DevBuf* b : bufs) b->release();
   for (auto& pr : p->timing.pending) {

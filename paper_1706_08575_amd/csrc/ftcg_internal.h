@@ -213,6 +213,8 @@ struct ftcg_plan_s {
   ftcg::DevBuf ws_idx;       // sorted original index
   ftcg::DevBuf wb_of;        // weight-bin id per sample (caller order)
   ftcg::DevBuf ws_inv;       // sorted position of every sample (caller order)
+  ftcg::DevBuf ws_sum;       // 2D: per-sample weight sums in bin order (symmetric form)
+  bool ws_sum_fresh = false; // ws_sum holds the self terms only (preset by the bin sort)
   ftcg::WBinGeom wgeom{};
   bool have_wbins = false;
   bool weights_only = false;  // internal plans that only compute weights (no tile binning)

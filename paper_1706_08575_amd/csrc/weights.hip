@@ -290,6 +290,131 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_rows(const WSample<2
   }
 }
 
+// Symmetric form of the 2D sum. T is symmetric, so each unordered pair
+// {n, i} is formed once, by the sample that comes first: i later in bin order
+// in n's own bin row, or anywhere in n's column window in the s bin rows
+// after it. The square goes to both sums: to n's in a register, and to i's in
+// an LDS slot of its staged candidate, flushed after every chunk with one
+// float64 atomic per touched candidate into the bin-order sums, which start
+// from the self terms pi^4 preset by the bin sort. Launch shape and staging
+// as k_frame_weights_rows with one sample per lane group.
+__device__ inline void sym_pair(double& acc, double* cacc, int p, const WSample<2>& o, const double (&x)[2],
+                                const double (&sn)[2], const double (&cs)[2], double R) {
+  const double q = pair_term<2>(o, x, sn, cs, R);
+  const double q2 = q * q;
+  acc += q2;
+  if (q2 != 0.0) __hip_atomic_fetch_add(cacc + p, q2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int S>
+__global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>* __restrict__ ss,
+                                                                const int32_t* __restrict__ boff, WBinGeom g,
+                                                                int cx, int chunk, double* __restrict__ wsum) {
+  constexpr int RUN = WB_BLOCK / S;
+  __shared__ __align__(16) WSample<2> cand[WCH];
+  __shared__ double cacc[WCH];
+  for (int i = threadIdx.x; i < WCH; i += WB_BLOCK) cacc[i] = 0.0;   // ordered by the first chunk's barriers
+  const int64_t lid = xcd_block_chunk(blockIdx.x, gridDim.x, chunk);
+  const int b0 = (int)(lid / cx), bx = (int)(lid % cx);
+  const int nb1 = g.nb[1];
+  const int rs = boff[b0 * nb1], re = boff[(b0 + 1) * nb1];
+  const int rhi = min(b0 + g.span, g.nb[0] - 1);
+  const int sub = (int)threadIdx.x % S;
+  for (int c0 = rs + bx * RUN; c0 < re; c0 += cx * RUN) {
+    const int cend = min(c0 + RUN, re);
+    const int t0 = c0 + (int)threadIdx.x / S;
+    const bool active = t0 < cend;
+    const int t = active ? t0 : cend - 1;
+    double x[2], sn[2], cs[2];
+    {
+      const WSample<2> me = ss[t];
+      for (int a = 0; a < 2; ++a) {
+        x[a] = me.k[a];
+        sn[a] = me.sc[a][0];
+        cs[a] = me.sc[a][1];
+      }
+    }
+    int b[2];
+    wbin_of<2>(x, g, b);
+    const int mylo = max(b[1] - g.span, 0), myhi = min(b[1] + g.span, nb1 - 1);
+    int lo1, hi1;
+    {
+      double xf[2] = {ss[c0].k[0], ss[c0].k[1]};
+      wbin_of<2>(xf, g, b);
+      lo1 = max(b[1] - g.span, 0);
+      double xl[2] = {ss[cend - 1].k[0], ss[cend - 1].k[1]};
+      wbin_of<2>(xl, g, b);
+      hi1 = min(b[1] + g.span, nb1 - 1);
+    }
+    double acc = 0.0;
+    for (int r = b0; r <= rhi; ++r) {
+      const int gs = boff[r * nb1 + lo1], ge = boff[r * nb1 + hi1 + 1];
+      int ms = 0, me = 0;
+      if (active) {
+        int fs = boff[r * nb1 + mylo];
+        const int fe = boff[r * nb1 + myhi + 1];
+        if (r == b0) fs = max(fs, t + 1);   // own row: the samples after this one
+        if (fs < fe) {
+          const int part = (fe - fs + S - 1) / S;
+          ms = min(fs + sub * part, fe);
+          me = min(ms + part, fe);
+        }
+      }
+      for (int q0 = gs; q0 < ge; q0 += WCH) {
+        const int q1 = min(q0 + WCH, ge);
+        __syncthreads();   // the previous chunk has been consumed and flushed
+        {
+          const float4* src = reinterpret_cast<const float4*>(ss + q0);
+          float4* dst = reinterpret_cast<float4*>(cand);
+          const int n4 = (q1 - q0) * 3;
+          for (int i = threadIdx.x; i < n4; i += WB_BLOCK) dst[i] = src[i];
+        }
+        __syncthreads();
+        const int a0 = max(ms, q0) - q0, a1 = min(me, q1) - q0;
+        // Lanes of one bin walk the same range; each starts at its own
+        // rotation of it, so their candidate atomics meet different slots.
+        const int len = a1 - a0;
+        if (len > 0) {
+          int p = a0 + (int)(((unsigned)t * 5u) % (unsigned)len);
+          for (int j = 0; j + 1 < len; j += 2) {
+            const int pb = p + 1 == a1 ? a0 : p + 1;
+            const WSample<2> ca = ld_wsample(cand + p);
+            const WSample<2> cb = ld_wsample(cand + pb);
+            sym_pair(acc, cacc, p, ca, x, sn, cs, g.R);
+            sym_pair(acc, cacc, pb, cb, x, sn, cs, g.R);
+            p = pb + 1 == a1 ? a0 : pb + 1;
+          }
+          if (len & 1) sym_pair(acc, cacc, p, ld_wsample(cand + p), x, sn, cs, g.R);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < q1 - q0; i += WB_BLOCK) {
+          const double v = cacc[i];
+          if (v != 0.0) {
+            unsafeAtomicAdd(wsum + q0 + i, v);
+            cacc[i] = 0.0;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < S; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if (sub == 0 && active) unsafeAtomicAdd(wsum + t, acc);
+  }
+}
+
+// alpha (caller order) from the bin-order sums
+__global__ __launch_bounds__(WB_BLOCK) void k_weights_from_sums(const double* __restrict__ wsum,
+                                                                const int32_t* __restrict__ sidx, int64_t m,
+                                                                double* __restrict__ alpha) {
+  const int64_t t = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
+  if (t < m) alpha[sidx[t]] = wscale<2>() / wsum[t];
+}
+
+__global__ __launch_bounds__(WB_BLOCK) void k_fill_f64(double* __restrict__ a, int64_t n, double v) {
+  const int64_t t = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
+  if (t < n) a[t] = v;
+}
+
 // the same sum for listed samples (caller indices), for audits and checks:
 // one wavefront per sample, lanes splitting its candidate ranges (the lists
 // are short, so one thread per sample would leave the GPU idle)
@@ -448,7 +573,8 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(const double* __restr
 __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_t* __restrict__ row_off,
                                                         const RowRec* __restrict__ rowbuf,
                                                         int32_t* __restrict__ boff, WSample<2>* __restrict__ ss,
-                                                        int32_t* __restrict__ sidx, int32_t* __restrict__ inv) {
+                                                        int32_t* __restrict__ sidx, int32_t* __restrict__ inv,
+                                                        double* __restrict__ sums) {
   constexpr int ITEMS = 4096 / WB_BLOCK;
   __shared__ int32_t cnt[4096 + 64];   // bin counters, then one spare word per lane
   __shared__ int32_t wsum[WB_BLOCK / 64];
@@ -535,6 +661,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_
           ss[rs + q] = smp;
           sidx[rs + q] = r[u].j;
           if (inv) inv[r[u].j] = rs + q;
+          if (sums) sums[rs + q] = wscale<2>();   // the self term
         }
       }
     }
@@ -551,6 +678,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_
     ss[pos] = smp;
     sidx[pos] = r.j;
     if (inv) inv[r.j] = pos;
+    if (sums) sums[pos] = wscale<2>();
   }
 }
 
@@ -576,10 +704,14 @@ void sort_weight_rows(ftcg_plan p) {
   const WBinGeom& g = p->wgeom;
   // the inverse map serves the learned features and the audit only
   const bool need_inv = p->wmode == FTCG_W_LEARNED || p->weights_only;
+  // the symmetric weight sum starts from the self terms, preset here
+  p->ws_sum.ensure(sizeof(double) * p->m);
   hipLaunchKernelGGL(k_wrow_sort, dim3((unsigned)g.nb[0]), dim3(WB_BLOCK), 0, p->stream, g,
                      p->wb_rowoff.as<int32_t>(), p->wb_rowbuf.as<RowRec>(), p->wb_off.as<int32_t>(),
-                     p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), need_inv ? p->ws_inv.as<int32_t>() : nullptr);
+                     p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(), need_inv ? p->ws_inv.as<int32_t>() : nullptr,
+                     p->ws_sum.as<double>());
   FTCG_HIP(hipGetLastError());
+  p->ws_sum_fresh = true;
 }
 
 void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const double* kmax) {
@@ -636,6 +768,26 @@ static void launch_weights_rows(ftcg_plan p) {
                      p->alpha.as<double>());
 }
 
+template <int S>
+static void launch_weights_sym(ftcg_plan p) {
+  const WBinGeom& g = p->wgeom;
+  const int64_t m = p->m;
+  double* wsum = p->ws_sum.as<double>();
+  if (!p->ws_sum_fresh) {   // sums already used: start again from the self terms
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((m + WB_BLOCK - 1) / WB_BLOCK)), dim3(WB_BLOCK), 0, p->stream,
+                       wsum, m, wscale<2>());
+  }
+  p->ws_sum_fresh = false;
+  const int64_t runs = (m * S + WB_BLOCK - 1) / WB_BLOCK;
+  const int cx = (int)std::max<int64_t>(1, (2 * runs + g.nb[0] - 1) / g.nb[0]);
+  const int64_t nb = (int64_t)cx * g.nb[0];
+  const int chunk = cx * std::max(1, g.nb[0] / 64);
+  hipLaunchKernelGGL((k_frame_weights_sym<S>), dim3((unsigned)nb), dim3(WB_BLOCK), 0, p->stream,
+                     p->ws_k.as<WSample<2>>(), p->wb_off.as<int32_t>(), g, cx, chunk, wsum);
+  hipLaunchKernelGGL(k_weights_from_sums, dim3((unsigned)((m + WB_BLOCK - 1) / WB_BLOCK)), dim3(WB_BLOCK), 0,
+                     p->stream, wsum, p->ws_idx.as<int32_t>(), m, p->alpha.as<double>());
+}
+
 template <int WT>
 static void launch_weights_rows_s(ftcg_plan p, int S) {
   switch (S) {
@@ -656,6 +808,8 @@ static void launch_weights_1d(ftcg_plan p) {
 // samples per lane: the plan's tuning, else 1 (the staged 2D kernel is bound
 // by its float64 arithmetic, and one sample per lane keeps the most
 // wavefronts resident)
+constexpr bool WEIGHT_SYMMETRIC = true;
+
 void run_plain_weights(ftcg_plan p) {
   timing_begin(p, STEP_WEIGHTS);
   const int wt = p->w_samples ? p->w_samples : 1;
@@ -668,6 +822,16 @@ void run_plain_weights(ftcg_plan p) {
     const WBinGeom& g = p->wgeom;
     const double cand = (double)p->m / ((double)g.nb[0] * g.nb[1]) * (2 * g.span + 1) * (2 * g.span + 1);
     const int S = p->w_lanes ? p->w_lanes : (cand > 1e4 ? 1 : (p->m < (int64_t(1) << 21) ? 4 : 2));
+    if (wt == 1 && WEIGHT_SYMMETRIC) {
+      switch (S) {
+        case 1: launch_weights_sym<1>(p); break;
+        case 2: launch_weights_sym<2>(p); break;
+        default: launch_weights_sym<4>(p); break;
+      }
+      FTCG_HIP(hipGetLastError());
+      timing_end(p, STEP_WEIGHTS);
+      return;
+    }
     switch (wt) {
       case 1: launch_weights_rows_s<1>(p, S); break;
       case 2: launch_weights_rows_s<2>(p, S); break;
