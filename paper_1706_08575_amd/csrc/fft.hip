@@ -103,6 +103,12 @@ __device__ inline void idft8(cx (&v)[8]) {
   v[7] = csub(e3, o3);
 }
 
+// Row buffers in LDS are padded with one element after every 32 (element i
+// at lp(i)): the first radix-8 stage writes at a stride of 8 elements, which
+// without the pad puts 8 lanes of a half-wavefront on one bank.
+__device__ inline int lp(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int padded_len(int L) { return L + (L >> 5); }
+
 // in-place inverse (positive exponent) FFT of buf[0..L) in LDS, L = 2^log2L,
 // by threads tid = 0..nth-1, nth >= L / PPT (PPT points per thread per
 // stage, a multiple of 8); every thread of the workgroup calls it with the
@@ -132,16 +138,16 @@ __device__ __attribute__((always_inline)) inline void lds_ifft(typename CxF<real
     for (int u = 0; u < NB; ++u)
       if (tid + u * nth < half) {
         const int b = tid + u * nth;
-        v0[u] = buf[b];
-        v1[u] = buf[b + half];
+        v0[u] = buf[lp(b)];
+        v1[u] = buf[lp(b + half)];
       }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NB; ++u)
       if (tid + u * nth < half) {
         const int b = tid + u * nth;
-        buf[2 * b] = cadd(v0[u], v1[u]);
-        buf[2 * b + 1] = csub(v0[u], v1[u]);
+        buf[lp(2 * b)] = cadd(v0[u], v1[u]);
+        buf[lp(2 * b + 1)] = csub(v0[u], v1[u]);
       }
     __syncthreads();
     Ns = 2;
@@ -156,7 +162,7 @@ __device__ __attribute__((always_inline)) inline void lds_ifft(typename CxF<real
       if (tid + u * nth < quarter) {
         const int b = tid + u * nth;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[u][r] = buf[b + r * quarter];
+        for (int r = 0; r < 4; ++r) v[u][r] = buf[lp(b + r * quarter)];
       }
     __syncthreads();
 #pragma unroll
@@ -165,7 +171,7 @@ __device__ __attribute__((always_inline)) inline void lds_ifft(typename CxF<real
         const int b = tid + u * nth;
         idft4(v[u][0], v[u][1], v[u][2], v[u][3]);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) buf[4 * b + r] = v[u][r];
+        for (int r = 0; r < 4; ++r) buf[lp(4 * b + r)] = v[u][r];
       }
     __syncthreads();
     Ns = 4;
@@ -182,7 +188,7 @@ __device__ __attribute__((always_inline)) inline void lds_ifft(typename CxF<real
         const int b = tid + u * nth;
         const int k = b & (Ns - 1);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[u][r] = buf[b + r * eighth];
+        for (int r = 0; r < 8; ++r) v[u][r] = buf[lp(b + r * eighth)];
         if (Ns > 1) {
           const int j = k << sh;
           const cx w1 = cmul(tw_hi[j >> 6], tw_lo[j & 63]);
@@ -207,7 +213,7 @@ __device__ __attribute__((always_inline)) inline void lds_ifft(typename CxF<real
         idft8(v[u]);
         const int d = (b - k) * 8 + k;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) buf[d + r * Ns] = v[u][r];
+        for (int r = 0; r < 8; ++r) buf[lp(d + r * Ns)] = v[u][r];
       }
     __syncthreads();
   }
@@ -215,8 +221,9 @@ __device__ __attribute__((always_inline)) inline void lds_ifft(typename CxF<real
 
 // RB consecutive rows r0..r0+RB-1 through one workgroup, RC of them at a
 // time (RC = 1 or RB): the threads form RC slots of blockDim.x / RC threads,
-// slot s owning LDS buf[s L ..) and rows s, s + RC, ... Each row is read from
-// HBM into registers one step ahead (while the previous one is transformed),
+// slot s owning LDS buf[s Lp ..) (Lp = padded_len(L)) and rows s, s + RC, ...
+// Each row is read from HBM into registers one step ahead (while the previous
+// one is transformed),
 // multiplied by (-1)^(row+g) when pre_sign, transformed in LDS, and its
 // cropped outputs times (-1)^q * drow[row] * dq[q'] are kept in registers.
 // All RB rows of an output q' then leave as one RB-element segment at
@@ -230,7 +237,7 @@ __device__ __attribute__((always_inline)) inline void fft_rows_block(const typen
                                       typename CxF<real>::t* buf, const typename CxF<real>::t* __restrict__ tw,
                                       int log2T) {
   // twiddle tables behind the RC row buffers: lo (64 entries), hi (2^log2T / 64)
-  typename CxF<real>::t* tw_lo = buf + (size_t)RC * L;
+  typename CxF<real>::t* tw_lo = buf + (size_t)RC * padded_len(L);
   typename CxF<real>::t* tw_hi = tw_lo + 64;
   {
     const int ntw = 64 + max(1, (1 << log2T) >> 6);
@@ -242,7 +249,7 @@ __device__ __attribute__((always_inline)) inline void fft_rows_block(const typen
   const int nts = blockDim.x / RC;
   const int slot = RC == 1 ? 0 : (int)threadIdx.x / nts;
   const int t = (int)threadIdx.x - slot * nts;
-  cx* sbuf = buf + (size_t)slot * L;
+  cx* sbuf = buf + (size_t)slot * padded_len(L);
   cx outv[NJ][MAXQ];
   cx nxt[PPT];
   {
@@ -264,7 +271,7 @@ __device__ __attribute__((always_inline)) inline void fft_rows_block(const typen
           v.x = -v.x;
           v.y = -v.y;
         }
-        sbuf[g] = v;
+        sbuf[lp(g)] = v;
       }
     }
     if (j + 1 < NJ) {
@@ -284,7 +291,7 @@ __device__ __attribute__((always_inline)) inline void fft_rows_block(const typen
         double f = (q & 1) ? -fr : fr;
         if (dq) f *= dq[qp];
         const real fs = (real)f;
-        cx v = sbuf[q];
+        cx v = sbuf[lp(q)];
         v.x *= fs;
         v.y *= fs;
         outv[j][kq] = v;
@@ -376,7 +383,7 @@ static FftShape fft_shape(int64_t L, int64_t ncrop, int64_t rows, int elem_bytes
   f.maxq = q <= 4 && f.ppt == 8 ? 4 : 8;
   f.rb = (elem_bytes == 8 && f.ppt == 8) ? 4 : 2;
   if (rows % f.rb != 0) f.rb = 1;
-  f.rc = (f.rb * f.nts <= 1024 && f.rb * L * elem_bytes <= 64 * 1024) ? f.rb : 1;
+  f.rc = (f.rb * f.nts <= 1024 && f.rb * padded_len((int)L) * elem_bytes <= 72 * 1024) ? f.rb : 1;
   return f;
 }
 
@@ -417,7 +424,7 @@ struct BatchedLaunch {
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
       attr_done = true;
     }
-    const size_t lds = ((size_t)RC * L + 64 + std::max(1, L >> 6)) * sizeof(float2);
+    const size_t lds = ((size_t)RC * padded_len(L) + 64 + std::max(1, L >> 6)) * sizeof(float2);
     hipLaunchKernelGGL((k_fft_rows_batched<RB, RC, MAXQ, PPT>), dim3((unsigned)(rows / RB)), dim3(f.nts * RC), lds,
                        b->stream, b->items_dev.as<BatchItem>(), list, b->args_dev.as<BatchArgs>(), pass, L, log2L, n,
                        tw, log2L);
@@ -466,7 +473,7 @@ struct RowsLaunch {
     const int L = (int)p->G;
     int log2L = 0;
     while ((1 << log2L) < L) ++log2L;
-    const size_t lds = ((size_t)RC * L + 64 + std::max(1, L >> 6)) * sizeof(cx);
+    const size_t lds = ((size_t)RC * padded_len(L) + 64 + std::max(1, L >> 6)) * sizeof(cx);
     static bool attr_done = false;
     if (!attr_done) {
       FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows<real, RB, RC, MAXQ, PPT>,
