@@ -161,7 +161,8 @@ ftcg_status ftcg_plan_set_tuning(ftcg_plan plan, int tile, int accum, int lds_co
 /* Launch shape of the frame-weight sum (Sec. III-C, eq:difopt), taking effect
  * at the next weight computation:
  *   samples_per_lane : 1, 2 or 4 consecutive bin-sorted samples share each
- *                      lane's candidate reads (0 = automatic: 1);
+ *                      lane's candidate reads (0 = automatic: 2 in 2D from
+ *                      2^20 samples, else 1; 4 uses the one-sided sum);
  *   lanes_per_group  : 1, 2 or 4 lanes split every candidate range of a group
  *                      of samples and add their partial sums (2D only;
  *                      0 = automatic: 1 when a sample has more than about

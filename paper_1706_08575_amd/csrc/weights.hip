@@ -298,19 +298,32 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_rows(const WSample<2
 // float64 atomic per touched candidate into the bin-order sums, which start
 // from the self terms pi^4 preset by the bin sort. Launch shape and staging
 // as k_frame_weights_rows with one sample per lane group.
-__device__ inline void sym_pair(double& acc, double* cacc, int p, const WSample<2>& o, const double (&x)[2],
-                                const double (&sn)[2], const double (&cs)[2], double R) {
-  const double q = pair_term<2>(o, x, sn, cs, R);
-  const double q2 = q * q;
-  acc += q2;
-  if (q2 != 0.0) __hip_atomic_fetch_add(cacc + p, q2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// One staged candidate i (chunk slot p) against the WT samples of a lane:
+// each in-box square goes to the sample's sum and, summed over the WT
+// samples, to the candidate's slot. Sample u only takes candidates after
+// first[u] (its own position in its own bin row, else -1) and only while
+// active.
+template <int WT>
+__device__ inline void sym_pair(double (&acc)[WT], double* cacc, int p, int i, const WSample<2>& o,
+                                const double (&x)[WT][2], const double (&sn)[WT][2], const double (&cs)[WT][2],
+                                const int (&first)[WT], double R) {
+  double csum = 0.0;
+#pragma unroll
+  for (int u = 0; u < WT; ++u) {
+    const double q = pair_term<2>(o, x[u], sn[u], cs[u], R);
+    // (one sample per lane: its range already starts after first[0])
+    const double q2 = (WT == 1 || i > first[u]) ? q * q : 0.0;
+    acc[u] += q2;
+    csum += q2;
+  }
+  if (csum != 0.0) __hip_atomic_fetch_add(cacc + p, csum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <int S>
+template <int WT, int S>
 __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>* __restrict__ ss,
                                                                 const int32_t* __restrict__ boff, WBinGeom g,
                                                                 int cx, int chunk, double* __restrict__ wsum) {
-  constexpr int RUN = WB_BLOCK / S;
+  constexpr int RUN = WB_BLOCK * WT / S;
   __shared__ __align__(16) WSample<2> cand[WCH];
   __shared__ double cacc[WCH];
   for (int i = threadIdx.x; i < WCH; i += WB_BLOCK) cacc[i] = 0.0;   // ordered by the first chunk's barriers
@@ -322,23 +335,30 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
   const int sub = (int)threadIdx.x % S;
   for (int c0 = rs + bx * RUN; c0 < re; c0 += cx * RUN) {
     const int cend = min(c0 + RUN, re);
-    const int t0 = c0 + (int)threadIdx.x / S;
+    const int t0 = c0 + ((int)threadIdx.x / S) * WT;   // this lane's samples t0 .. t0 + WT - 1
     const bool active = t0 < cend;
-    const int t = active ? t0 : cend - 1;
-    double x[2], sn[2], cs[2];
-    {
-      const WSample<2> me = ss[t];
+    double x[WT][2], sn[WT][2], cs[WT][2];
+    int mylo = 1 << 30, myhi = -1;
+    bool live[WT];
+#pragma unroll
+    for (int u = 0; u < WT; ++u) {
+      live[u] = t0 + u < cend;
+      const WSample<2> me = ss[live[u] ? t0 + u : cend - 1];
       for (int a = 0; a < 2; ++a) {
-        x[a] = me.k[a];
-        sn[a] = me.sc[a][0];
-        cs[a] = me.sc[a][1];
+        x[u][a] = me.k[a];
+        sn[u][a] = me.sc[a][0];
+        cs[u][a] = me.sc[a][1];
       }
+      int b[2];
+      wbin_of<2>(x[u], g, b);
+      mylo = min(mylo, b[1]);
+      myhi = max(myhi, b[1]);
     }
-    int b[2];
-    wbin_of<2>(x, g, b);
-    const int mylo = max(b[1] - g.span, 0), myhi = min(b[1] + g.span, nb1 - 1);
+    mylo = max(mylo - g.span, 0);
+    myhi = min(myhi + g.span, nb1 - 1);
     int lo1, hi1;
     {
+      int b[2];
       double xf[2] = {ss[c0].k[0], ss[c0].k[1]};
       wbin_of<2>(xf, g, b);
       lo1 = max(b[1] - g.span, 0);
@@ -346,14 +366,20 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
       wbin_of<2>(xl, g, b);
       hi1 = min(b[1] + g.span, nb1 - 1);
     }
-    double acc = 0.0;
+    double acc[WT];
+#pragma unroll
+    for (int u = 0; u < WT; ++u) acc[u] = 0.0;
     for (int r = b0; r <= rhi; ++r) {
       const int gs = boff[r * nb1 + lo1], ge = boff[r * nb1 + hi1 + 1];
+      // own row: the samples after each of this lane's; idle samples take none
+      int first[WT];
+#pragma unroll
+      for (int u = 0; u < WT; ++u) first[u] = !live[u] ? (1 << 30) : (r == b0 ? t0 + u : -1);
       int ms = 0, me = 0;
       if (active) {
         int fs = boff[r * nb1 + mylo];
         const int fe = boff[r * nb1 + myhi + 1];
-        if (r == b0) fs = max(fs, t + 1);   // own row: the samples after this one
+        if (r == b0) fs = max(fs, t0 + 1);
         if (fs < fe) {
           const int part = (fe - fs + S - 1) / S;
           ms = min(fs + sub * part, fe);
@@ -375,16 +401,16 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
         // rotation of it, so their candidate atomics meet different slots.
         const int len = a1 - a0;
         if (len > 0) {
-          int p = a0 + (int)(((unsigned)t * 5u) % (unsigned)len);
+          int p = a0 + (int)(((unsigned)t0 * 5u) % (unsigned)len);
           for (int j = 0; j + 1 < len; j += 2) {
             const int pb = p + 1 == a1 ? a0 : p + 1;
             const WSample<2> ca = ld_wsample(cand + p);
             const WSample<2> cb = ld_wsample(cand + pb);
-            sym_pair(acc, cacc, p, ca, x, sn, cs, g.R);
-            sym_pair(acc, cacc, pb, cb, x, sn, cs, g.R);
+            sym_pair<WT>(acc, cacc, p, q0 + p, ca, x, sn, cs, first, g.R);
+            sym_pair<WT>(acc, cacc, pb, q0 + pb, cb, x, sn, cs, first, g.R);
             p = pb + 1 == a1 ? a0 : pb + 1;
           }
-          if (len & 1) sym_pair(acc, cacc, p, ld_wsample(cand + p), x, sn, cs, g.R);
+          if (len & 1) sym_pair<WT>(acc, cacc, p, q0 + p, ld_wsample(cand + p), x, sn, cs, first, g.R);
         }
         __syncthreads();
         for (int i = threadIdx.x; i < q1 - q0; i += WB_BLOCK) {
@@ -397,8 +423,11 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
       }
     }
 #pragma unroll
-    for (int off = 1; off < S; off <<= 1) acc += __shfl_xor(acc, off, 64);
-    if (sub == 0 && active) unsafeAtomicAdd(wsum + t, acc);
+    for (int u = 0; u < WT; ++u) {
+#pragma unroll
+      for (int off = 1; off < S; off <<= 1) acc[u] += __shfl_xor(acc[u], off, 64);
+      if (sub == 0 && live[u]) unsafeAtomicAdd(wsum + t0 + u, acc[u]);
+    }
   }
 }
 
@@ -768,7 +797,7 @@ static void launch_weights_rows(ftcg_plan p) {
                      p->alpha.as<double>());
 }
 
-template <int S>
+template <int WT, int S>
 static void launch_weights_sym(ftcg_plan p) {
   const WBinGeom& g = p->wgeom;
   const int64_t m = p->m;
@@ -778,11 +807,11 @@ static void launch_weights_sym(ftcg_plan p) {
                        wsum, m, wscale<2>());
   }
   p->ws_sum_fresh = false;
-  const int64_t runs = (m * S + WB_BLOCK - 1) / WB_BLOCK;
+  const int64_t runs = (m * S + WB_BLOCK * WT - 1) / (WB_BLOCK * WT);
   const int cx = (int)std::max<int64_t>(1, (2 * runs + g.nb[0] - 1) / g.nb[0]);
   const int64_t nb = (int64_t)cx * g.nb[0];
   const int chunk = cx * std::max(1, g.nb[0] / 64);
-  hipLaunchKernelGGL((k_frame_weights_sym<S>), dim3((unsigned)nb), dim3(WB_BLOCK), 0, p->stream,
+  hipLaunchKernelGGL((k_frame_weights_sym<WT, S>), dim3((unsigned)nb), dim3(WB_BLOCK), 0, p->stream,
                      p->ws_k.as<WSample<2>>(), p->wb_off.as<int32_t>(), g, cx, chunk, wsum);
   hipLaunchKernelGGL(k_weights_from_sums, dim3((unsigned)((m + WB_BLOCK - 1) / WB_BLOCK)), dim3(WB_BLOCK), 0,
                      p->stream, wsum, p->ws_idx.as<int32_t>(), m, p->alpha.as<double>());
@@ -805,14 +834,17 @@ static void launch_weights_1d(ftcg_plan p) {
                      p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), p->m, p->wgeom, p->alpha.as<double>());
 }
 
-// samples per lane: the plan's tuning, else 1 (the staged 2D kernel is bound
-// by its float64 arithmetic, and one sample per lane keeps the most
-// wavefronts resident)
+// samples per lane: the plan's tuning, else in 2D 2 from 2^20 samples (each
+// staged candidate then serves two pairs and one LDS atomic; measured on SAS
+// rasters of 2^20 and 2^23 samples: 0.371 against 0.402 ms and 1.76 against
+// 1.92 ms) and 1 below (2^17 samples: 0.042 against 0.068 ms, where the
+// lanes are too few); 1 in 1D
 constexpr bool WEIGHT_SYMMETRIC = true;
+constexpr int SYM_MAX_WT = 2;   // samples per lane the symmetric kernel is built for
 
 void run_plain_weights(ftcg_plan p) {
   timing_begin(p, STEP_WEIGHTS);
-  const int wt = p->w_samples ? p->w_samples : 1;
+  const int wt = p->w_samples ? p->w_samples : (p->dim == 2 && p->m >= (int64_t(1) << 20) ? 2 : 1);
   if (p->dim == 2) {
     // lanes per sample group: the plan's tuning, else 4 below 2^21 samples
     // and 2 from there, but 1 when a sample has more than about 10^4
@@ -822,11 +854,15 @@ void run_plain_weights(ftcg_plan p) {
     const WBinGeom& g = p->wgeom;
     const double cand = (double)p->m / ((double)g.nb[0] * g.nb[1]) * (2 * g.span + 1) * (2 * g.span + 1);
     const int S = p->w_lanes ? p->w_lanes : (cand > 1e4 ? 1 : (p->m < (int64_t(1) << 21) ? 4 : 2));
-    if (wt == 1 && WEIGHT_SYMMETRIC) {
-      switch (S) {
-        case 1: launch_weights_sym<1>(p); break;
-        case 2: launch_weights_sym<2>(p); break;
-        default: launch_weights_sym<4>(p); break;
+    if (wt <= SYM_MAX_WT && WEIGHT_SYMMETRIC) {
+      const int key = (wt == 2 ? 10 : 0) + S;
+      switch (key) {
+        case 1: launch_weights_sym<1, 1>(p); break;
+        case 2: launch_weights_sym<1, 2>(p); break;
+        case 4: launch_weights_sym<1, 4>(p); break;
+        case 11: launch_weights_sym<2, 1>(p); break;
+        case 12: launch_weights_sym<2, 2>(p); break;
+        default: launch_weights_sym<2, 4>(p); break;
       }
       FTCG_HIP(hipGetLastError());
       timing_end(p, STEP_WEIGHTS);
