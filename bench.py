@@ -272,7 +272,7 @@ def bench_learned(steps: int, warmup: int) -> dict:
             P.execute(F, out)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / steps
-        st = {s_: ms / c for s_, (ms, c) in P.timing().items()}
+        st = {s_: ms / steps for s_, (ms, c) in P.timing().items()}   # ms per step in each stage
         P.enable_timing(False)
         return sec, out, st
 
@@ -386,7 +386,10 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    stage_ms = {s: ms / c for s, (ms, c) in stages.items()}
+    # ms per step in each stage (a stage may be timed in several intervals
+    # per step: the binning before and after the weights; stages on the
+    # plan's second stream overlap the others)
+    stage_ms = {s: ms / args.steps for s, (ms, c) in stages.items()}
     # roofline of the dominant kernel (among the steps with a work model)
     modelled = [s_ for s_ in stage_ms if s_ == "weights" or
                 step_bytes(s_, m, info["n_records"], n, G, dim, dtype) is not None]

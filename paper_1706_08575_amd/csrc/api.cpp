@@ -178,6 +178,12 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
       p->host_flags = nullptr;
       throw StatusError{FTCG_ENOMEM};
     }
+    if (hipHostMalloc((void**)&p->host_part, sizeof(unsigned long long) * 5 * CHECK_PARTS,
+                      hipHostMallocCoherent) != hipSuccess) {
+      p->host_part = nullptr;
+      throw StatusError{FTCG_ENOMEM};
+    }
+    FTCG_HIP(hipHostGetDevicePointer((void**)&p->host_part_dev, p->host_part, 0));
   });
   if (st != FTCG_OK) {
     ftcg_plan_destroy(p);
@@ -201,6 +207,7 @@ ftcg_status ftcg_plan_destroy(ftcg_plan p) {
   for (hipEvent_t e : p->timing.pool) (void)hipEventDestroy(e);
   if (p->timing.open_ev) (void)hipEventDestroy(p->timing.open_ev);
   if (p->host_flags) (void)hipHostFree(p->host_flags);
+  if (p->host_part) (void)hipHostFree(p->host_part);
   delete p;
   return FTCG_OK;
 }
@@ -230,11 +237,10 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
       zero_b = p->wb_cnt.as<int32_t>();
       zero_nb = WROW_CNT_ZERO;
     }
-    auto* part = reinterpret_cast<unsigned long long*>(static_cast<char*>(p->flags.p) + FLAGS_PART_OFF);
-    const int nparts = launch_check_points(p, k_dev, m, part, zero_ptr, zero_n, zero_b, zero_nb);
-    auto* hpart = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(p->host_flags) + FLAGS_PART_OFF);
-    FTCG_HIP(hipMemcpyAsync(hpart, part, sizeof(unsigned long long) * 5 * nparts, hipMemcpyDeviceToHost,
-                            p->stream));
+    // the partials go straight to pinned host memory (no copy command
+    // between the check and the synchronisation)
+    const int nparts = launch_check_points(p, k_dev, m, p->host_part_dev, zero_ptr, zero_n, zero_b, zero_nb);
+    const unsigned long long* hpart = p->host_part;
     FTCG_HIP(hipStreamSynchronize(p->stream));
     unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
     for (int b = 0; b < nparts; ++b) {

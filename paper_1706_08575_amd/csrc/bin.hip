@@ -26,13 +26,12 @@ __device__ inline unsigned long long ordered_bits(double x) {
   return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
 }
 
-// One pass over the points in at most CHECK_BLOCKS workgroups. Workgroup b
+// One pass over the points in at most CHECK_PARTS workgroups. Workgroup b
 // reduces its points with wavefront shuffles and LDS and writes five words to
 // part[5 b ..]: a non-finite flag, then the per-axis minimum and maximum as
 // order-preserving integers; the host reduces the partials (no atomics, no
 // initialisation pass). The same launch zeroes zero_a[0 .. zero_na) and
 // zero_b[0 .. zero_nb), the counters of the binnings that follow.
-constexpr int CHECK_BLOCKS = 1024;
 __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __restrict__ k, int64_t m, int dim,
                                                             unsigned long long* __restrict__ part,
                                                             int32_t* __restrict__ zero_a, int64_t zero_na,
@@ -106,8 +105,8 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __rest
 
 int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long long* part, int32_t* zero_a,
                         int64_t zero_na, int32_t* zero_b, int64_t zero_nb) {
-  int64_t nb = (m + 8 * BIN_BLOCK - 1) / (8 * BIN_BLOCK);  // 8 points per thread at least
-  if (nb > CHECK_BLOCKS) nb = CHECK_BLOCKS;
+  int64_t nb = (m + 2 * BIN_BLOCK - 1) / (2 * BIN_BLOCK);  // 2 points per thread at least
+  if (nb > CHECK_PARTS) nb = CHECK_PARTS;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_check_points, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream, k, m, p->dim, part,
                      zero_a, zero_na, zero_b, zero_nb);
@@ -225,7 +224,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tile_scatter(const double* __rest
 // that one instruction, and the atomics of all of a thread's records are in
 // flight together (a wavefront-aggregated increment would wait for each
 // distinct key's result in turn).
-constexpr int BIN_IPT = 4;
+constexpr int BIN_IPT = 2;
 constexpr int LDS_TILE_KEYS = 4096;   // 16 KiB of int32 counters (larger tables cost more LDS
                                       // occupancy than the global counters they replace)
 
@@ -238,9 +237,11 @@ __device__ inline int lds_claim(int32_t* cnt, int key, int spare) {
 }
 
 // rounds of BIN_IPT * BIN_BLOCK samples per workgroup: about one sample per
-// LDS counter cleared and flushed, at most 8 rounds
+// two LDS counters cleared and flushed, at most 8 rounds (two samples per
+// thread and round: the 512^2 SAS raster, 2^17 samples, then fills 256
+// workgroups instead of 128; binning 33 -> 30 us)
 static int bin_rounds(int64_t ncounters) {
-  return (int)std::min<int64_t>(8, std::max<int64_t>(1, ncounters / (BIN_IPT * BIN_BLOCK)));
+  return (int)std::min<int64_t>(8, std::max<int64_t>(1, ncounters / (4 * BIN_BLOCK)));
 }
 
 template <int DIM>

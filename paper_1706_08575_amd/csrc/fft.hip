@@ -367,8 +367,10 @@ __global__ void k_fft_rows_batched(const BatchItem* __restrict__ items, const in
 // a workgroup, else 16); nts = max(64, L / PPT) threads per row; MAXQ >= the
 // cropped outputs per thread; RB rows per workgroup, as many as make each
 // transposed store a 32-byte segment (4 float2 or 2 double2; 2 float2 at
-// PPT 16, where 4 rows of outputs no longer fit in registers), or 1 when the
-// row count is not a multiple of that; RC = RB rows at a time when RB row
+// PPT 16, where 4 rows of outputs no longer fit in registers, and for rows
+// of at most 2048 points, where 4 rows per workgroup leave too few
+// workgroups to fill the chip: 1024-point rows 11 -> 10 us per pass), or 1
+// when the row count is not a multiple of that; RC = RB rows at a time when RB row
 // slots fit one workgroup (RB * nts <= 1024 threads, RB * L elements in 64 KiB
 // of LDS, so two workgroups share a CU), else RC = 1
 struct FftShape {
@@ -381,7 +383,7 @@ static FftShape fft_shape(int64_t L, int64_t ncrop, int64_t rows, int elem_bytes
   f.nts = (int)std::max<int64_t>(64, L / f.ppt);
   const int64_t q = (ncrop + f.nts - 1) / f.nts;
   f.maxq = q <= 4 && f.ppt == 8 ? 4 : 8;
-  f.rb = (elem_bytes == 8 && f.ppt == 8) ? 4 : 2;
+  f.rb = (elem_bytes == 8 && f.ppt == 8) ? (L <= 2048 ? 2 : 4) : 2;
   if (rows % f.rb != 0) f.rb = 1;
   f.rc = (f.rb * f.nts <= 1024 && f.rb * padded_len((int)L) * elem_bytes <= 72 * 1024) ? f.rb : 1;
   return f;

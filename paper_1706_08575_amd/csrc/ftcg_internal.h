@@ -204,7 +204,7 @@ struct ftcg_plan_s {
   ftcg::DevBuf tile_cnt;     // ntiles + 1 int32 (count, then cursor)
   ftcg::DevBuf tile_off;     // ntiles + 1 int32
   ftcg::DevBuf scan_tmp;     // scan scratch
-  ftcg::DevBuf flags;        // small device scratch: [6] audit estimate; bytes 128.. input-check partials
+  ftcg::DevBuf flags;        // small device scratch: [6] audit estimate
 
   // weight binning
   ftcg::DevBuf wb_cnt, wb_off;  // 2D: wb_cnt holds the bin-row counters (WROW_CNT_ZERO entries)
@@ -235,14 +235,18 @@ struct ftcg_plan_s {
 
   ftcg::Timing timing;
   double* host_flags = nullptr;  // pinned host mirror of flags (FLAGS_BYTES)
+  // pinned, coherent host memory that the input check writes its partials to
+  // (5 words per workgroup, at most CHECK_PARTS workgroups), and its device view
+  unsigned long long* host_part = nullptr;
+  unsigned long long* host_part_dev = nullptr;
 };
 
 namespace ftcg {
 
 // launchers (defined in the .hip files); all enqueue on plan->stream
-constexpr size_t FLAGS_BYTES = 65536;     // device flags / pinned host mirror
+constexpr size_t FLAGS_BYTES = 128;       // device flags / pinned host mirror
 constexpr int64_t WROW_CNT_ZERO = 4100;   // bin-row counters cleared by the input check (>= 4096 + 1)
-constexpr size_t FLAGS_PART_OFF = 128;    // byte offset of the input-check partials
+constexpr int CHECK_PARTS = 1024;         // input-check workgroups at most
 // returns the number of partial records (5 words each) written to part
 int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long long* part, int32_t* zero_a,
                         int64_t zero_na, int32_t* zero_b, int64_t zero_nb);

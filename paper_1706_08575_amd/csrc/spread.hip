@@ -157,6 +157,14 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d(const Rec<real>* __re
 // flush); columns outside the tile are skipped per lane.
 // ---------------------------------------------------------------------------
 
+// Records are staged in LDS in chunks of FX_STAGE (the first chunk while the
+// bound is formed): each record's geometry, weight and sample value are read
+// from global memory by one thread, in parallel over the workgroup, and the
+// tap loop then reads LDS only, so the dependent record -> sample loads are
+// not paid once per record batch of each wavefront (4096^2 SAS raster, 8.4M
+// samples: 0.73 -> 0.59 ms; on small grids the LDS atomics bound the loop).
+constexpr int FX_STAGE = 256;   // 6 KiB: keeps 7 workgroups of tile 32, W = 6 per CU
+
 template <int W, int T>
 __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* __restrict__ recs,
                                                               const float* __restrict__ alpha_s,
@@ -168,7 +176,12 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
   constexpr int PAD = 2 * W - 1;        // halo rows each side
   constexpr int TP = T + 1;             // row pitch (64-bit words)
   constexpr int ROWS = T + 2 * PAD;
+  // stage only while the tile and the stage fit 64 KiB of LDS together
+  constexpr bool STAGED = ROWS * TP * 8 + FX_STAGE * 24 <= 64 * 1024;
+  constexpr int STG = STAGED ? FX_STAGE : 1;
   __shared__ unsigned long long acc[ROWS * TP];
+  __shared__ float4 sgeo[STG];          // f0, f1, c01 (bits), alpha
+  __shared__ float2 sval[STG];          // fhat[src]
   __shared__ float red[SPREAD_BLOCK / 64];
   __shared__ long long red2[SPREAD_BLOCK / 64];
 
@@ -186,11 +199,17 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
   // Bound of every cell of the tile, computed so that it does not depend on
   // the order of the records: first the largest |component| of alpha * fhat,
   // then the integer sum of each record's component bound rounded up in
-  // units of 2^-20 of that maximum.
+  // units of 2^-20 of that maximum. The first pass stages the first chunk.
+  const int first = STAGED ? min(end - beg, STG) : 0;
   float mx = 0.f;
   for (int r = beg + tid; r < end; r += SPREAD_BLOCK) {
+    const Rec<float> rec = recs[r];
     const float a = alpha_s[r];
-    const float2 v = fhat[recs[r].src];
+    const float2 v = fhat[rec.src];
+    if (r - beg < first) {
+      sgeo[r - beg] = make_float4(rec.f0, rec.f1, __int_as_float(rec.c01), a);
+      sval[r - beg] = v;
+    }
     const float cr = v.x * a, ci = v.y * a;
     // fmaxf drops NaN operands: flag non-finite values explicitly
     mx = (isfinite(cr) && isfinite(ci)) ? fmaxf(mx, fmaxf(fabsf(cr), fabsf(ci))) : __builtin_inff();
@@ -212,8 +231,15 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
   const float qs = 1048576.f / mx;
   long long qsum = 0;
   for (int r = beg + tid; r < end; r += SPREAD_BLOCK) {
-    const float a = alpha_s[r];
-    const float2 v = fhat[recs[r].src];
+    float a;
+    float2 v;
+    if (r - beg < first) {   // staged by this thread in the first pass
+      a = sgeo[r - beg].w;
+      v = sval[r - beg];
+    } else {
+      a = alpha_s[r];
+      v = fhat[recs[r].src];
+    }
     qsum += (long long)ceilf(fmaxf(fabsf(v.x * a), fabsf(v.y * a)) * qs) + 1;
   }
   for (int off = 32; off > 0; off >>= 1) qsum += __shfl_xor(qsum, off);
@@ -230,32 +256,56 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
   const int s = lane / L, i = lane - (lane / L) * L;
   const float e2b = __expf(-2.f * beta);
   constexpr int NWAVES = SPREAD_BLOCK / 64;
-  for (int base = beg + wave * RPW; base < end; base += NWAVES * RPW) {
-    const int r = base + s;
-    if (s < RPW && r < end) {
-      const Rec<float> rec = recs[r];
-      const int c1 = rec.c01 >> 16;
-      const int col = c1 - W + 1 + i;
-      if (col >= 0 && col < T) {
-        const float a = alpha_s[r] * scale;
-        const float2 v = fhat[rec.src];
-        const int c0 = (int)(int16_t)(rec.c01 & 0xffff);
-        const float d1 = (float)(i - W + 1) - rec.f1;
-        const float d0 = (float)(1 - W) - rec.f0;
-        const float w10 = __expf(-beta * (d1 * d1 + d0 * d0)) * a;
-        float q = __expf(-beta * (2.f * d0 + 1.f));
-        float pr = v.x * w10, pi = v.y * w10;
-        unsigned long long* dst = acc + (c0 - W + 1 + PAD) * TP + col;
+  // one record's 2W x 2W taps: lane i takes footprint column i
+  auto splat = [&](float f0, float f1, int c01, float araw, float2 v) {
+    const int c1 = c01 >> 16;
+    const int col = c1 - W + 1 + i;
+    if (col < 0 || col >= T) return;
+    const float a = araw * scale;
+    const int c0 = (int)(int16_t)(c01 & 0xffff);
+    const float d1 = (float)(i - W + 1) - f1;
+    const float d0 = (float)(1 - W) - f0;
+    const float w10 = __expf(-beta * (d1 * d1 + d0 * d0)) * a;
+    float q = __expf(-beta * (2.f * d0 + 1.f));
+    float pr = v.x * w10, pi = v.y * w10;
+    unsigned long long* dst = acc + (c0 - W + 1 + PAD) * TP + col;
 #pragma unroll
-        for (int j = 0; j < L; ++j) {
-          const int ir = (int)pr, ii = (int)pi;   // truncation toward zero
-          const unsigned hi = (unsigned)ii + (unsigned)(ir >> 31);
-          const unsigned long long packed = ((unsigned long long)hi << 32) | (unsigned)ir;
-          __hip_atomic_fetch_add(dst + j * TP, packed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          pr *= q;
-          pi *= q;
-          q *= e2b;
+    for (int j = 0; j < L; ++j) {
+      const int ir = (int)pr, ii = (int)pi;   // truncation toward zero
+      const unsigned hi = (unsigned)ii + (unsigned)(ir >> 31);
+      const unsigned long long packed = ((unsigned long long)hi << 32) | (unsigned)ir;
+      __hip_atomic_fetch_add(dst + j * TP, packed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      pr *= q;
+      pi *= q;
+      q *= e2b;
+    }
+  };
+  if constexpr (STAGED) {
+    for (int cb = beg; cb < end; cb += FX_STAGE) {
+      const int cn = min(end - cb, FX_STAGE);
+      if (cb != beg) {   // later chunks: restage once every wavefront has left the previous one
+        __syncthreads();
+        for (int r = tid; r < cn; r += SPREAD_BLOCK) {
+          const Rec<float> rec = recs[cb + r];
+          sgeo[r] = make_float4(rec.f0, rec.f1, __int_as_float(rec.c01), alpha_s[cb + r]);
+          sval[r] = fhat[rec.src];
         }
+        __syncthreads();
+      }
+      for (int base = wave * RPW; base < cn; base += NWAVES * RPW) {
+        const int r = base + s;
+        if (s < RPW && r < cn) {
+          const float4 g4 = sgeo[r];
+          splat(g4.x, g4.y, __float_as_int(g4.z), g4.w, sval[r]);
+        }
+      }
+    }
+  } else {
+    for (int base = beg + wave * RPW; base < end; base += NWAVES * RPW) {
+      const int r = base + s;
+      if (s < RPW && r < end) {
+        const Rec<float> rec = recs[r];
+        splat(rec.f0, rec.f1, rec.c01, alpha_s[r], fhat[rec.src]);
       }
     }
   }
