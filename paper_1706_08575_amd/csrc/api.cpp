@@ -218,6 +218,7 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
   return guarded([&] {
     p->have_points = false;
     p->have_weights = false;
+    p->finish_recs = false;
     p->m = m;
     // 1) finiteness + bounding box (one host synchronisation); the same
     //    launch zeroes the tile counters of step 3
@@ -265,6 +266,7 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
       // tile records and the bin-row sort of the weight sum from the same
       // passes over the samples; the records get their weights afterwards
       setup_weight_bins(p, kmin, kmax);
+      p->finish_recs = p->wmode == FTCG_W_PLAIN;
       p->recs.ensure(rsz * cap);
       p->alpha_s.ensure(asz * cap);
       p->tile_off.ensure(sizeof(int32_t) * (p->ntiles + 1));
@@ -281,9 +283,12 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
         run_learned_with_audit(p, k_dev);
       }
       p->have_weights = true;
-      timing_begin(p, STEP_BIN);
-      refill_alpha_dev(p);
-      timing_end(p, STEP_BIN);
+      if (p->finish_recs || p->wmode != FTCG_W_PLAIN) {   // records not weighted by the weight sum
+        timing_begin(p, STEP_BIN);
+        refill_alpha_dev(p);
+        timing_end(p, STEP_BIN);
+      }
+      p->finish_recs = false;
       p->nrec = -1;
       p->have_points = true;
       return;

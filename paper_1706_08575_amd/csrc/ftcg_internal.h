@@ -215,6 +215,9 @@ struct ftcg_plan_s {
   ftcg::DevBuf ws_inv;       // sorted position of every sample (caller order)
   ftcg::DevBuf ws_sum;       // 2D: per-sample weight sums in bin order (symmetric form)
   bool ws_sum_fresh = false; // ws_sum holds the self terms only (preset by the bin sort)
+  // set by the fused binning: the finish of the symmetric weight sum also
+  // writes the record-order weights (through ws_inv) and then clears it
+  bool finish_recs = false;
   ftcg::WBinGeom wgeom{};
   bool have_wbins = false;
   bool weights_only = false;  // internal plans that only compute weights (no tile binning)

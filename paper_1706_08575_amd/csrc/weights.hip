@@ -439,6 +439,22 @@ __global__ __launch_bounds__(WB_BLOCK) void k_weights_from_sums(const double* __
   if (t < m) alpha[sidx[t]] = wscale<2>() / wsum[t];
 }
 
+// the same, and the weights of the tile records (record r of sample j gets
+// alpha_j), the record count read on the device: one launch for both orders
+template <class real>
+__global__ __launch_bounds__(WB_BLOCK) void k_weights_from_sums_recs(const double* __restrict__ wsum,
+                                                                     const int32_t* __restrict__ sidx,
+                                                                     const int32_t* __restrict__ inv, int64_t m,
+                                                                     double* __restrict__ alpha,
+                                                                     const Rec<real>* __restrict__ recs,
+                                                                     const int32_t* __restrict__ nrec_dev,
+                                                                     real* __restrict__ alpha_s) {
+  const int64_t t0 = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x, gs = (int64_t)gridDim.x * WB_BLOCK;
+  for (int64_t t = t0; t < m; t += gs) alpha[sidx[t]] = wscale<2>() / wsum[t];
+  const int64_t nrec = *nrec_dev;
+  for (int64_t r = t0; r < nrec; r += gs) alpha_s[r] = (real)(wscale<2>() / wsum[inv[recs[r].src]]);
+}
+
 __global__ __launch_bounds__(WB_BLOCK) void k_fill_f64(double* __restrict__ a, int64_t n, double v) {
   const int64_t t = (int64_t)blockIdx.x * WB_BLOCK + threadIdx.x;
   if (t < n) a[t] = v;
@@ -731,8 +747,9 @@ void setup_weight_bins(ftcg_plan p, const double* kmin, const double* kmax) {
 // tile binning)
 void sort_weight_rows(ftcg_plan p) {
   const WBinGeom& g = p->wgeom;
-  // the inverse map serves the learned features and the audit only
-  const bool need_inv = p->wmode == FTCG_W_LEARNED || p->weights_only;
+  // the inverse map serves the learned features, the audit and the
+  // record-order weights written by the finish of the weight sum
+  const bool need_inv = p->wmode == FTCG_W_LEARNED || p->weights_only || p->finish_recs;
   // the symmetric weight sum starts from the self terms, preset here
   p->ws_sum.ensure(sizeof(double) * p->m);
   hipLaunchKernelGGL(k_wrow_sort, dim3((unsigned)g.nb[0]), dim3(WB_BLOCK), 0, p->stream, g,
@@ -813,6 +830,20 @@ static void launch_weights_sym(ftcg_plan p) {
   const int chunk = cx * std::max(1, g.nb[0] / 64);
   hipLaunchKernelGGL((k_frame_weights_sym<WT, S>), dim3((unsigned)nb), dim3(WB_BLOCK), 0, p->stream,
                      p->ws_k.as<WSample<2>>(), p->wb_off.as<int32_t>(), g, cx, chunk, wsum);
+  if (p->finish_recs) {
+    const unsigned fb = (unsigned)std::min<int64_t>(2048, (2 * m + WB_BLOCK - 1) / WB_BLOCK);
+    const int32_t* nrec = p->tile_off.as<int32_t>() + p->ntiles;
+    if (p->dtype == FTCG_F64)
+      hipLaunchKernelGGL(k_weights_from_sums_recs<double>, dim3(fb), dim3(WB_BLOCK), 0, p->stream, wsum,
+                         p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>(), m, p->alpha.as<double>(),
+                         p->recs.as<Rec<double>>(), nrec, p->alpha_s.as<double>());
+    else
+      hipLaunchKernelGGL(k_weights_from_sums_recs<float>, dim3(fb), dim3(WB_BLOCK), 0, p->stream, wsum,
+                         p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>(), m, p->alpha.as<double>(),
+                         p->recs.as<Rec<float>>(), nrec, p->alpha_s.as<float>());
+    p->finish_recs = false;
+    return;
+  }
   hipLaunchKernelGGL(k_weights_from_sums, dim3((unsigned)((m + WB_BLOCK - 1) / WB_BLOCK)), dim3(WB_BLOCK), 0,
                      p->stream, wsum, p->ws_idx.as<int32_t>(), m, p->alpha.as<double>());
 }
