@@ -174,11 +174,14 @@ ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan plan, int samples_per_lane, in
 /* Per-step timing with HIP events on the plan's stream.
  * enable != 0 records events around every step of later calls; ftcg_plan_timing
  * synchronises the stream and returns, for each step s in
- * {0 input check + tile binning, 1 frame-weight sum kernel, 2 spread,
- *  3 fft pass 1, 4 fft pass 2 + deapodize + crop, 5 neighbour binning for weights,
- *  6 learned-weight inference, 7 learned-weight audit},
- * the summed milliseconds ms[s] and the number of launches count[s]
- * (arrays of 8 entries; unused entries are 0), then resets the sums. */
+ * {0 input check + tile binning, 1 frame-weight sum kernel and its finish,
+ *  2 spread, 3 fft pass 1, 4 fft pass 2 + deapodize + crop, 5 neighbour binning
+ *  for weights, 6 learned-weight inference, 7 learned-weight audit},
+ * the summed milliseconds ms[s] and the number of timed intervals count[s]
+ * (arrays of 8 entries; unused entries are 0), then resets the sums. A step
+ * can be timed in several intervals per call (step 0: the input check, then
+ * the binning after the host has read the check's result; the host's wait
+ * in between is in no step). */
 ftcg_status ftcg_plan_enable_timing(ftcg_plan plan, int enable);
 ftcg_status ftcg_plan_timing(ftcg_plan plan, double* ms, int64_t* count);
 

@@ -242,6 +242,7 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     // between the check and the synchronisation)
     const int nparts = launch_check_points(p, k_dev, m, p->host_part_dev, zero_ptr, zero_n, zero_b, zero_nb);
     const unsigned long long* hpart = p->host_part;
+    timing_end(p, STEP_BIN);   // the step's time excludes the host's turn
     FTCG_HIP(hipStreamSynchronize(p->stream));
     unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
     for (int b = 0; b < nparts; ++b) {
@@ -257,6 +258,7 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
       kmin[a] = decode_ordered(lo[a]);
       kmax[a] = decode_ordered(hi[a]);
     }
+    timing_begin(p, STEP_BIN);
     // 2) weights (caller order)
     p->alpha.ensure(sizeof(double) * m);
     const int64_t cap = m << p->dim;  // worst case 2^dim tile records per sample
