@@ -181,6 +181,32 @@ def test_2d_spread_step_mfma_vs_oracle():
         assert O.rel_l2(H, Href) < TOL_NORTH_STAR, (n, m)
 
 
+@pytest.mark.parametrize("tile", [16, 32, 64, 128])
+def test_2d_spread_fixed_dense_tiles_vs_oracle(tile):
+    # fixed-point accumulation with a dense cluster (thousands of records in
+    # a few tiles: many LDS staging chunks of records per tile, the last one
+    # ragged) beside sparse tiles and samples on the periodic seam; tile 128
+    # leaves no LDS room for staging and reads the records directly
+    from paper_1706_08575_amd.ftcg import Plan
+    rng = np.random.default_rng(24)
+    n = 128
+    kd = rng.uniform(-6.0, 6.0, size=(6001, 2)) + np.array([10.3, -20.7])
+    ks = rng.uniform(-0.6 * n, 0.6 * n, size=(1500, 2))
+    ks[:20, 1] = -n / 2 + 0.01 * rng.random(20)
+    k = np.vstack([kd, ks])
+    f = S.random_values(25, k.shape[0])
+    with Plan(n, dim=2, dtype="f32", weights="none") as P:
+        P.set_tuning(tile, "fixed", 1)
+        P.set_points(dev(k))
+        ff = dev(f, torch.complex64)
+        H = host(P.spread_only(ff))
+        P.set_points(dev(k))        # re-binned: the integer sums do not depend on record order
+        H2 = host(P.spread_only(ff))
+    assert np.array_equal(H, H2)
+    Href = O.spread(k, f, n)
+    assert O.rel_l2(H, Href) < TOL_NORTH_STAR
+
+
 def test_plan_autotuner(tmp_path, monkeypatch):
     # the tuner times every candidate launch on the caller's data, leaves the
     # plan on the fastest, and the result stays within the float32 bar
