@@ -98,9 +98,9 @@ ftcg_status ftcg_plan_destroy(ftcg_plan plan);
  *   m     : number of samples, 1 <= m < 2^31.
  *   k_dev : device float64 array, m x dim, row-major (k_dev[j*dim + a]).
  * Bins the samples by grid tile and, in FTCG_W_PLAIN / FTCG_W_LEARNED mode,
- * computes the weights. Non-finite coordinates give FTCG_EINVAL (checked on
- * the device; this call synchronises the stream once to read that flag and
- * the record count). */
+ * computes the weights. A non-finite coordinate, or one beyond 2^40 in
+ * magnitude, gives FTCG_EINVAL (checked on the device; the host waits once,
+ * for that check alone, while the binning passes already run). */
 ftcg_status ftcg_set_points(ftcg_plan plan, int64_t m, const double* k_dev);
 
 /* FTCG_W_USER only: alpha_dev is a device float64 array of m weights. */

@@ -5,6 +5,7 @@
 #include <new>
 
 #include "ftcg_internal.h"
+#include "wbins.h"
 #include "mlp_internal.h"
 
 namespace ftcg {
@@ -38,12 +39,6 @@ void timing_end(ftcg_plan p, int step) {
   t.open_ev = nullptr;
 }
 
-static double decode_ordered(unsigned long long o) {
-  unsigned long long b = (o & 0x8000000000000000ull) ? (o & 0x7fffffffffffffffull) : ~o;
-  double x;
-  memcpy(&x, &b, sizeof x);
-  return x;
-}
 
 static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
@@ -178,12 +173,13 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
       p->host_flags = nullptr;
       throw StatusError{FTCG_ENOMEM};
     }
-    if (hipHostMalloc((void**)&p->host_part, sizeof(unsigned long long) * 5 * CHECK_PARTS,
-                      hipHostMallocCoherent) != hipSuccess) {
-      p->host_part = nullptr;
+    p->check_part.ensure(sizeof(unsigned long long) * 5 * CHECK_PARTS);
+    p->geo.ensure(sizeof(CheckOut));
+    if (hipHostMalloc((void**)&p->host_geo, sizeof(CheckOut), hipHostMallocCoherent) != hipSuccess) {
+      p->host_geo = nullptr;
       throw StatusError{FTCG_ENOMEM};
     }
-    FTCG_HIP(hipHostGetDevicePointer((void**)&p->host_part_dev, p->host_part, 0));
+    FTCG_HIP(hipEventCreateWithFlags(&p->ev_check, hipEventDisableTiming));
   });
   if (st != FTCG_OK) {
     ftcg_plan_destroy(p);
@@ -196,7 +192,7 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
 ftcg_status ftcg_plan_destroy(ftcg_plan p) {
   if (!p) return FTCG_EINVAL;
   (void)hipStreamSynchronize(p->stream);
-  DevBuf* bufs[] = {&p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp,
+  DevBuf* bufs[] = {&p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp, &p->tile_scan_tmp, &p->check_part, &p->geo,
                     &p->flags,  &p->wb_cnt, &p->wb_off, &p->wb_rowoff, &p->wb_rowbuf, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->ws_inv, &p->ws_sum, &p->audit_buf,
                     &p->grid,   &p->fft_tmp, &p->deapod, &p->twiddle, &p->tile_order};
   for (DevBuf* b : bufs) b->release();
@@ -207,7 +203,8 @@ ftcg_status ftcg_plan_destroy(ftcg_plan p) {
   for (hipEvent_t e : p->timing.pool) (void)hipEventDestroy(e);
   if (p->timing.open_ev) (void)hipEventDestroy(p->timing.open_ev);
   if (p->host_flags) (void)hipHostFree(p->host_flags);
-  if (p->host_part) (void)hipHostFree(p->host_part);
+  if (p->host_geo) (void)hipHostFree(p->host_geo);
+  if (p->ev_check) (void)hipEventDestroy(p->ev_check);
   delete p;
   return FTCG_OK;
 }
@@ -220,8 +217,9 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     p->have_weights = false;
     p->finish_recs = false;
     p->m = m;
-    // 1) finiteness + bounding box (one host synchronisation); the same
-    //    launch zeroes the tile counters of step 3
+    // 1) input check: finiteness, bounding box and the neighbour-bin
+    //    geometry, reduced on the device; the check also zeroes the tile and
+    //    bin-row counters of the binning passes
     timing_begin(p, STEP_BIN);
     int32_t* zero_ptr = nullptr;
     int64_t zero_n = 0;
@@ -231,99 +229,99 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
       zero_ptr = p->tile_cnt.as<int32_t>();
       zero_n = p->ntiles + 1;
     }
+    const bool rows2d = p->dim == 2 && (p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED);
     int32_t* zero_b = nullptr;
     int64_t zero_nb = 0;
-    if (p->dim == 2 && (p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED)) {
+    if (rows2d) {
       p->wb_cnt.ensure(sizeof(int32_t) * WROW_CNT_ZERO);
       zero_b = p->wb_cnt.as<int32_t>();
       zero_nb = WROW_CNT_ZERO;
     }
-    // the partials go straight to pinned host memory (no copy command
-    // between the check and the synchronisation)
-    const int nparts = launch_check_points(p, k_dev, m, p->host_part_dev, zero_ptr, zero_n, zero_b, zero_nb);
-    const unsigned long long* hpart = p->host_part;
-    timing_end(p, STEP_BIN);   // the step's time excludes the host's turn
-    FTCG_HIP(hipStreamSynchronize(p->stream));
-    unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
-    for (int b = 0; b < nparts; ++b) {
-      const unsigned long long* q = hpart + 5 * b;
-      if (q[0] != 0) throw StatusError{FTCG_EINVAL};
-      for (int a = 0; a < 2; ++a) {
-        lo[a] = q[1 + a] < lo[a] ? q[1 + a] : lo[a];
-        hi[a] = q[3 + a] > hi[a] ? q[3 + a] : hi[a];
-      }
-    }
-    double kmin[2] = {0, 0}, kmax[2] = {0, 0};
-    for (int a = 0; a < p->dim; ++a) {
-      kmin[a] = decode_ordered(lo[a]);
-      kmax[a] = decode_ordered(hi[a]);
-    }
-    timing_begin(p, STEP_BIN);
-    // 2) weights (caller order)
-    p->alpha.ensure(sizeof(double) * m);
+    auto* part = p->check_part.as<unsigned long long>();
+    const int nparts = launch_check_points(p, k_dev, m, part, zero_ptr, zero_n, zero_b, zero_nb);
+    launch_check_reduce(p, part, nparts);
+    timing_end(p, STEP_BIN);
+    FTCG_HIP(hipEventRecord(p->ev_check, p->stream));
+    // 2) binning passes that need no host decision are enqueued before the
+    //    host waits for the check, and run during the host's turn (their
+    //    kernels keep every index in range for any input; rejected points
+    //    are reported below):
+    //    - 2D weights, tile counters in LDS: tile records and bin rows fused;
+    //    - otherwise the tile binning: whole when its counters fit LDS, else
+    //      the counting + scan (the tile scatter writes the weights with the
+    //      records later; there these passes outlast the host's turn, and
+    //      the bin rows follow it).
+    //    Records written here get their weights once those are known.
+    const bool tiles = !p->weights_only;
+    const bool early_scatter = tiles && tile_keys_in_lds(p);
+    const bool fused = rows2d && early_scatter;
     const int64_t cap = m << p->dim;  // worst case 2^dim tile records per sample
-    const size_t rsz = p->dtype == FTCG_F64 ? sizeof(Rec<double>) : sizeof(Rec<float>);
-    const size_t asz = p->dtype == FTCG_F64 ? sizeof(double) : sizeof(float);
-    if (fused_binning_ok(p)) {
-      // tile records and the bin-row sort of the weight sum from the same
-      // passes over the samples; the records get their weights afterwards
-      setup_weight_bins(p, kmin, kmax);
-      p->finish_recs = p->wmode == FTCG_W_PLAIN;
-      p->recs.ensure(rsz * cap);
-      p->alpha_s.ensure(asz * cap);
+    if (tiles) {
+      p->recs.ensure((p->dtype == FTCG_F64 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * cap);
+      p->alpha_s.ensure((p->dtype == FTCG_F64 ? sizeof(double) : sizeof(float)) * cap);
       p->tile_off.ensure(sizeof(int32_t) * (p->ntiles + 1));
+      p->tile_scan_tmp.ensure(scan_tmp_bytes(p->ntiles));
+    }
+    if (rows2d) {
+      p->wb_rowoff.ensure(sizeof(int32_t) * (WROW_MAX + 1));
+      p->wb_rowbuf.ensure(sizeof(RowRec) * m);
+      p->scan_tmp.ensure(scan_tmp_bytes(WROW_MAX));
+    }
+    if (fused) {
+      timing_begin(p, STEP_BIN);
       bin_points_fused(p, k_dev);
       timing_end(p, STEP_BIN);
-      timing_begin(p, STEP_WBIN);
-      sort_weight_rows(p);
-      timing_end(p, STEP_WBIN);
-      p->have_wbins = true;
-      if (p->wmode == FTCG_W_PLAIN) {
-        run_plain_weights(p);
-      } else {
-        if (!p->mlp) throw StatusError{FTCG_ESTATE};
-        run_learned_with_audit(p, k_dev);
-      }
-      p->have_weights = true;
-      if (p->finish_recs || p->wmode != FTCG_W_PLAIN) {   // records not weighted by the weight sum
-        timing_begin(p, STEP_BIN);
-        refill_alpha_dev(p);
-        timing_end(p, STEP_BIN);
-      }
-      p->finish_recs = false;
-      p->nrec = -1;
-      p->have_points = true;
-      return;
+    } else if (tiles) {
+      timing_begin(p, STEP_BIN);
+      if (early_scatter)
+        bin_points_k(p, k_dev);   // weight 1 until the weights are known
+      else
+        bin_count_k(p, k_dev);
+      timing_end(p, STEP_BIN);
     }
-    if (p->wmode == FTCG_W_PLAIN) {
-      timing_end(p, STEP_BIN);
-      build_weight_bins(p, k_dev, kmin, kmax);
-      run_plain_weights(p);
-      timing_begin(p, STEP_BIN);
-      p->have_weights = true;
-    } else if (p->wmode == FTCG_W_LEARNED) {
-      if (!p->mlp) throw StatusError{FTCG_ESTATE};
-      timing_end(p, STEP_BIN);
-      build_weight_bins(p, k_dev, kmin, kmax);
-      run_learned_with_audit(p, k_dev);
-      timing_begin(p, STEP_BIN);
+    FTCG_HIP(hipEventSynchronize(p->ev_check));
+    const CheckOut chk = *p->host_geo;
+    if (chk.bad) throw StatusError{FTCG_EINVAL};
+    p->wgeom = chk.g;
+    // 3) weights (caller order)
+    p->alpha.ensure(sizeof(double) * m);
+    const bool computed = p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED;
+    // records already written: in 2D the finish of the plain weight sum
+    // weights them (through the caller-to-bin map the bin sort then writes)
+    const bool want_finish = early_scatter && p->dim == 2 && p->wmode == FTCG_W_PLAIN;
+    if (computed) {
+      if (p->wmode == FTCG_W_LEARNED && !p->mlp) throw StatusError{FTCG_ESTATE};
+      p->finish_recs = want_finish;
+      if (p->dim == 2) {
+        setup_weight_bins(p);
+        timing_begin(p, STEP_WBIN);
+        if (!fused) wrow_bin(p, k_dev, p->wgeom.nb[0]);
+        sort_weight_rows(p);
+        timing_end(p, STEP_WBIN);
+        p->have_wbins = true;
+      } else {
+        build_weight_bins_1d(p, k_dev);
+      }
+      if (p->wmode == FTCG_W_PLAIN)
+        run_plain_weights(p);
+      else
+        run_learned_with_audit(p, k_dev);
       p->have_weights = true;
     } else if (p->wmode == FTCG_W_NONE) {
       fill_ones(p->alpha.as<double>(), m, p->stream);
       p->have_weights = true;
     }
-    if (p->weights_only) {
+    // 4) the records' weights
+    if (tiles) {
+      const bool finished = want_finish && !p->finish_recs;
+      timing_begin(p, STEP_BIN);
+      if (!early_scatter)
+        bin_scatter_k(p, k_dev);   // with the weights when there are any
+      else if (computed && !finished)
+        refill_alpha_dev(p);
       timing_end(p, STEP_BIN);
-      p->have_points = true;
-      return;
     }
-    // 3) tile binning of spread records
-    p->recs.ensure(rsz * cap);
-    p->alpha_s.ensure(asz * cap);
-    p->tile_off.ensure(sizeof(int32_t) * (p->ntiles + 1));
-    p->scan_tmp.ensure(scan_tmp_bytes(p->ntiles));
-    bin_points_k(p, k_dev);
-    timing_end(p, STEP_BIN);
+    p->finish_recs = false;
     p->nrec = -1;  // on the device (tile_off[ntiles]); read only when asked for
     p->have_points = true;
   });

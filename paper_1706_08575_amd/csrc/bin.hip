@@ -29,8 +29,8 @@ __device__ inline unsigned long long ordered_bits(double x) {
 // One pass over the points in at most CHECK_PARTS workgroups. Workgroup b
 // reduces its points with wavefront shuffles and LDS and writes five words to
 // part[5 b ..]: a non-finite flag, then the per-axis minimum and maximum as
-// order-preserving integers; the host reduces the partials (no atomics, no
-// initialisation pass). The same launch zeroes zero_a[0 .. zero_na) and
+// order-preserving integers; one workgroup of k_check_reduce then reduces the
+// partials (no atomics, no initialisation pass). The same launch zeroes zero_a[0 .. zero_na) and
 // zero_b[0 .. zero_nb), the counters of the binnings that follow.
 __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __restrict__ k, int64_t m, int dim,
                                                             unsigned long long* __restrict__ part,
@@ -126,11 +126,15 @@ struct TileGeom {
   int W;
 };
 
+// u modulo G in [0, G). Rounding can land exactly on G; anything still
+// outside [0, G) (a non-finite u, or |u| so large that the reduction has no
+// bits left) becomes 0, so every tile key stays in range for any input. The
+// binning can run before the host has seen the input check, which then
+// rejects non-finite samples.
 __device__ inline double wrap_u(double u, double G) {
   double w = u - G * floor(u / G);
-  if (w >= G) w -= G;   // rounding can land exactly on G
-  if (w < 0.0) w = 0.0;
-  return w;
+  if (w >= G) w -= G;
+  return (w >= 0.0 && w < G) ? w : 0.0;
 }
 
 __device__ inline int floor_div(int a, int b) {  // b > 0
@@ -355,8 +359,10 @@ __device__ inline void bin2_keys(const double* __restrict__ k, int64_t m, const 
 
 template <class real>
 __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_count(const double* __restrict__ k, int64_t m, TileGeom tg,
-                                                          WBinGeom wg, int32_t* __restrict__ tile_cnt, int ntiles,
+                                                          const WBinGeom* __restrict__ wgp,
+                                                          int32_t* __restrict__ tile_cnt, int ntiles,
                                                           int32_t* __restrict__ row_cnt, int rounds) {
+  const WBinGeom wg = *wgp;
   extern __shared__ int32_t sm[];
   int32_t* ht = sm;
   int32_t* hr = sm + ntiles;
@@ -389,10 +395,12 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_count(const double* __restri
 
 template <class real>
 __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_scatter(const double* __restrict__ k, int64_t m, TileGeom tg,
-                                                            WBinGeom wg, int32_t* __restrict__ tile_cursor,
+                                                            const WBinGeom* __restrict__ wgp,
+                                                            int32_t* __restrict__ tile_cursor,
                                                             int ntiles, int32_t* __restrict__ row_cursor,
                                                             int rounds, Rec<real>* __restrict__ recs,
                                                             RowRec* __restrict__ rowbuf) {
+  const WBinGeom wg = *wgp;
   extern __shared__ int32_t sm[];   // ntiles + nrow counters, then LDS_SPARE spare words
   int32_t* bt = sm;
   int32_t* br = sm + ntiles;
@@ -491,14 +499,13 @@ static TileGeom tile_geom(ftcg_plan p) {
 }
 
 // tile binning; the tile counters were zeroed by the input check
-template <class real>
-static void bin_points_t(ftcg_plan p, const double* k) {
+// counting and scan of the tile binning (cnt then holds the cursors)
+static void bin_count_t(ftcg_plan p, const double* k) {
   const TileGeom g = tile_geom(p);
   hipStream_t s = p->stream;
   const int64_t m = p->m;
   int32_t* cnt = p->tile_cnt.as<int32_t>();
   int32_t* off = p->tile_off.as<int32_t>();
-  const double* alpha = p->have_weights ? p->alpha.as<double>() : nullptr;
   const int nkeys = (int)p->ntiles;
   if (nkeys <= LDS_TILE_KEYS) {
     const int rounds = bin_rounds(nkeys);
@@ -509,7 +516,32 @@ static void bin_points_t(ftcg_plan p, const double* k) {
       hipLaunchKernelGGL(k_tile_count_lds<1>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, cnt, nkeys, rounds);
     else
       hipLaunchKernelGGL(k_tile_count_lds<2>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, cnt, nkeys, rounds);
-    exclusive_scan_i32(cnt, off, p->ntiles, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
+  } else {
+    const unsigned nb = (unsigned)((m + BIN_BLOCK - 1) / BIN_BLOCK);
+    if (p->dim == 1)
+      hipLaunchKernelGGL(k_tile_count<1>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
+    else
+      hipLaunchKernelGGL(k_tile_count<2>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
+  }
+  exclusive_scan_i32(cnt, off, p->ntiles, p->tile_scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
+  FTCG_HIP(hipGetLastError());
+}
+
+// scatter of the tile records; with weights (p->have_weights) they go into
+// record order as the records are written, else every record gets weight 1
+template <class real>
+static void bin_scatter_t(ftcg_plan p, const double* k) {
+  const TileGeom g = tile_geom(p);
+  hipStream_t s = p->stream;
+  const int64_t m = p->m;
+  int32_t* cnt = p->tile_cnt.as<int32_t>();
+  const double* alpha = p->have_weights ? p->alpha.as<double>() : nullptr;
+  const int nkeys = (int)p->ntiles;
+  if (nkeys <= LDS_TILE_KEYS) {
+    const int rounds = bin_rounds(nkeys);
+    const int64_t per = (int64_t)rounds * BIN_IPT * BIN_BLOCK;
+    const unsigned nb = (unsigned)((m + per - 1) / per);
+    const size_t lds = sizeof(int32_t) * (nkeys + LDS_SPARE);
     if (p->dim == 1)
       hipLaunchKernelGGL((k_tile_scatter_lds<1, real>), dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, g, alpha, cnt,
                          nkeys, rounds, p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
@@ -518,11 +550,6 @@ static void bin_points_t(ftcg_plan p, const double* k) {
                          nkeys, rounds, p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
   } else {
     const unsigned nb = (unsigned)((m + BIN_BLOCK - 1) / BIN_BLOCK);
-    if (p->dim == 1)
-      hipLaunchKernelGGL(k_tile_count<1>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
-    else
-      hipLaunchKernelGGL(k_tile_count<2>, dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, cnt);
-    exclusive_scan_i32(cnt, off, p->ntiles, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
     if (p->dim == 1)
       hipLaunchKernelGGL((k_tile_scatter<1, real>), dim3(nb), dim3(BIN_BLOCK), 0, s, k, m, g, alpha, cnt,
                          p->recs.as<Rec<real>>(), p->alpha_s.as<real>());
@@ -533,27 +560,39 @@ static void bin_points_t(ftcg_plan p, const double* k) {
   FTCG_HIP(hipGetLastError());
 }
 
-bool fused_binning_ok(ftcg_plan p) {
-  return p->dim == 2 && (p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED) && !p->weights_only &&
-         p->ntiles <= LDS_TILE_KEYS;
+bool tile_keys_in_lds(ftcg_plan p) { return p->ntiles <= LDS_TILE_KEYS; }
+
+void bin_count_k(ftcg_plan p, const double* k) { bin_count_t(p, k); }
+
+void bin_scatter_k(ftcg_plan p, const double* k) {
+  if (p->dtype == FTCG_F64)
+    bin_scatter_t<double>(p, k);
+  else
+    bin_scatter_t<float>(p, k);
 }
 
+
+// the bin-row geometry comes from the input check in device memory (these
+// passes are enqueued before the host has read it): LDS is sized for
+// WROW_MAX rows, the kernels clear and flush the geometry's own row count,
+// and the row scan covers all WROW_MAX counters (rows past the count stay
+// empty)
 template <class real>
 static void bin_points_fused_t(ftcg_plan p, const double* k) {
   const TileGeom tg = tile_geom(p);
-  const WBinGeom& wg = p->wgeom;
+  const WBinGeom* wg = &p->geo.as<CheckOut>()->g;
   hipStream_t s = p->stream;
   const int64_t m = p->m;
   int32_t* tcnt = p->tile_cnt.as<int32_t>();   // zeroed by the input check
   int32_t* rcnt = p->wb_cnt.as<int32_t>();     // zeroed by the input check
-  const int rounds = bin_rounds(p->ntiles + wg.nb[0]);
+  const int rounds = bin_rounds(p->ntiles);
   const int64_t per = (int64_t)rounds * BIN_IPT * BIN_BLOCK;
   const unsigned nb = (unsigned)((m + per - 1) / per);
-  const size_t lds = sizeof(int32_t) * (size_t)(p->ntiles + wg.nb[0] + LDS_SPARE);   // <= 32.25 KiB
+  const size_t lds = sizeof(int32_t) * (size_t)(p->ntiles + WROW_MAX + LDS_SPARE);   // <= 32.25 KiB
   hipLaunchKernelGGL(k_bin2_count<real>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, tg, wg, tcnt, (int)p->ntiles,
                      rcnt, rounds);
   exclusive_scan_pair_i32(tcnt, p->tile_off.as<int32_t>(), p->ntiles, tcnt, rcnt, p->wb_rowoff.as<int32_t>(),
-                          wg.nb[0], rcnt, s);
+                          WROW_MAX, rcnt, s);
   hipLaunchKernelGGL(k_bin2_scatter<real>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, tg, wg, tcnt, (int)p->ntiles,
                      rcnt, rounds, p->recs.as<Rec<real>>(), p->wb_rowbuf.as<RowRec>());
   FTCG_HIP(hipGetLastError());
@@ -580,10 +619,8 @@ void refill_alpha_dev(ftcg_plan p) {
 }
 
 void bin_points_k(ftcg_plan p, const double* k) {
-  if (p->dtype == FTCG_F64)
-    bin_points_t<double>(p, k);
-  else
-    bin_points_t<float>(p, k);
+  bin_count_k(p, k);
+  bin_scatter_k(p, k);
 }
 
 void refill_alpha(ftcg_plan p) {

@@ -39,6 +39,9 @@ struct DevBuf {
   size_t bytes = 0;
   void ensure(size_t need) {
     if (need <= bytes) return;
+    // work still queued may use the old buffer (a plan enqueues some of
+    // its passes before it waits for anything)
+    if (p) (void)hipDeviceSynchronize();
     release();
     if (hipMalloc(&p, need) != hipSuccess) {
       p = nullptr;
@@ -81,6 +84,18 @@ struct WBinGeom {
   int nb[2];         // bins per axis
   int span;          // neighbour bins each side covering the box of radius R
   double R;
+};
+
+// bin rows (2D) at most: the row counters and the row scan have this size
+constexpr int WROW_MAX = 4096;
+
+// the input check reduced on the device: bounding box, the neighbour-bin
+// geometry derived from it, and whether the points are rejected
+struct CheckOut {
+  WBinGeom g;
+  double kmin[2], kmax[2];
+  int bad;   // a coordinate is non-finite or beyond 2^40 in magnitude
+  int pad;
 };
 
 // a sample in bin order: coordinates, then sin(pi k_a), cos(pi k_a) per axis
@@ -204,6 +219,7 @@ struct ftcg_plan_s {
   ftcg::DevBuf tile_cnt;     // ntiles + 1 int32 (count, then cursor)
   ftcg::DevBuf tile_off;     // ntiles + 1 int32
   ftcg::DevBuf scan_tmp;     // scan scratch
+  ftcg::DevBuf tile_scan_tmp;  // scan scratch of the tile binning (in flight while the host reads the check)
   ftcg::DevBuf flags;        // small device scratch: [6] audit estimate
 
   // weight binning
@@ -238,32 +254,40 @@ struct ftcg_plan_s {
 
   ftcg::Timing timing;
   double* host_flags = nullptr;  // pinned host mirror of flags (FLAGS_BYTES)
-  // pinned, coherent host memory that the input check writes its partials to
-  // (5 words per workgroup, at most CHECK_PARTS workgroups), and its device view
-  unsigned long long* host_part = nullptr;
-  unsigned long long* host_part_dev = nullptr;
+  // the input check: per-workgroup partials, the reduced result on the
+  // device, its pinned coherent host copy (written by the same kernel), and
+  // the event after it, which is all the host waits for
+  ftcg::DevBuf check_part;
+  ftcg::DevBuf geo;
+  ftcg::CheckOut* host_geo = nullptr;
+  hipEvent_t ev_check = nullptr;
 };
 
 namespace ftcg {
 
 // launchers (defined in the .hip files); all enqueue on plan->stream
 constexpr size_t FLAGS_BYTES = 128;       // device flags / pinned host mirror
-constexpr int64_t WROW_CNT_ZERO = 4100;   // bin-row counters cleared by the input check (>= 4096 + 1)
+constexpr int64_t WROW_CNT_ZERO = 4100;   // bin-row counters cleared by the input check (>= WROW_MAX + 1)
 constexpr int CHECK_PARTS = 1024;         // input-check workgroups at most
 // returns the number of partial records (5 words each) written to part
 int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long long* part, int32_t* zero_a,
                         int64_t zero_na, int32_t* zero_b, int64_t zero_nb);
+// reduces the partials into p->geo and p->host_geo (one workgroup)
+void launch_check_reduce(ftcg_plan p, const unsigned long long* part, int nparts);
 void bin_points_k(ftcg_plan p, const double* k);   // fills recs, alpha_s, tile_off
+void bin_count_k(ftcg_plan p, const double* k);    // its counting + scan (tile_off, cursors)
+void bin_scatter_k(ftcg_plan p, const double* k);  // its scatter (recs, alpha_s)
+bool tile_keys_in_lds(ftcg_plan p);                 // the tile counters fit one workgroup's LDS
 void refill_alpha(ftcg_plan p);                     // alpha_s[r] = alpha[recs[r].src]
 void refill_alpha_dev(ftcg_plan p);  // the same, record count read on the device (no host sync)
 // 2D, <= LDS_TILE_KEYS tiles: tile records and weight-bin rows from one
-// counting pass, one paired scan and one scatter pass
-bool fused_binning_ok(ftcg_plan p);
+// counting pass, one paired scan and one scatter pass (geometry read from
+// p->geo on the device)
 void bin_points_fused(ftcg_plan p, const double* k);
-void setup_weight_bins(ftcg_plan p, const double* kmin, const double* kmax);
-void sort_weight_rows(ftcg_plan p);
-void build_weight_bins(ftcg_plan p, const double* k, const double* kmin,
-                       const double* kmax);         // sorted neighbour bins (+ sin/cos)
+void wrow_bin(ftcg_plan p, const double* k, int nrows);   // 2D bin rows, geometry from p->geo
+void setup_weight_bins(ftcg_plan p);                 // buffers for the geometry p->wgeom
+void sort_weight_rows(ftcg_plan p);                  // 2D bins from the rows (+ sin/cos)
+void build_weight_bins_1d(ftcg_plan p, const double* k);   // 1D sorted neighbour bins
 void run_plain_weights(ftcg_plan p);                // alpha (caller order) from the bins
 // plain weights of the samples idx[0..n) (caller indices) into out[0..n)
 void plain_weights_at(ftcg_plan p, const double* k, const int32_t* idx, int64_t n, double* out);

@@ -503,29 +503,106 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_at(const int32_t* __
 // on SAS rasters of 2^17, 2^20 and 2^23 samples (span 3 against span 4), the
 // weight kernel took 0.053 / 0.507 / 2.23 ms against 0.058 / 0.528 / 2.21 ms.
 constexpr double BIN_TARGET = 4.5;
-static WBinGeom wbin_geom(ftcg_plan p, const double* kmin, const double* kmax) {
-  WBinGeom g{};
-  g.R = p->R;
-  double vol = 1.0;
-  for (int a = 0; a < p->dim; ++a) vol *= fmax(kmax[a] - kmin[a], 1e-9);
-  const double rho = (double)p->m / vol;
-  const double h_target = p->dim == 2 ? sqrt(BIN_TARGET / rho) : BIN_TARGET / rho;
-  // h = R / span exactly, so the 2 span + 1 bins of a row range end on the box
-  int span = (int)lround(p->R / h_target);
-  span = span < 2 ? 2 : (span > 16 ? 16 : span);
-  double h = p->R / span;
-  const int max_bins = p->dim == 1 ? (1 << 22) : 4096;
-  for (int a = 0; a < p->dim; ++a) {
-    double ext = kmax[a] - kmin[a];
-    if (ext / h + 1.0 > (double)max_bins) h = ext / (double)(max_bins - 1);
+// Second step of the input check: one workgroup reduces the partials of
+// k_check_points, rejects the points when one is non-finite or farther than
+// 2^40 from the origin on an axis, and derives the neighbour-bin geometry
+// from the bounding box. The result goes to device memory, for the binning
+// passes enqueued before the host has looked at it, and to pinned host
+// memory, from which the host launches the rest with the same values. A
+// rejected set still gets a valid one-bin geometry, so those passes stay in
+// bounds.
+constexpr double KMAX_ABS = 1099511627776.0;   // 2^40
+
+__device__ inline double decode_ordered_dev(unsigned long long o) {
+  const unsigned long long b = (o & 0x8000000000000000ull) ? (o & 0x7fffffffffffffffull) : ~o;
+  return __longlong_as_double((long long)b);
+}
+
+constexpr int CR_BLOCK = 256;
+__global__ __launch_bounds__(CR_BLOCK) void k_check_reduce(const unsigned long long* __restrict__ part, int nparts,
+                                                           int dim, int64_t m, double R,
+                                                           CheckOut* __restrict__ out_dev,
+                                                           CheckOut* __restrict__ out_host) {
+  __shared__ unsigned long long sred[5][CR_BLOCK / 64];
+  unsigned long long v[5] = {0ull, ~0ull, ~0ull, 0ull, 0ull};   // flag, lo0, lo1, hi0, hi1
+  for (int b = threadIdx.x; b < nparts; b += CR_BLOCK) {
+    const unsigned long long* q = part + 5 * b;
+    v[0] |= q[0];
+    v[1] = q[1] < v[1] ? q[1] : v[1];
+    v[2] = q[2] < v[2] ? q[2] : v[2];
+    v[3] = q[3] > v[3] ? q[3] : v[3];
+    v[4] = q[4] > v[4] ? q[4] : v[4];
   }
-  g.h = h;
-  g.span = (int)ceil(p->R / h);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long y[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) y[i] = __shfl_xor(v[i], off, 64);
+    v[0] |= y[0];
+    v[1] = y[1] < v[1] ? y[1] : v[1];
+    v[2] = y[2] < v[2] ? y[2] : v[2];
+    v[3] = y[3] > v[3] ? y[3] : v[3];
+    v[4] = y[4] > v[4] ? y[4] : v[4];
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int i = 0; i < 5; ++i) sred[i][w] = v[i];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int q = 1; q < CR_BLOCK / 64; ++q) {
+    v[0] |= sred[0][q];
+    v[1] = sred[1][q] < v[1] ? sred[1][q] : v[1];
+    v[2] = sred[2][q] < v[2] ? sred[2][q] : v[2];
+    v[3] = sred[3][q] > v[3] ? sred[3][q] : v[3];
+    v[4] = sred[4][q] > v[4] ? sred[4][q] : v[4];
+  }
+  CheckOut o;
+  bool bad = v[0] != 0;
   for (int a = 0; a < 2; ++a) {
-    g.kmin[a] = a < p->dim ? kmin[a] : 0.0;
-    g.nb[a] = a < p->dim ? (int)floor((kmax[a] - kmin[a]) / h) + 1 : 1;
+    o.kmin[a] = a < dim ? decode_ordered_dev(v[1 + a]) : 0.0;
+    o.kmax[a] = a < dim ? decode_ordered_dev(v[3 + a]) : 0.0;
+    bad = bad || !(o.kmin[a] >= -KMAX_ABS && o.kmax[a] <= KMAX_ABS);
   }
-  return g;
+  WBinGeom g;
+  g.R = R;
+  if (bad) {
+    g.kmin[0] = g.kmin[1] = 0.0;
+    g.h = 1.0;
+    g.nb[0] = g.nb[1] = 1;
+    g.span = 1;
+  } else {
+    // bins of about BIN_TARGET samples at the mean density of the box, with
+    // h = R / span exactly, so the 2 span + 1 bins of a row range end on the
+    // box of radius R; at most max_bins bins per axis
+    double vol = 1.0;
+    for (int a = 0; a < dim; ++a) vol *= fmax(o.kmax[a] - o.kmin[a], 1e-9);
+    const double rho = (double)m / vol;
+    const double h_target = dim == 2 ? sqrt(BIN_TARGET / rho) : BIN_TARGET / rho;
+    const double sp = fmin(fmax(floor(R / h_target + 0.5), 2.0), 16.0);
+    double h = R / sp;
+    const double max_bins = dim == 1 ? (double)(1 << 22) : (double)WROW_MAX;
+    for (int a = 0; a < dim; ++a) {
+      const double ext = o.kmax[a] - o.kmin[a];
+      if (ext / h + 1.0 > max_bins) h = ext / (max_bins - 1.0);
+    }
+    g.h = h;
+    g.span = (int)ceil(R / h);
+    for (int a = 0; a < 2; ++a) {
+      g.kmin[a] = a < dim ? o.kmin[a] : 0.0;
+      g.nb[a] = a < dim ? (int)fmin(fmax(floor((o.kmax[a] - o.kmin[a]) / h) + 1.0, 1.0), max_bins) : 1;
+    }
+  }
+  o.g = g;
+  o.bad = bad ? 1 : 0;
+  o.pad = 0;
+  *out_dev = o;
+  *out_host = o;
+}
+
+void launch_check_reduce(ftcg_plan p, const unsigned long long* part, int nparts) {
+  hipLaunchKernelGGL(k_check_reduce, dim3(1), dim3(CR_BLOCK), 0, p->stream, part, nparts, p->dim, p->m, p->R,
+                     p->geo.as<CheckOut>(), p->host_geo);
+  FTCG_HIP(hipGetLastError());
 }
 
 // 2D neighbour binning in two levels, so no pass spreads atomics over all
@@ -548,9 +625,11 @@ constexpr int WROW_IPT = 4;
 constexpr int WROW_LMAX = 16384;   // rows up to this many samples are ordered in LDS
 
 
-__global__ __launch_bounds__(WB_BLOCK) void k_wrow_count(const double* __restrict__ k, int64_t m, WBinGeom g,
+__global__ __launch_bounds__(WB_BLOCK) void k_wrow_count(const double* __restrict__ k, int64_t m,
+                                                         const WBinGeom* __restrict__ gp,
                                                          int32_t* __restrict__ row_cnt) {
-  __shared__ int32_t hist[4096];
+  const WBinGeom g = *gp;
+  __shared__ int32_t hist[WROW_MAX];
   const int nrow = g.nb[0];
   for (int i = threadIdx.x; i < nrow; i += WB_BLOCK) hist[i] = 0;
   __syncthreads();
@@ -571,10 +650,12 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_count(const double* __restric
   }
 }
 
-__global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(const double* __restrict__ k, int64_t m, WBinGeom g,
+__global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(const double* __restrict__ k, int64_t m,
+                                                           const WBinGeom* __restrict__ gp,
                                                            int32_t* __restrict__ row_cursor,
                                                            RowRec* __restrict__ rowbuf) {
-  __shared__ int32_t base[4096 + 64];   // row counters, then one spare word per lane
+  const WBinGeom g = *gp;
+  __shared__ int32_t base[WROW_MAX + 64];   // row counters, then one spare word per lane
   const int nrow = g.nb[0];
   for (int i = threadIdx.x; i < nrow; i += WB_BLOCK) base[i] = 0;
   __syncthreads();
@@ -600,7 +681,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(const double* __restr
   // word), so all claims are in flight before the first is used
   int pos[WROW_IPT];
 #pragma unroll
-  for (int u = 0; u < WROW_IPT; ++u) pos[u] = atomicAdd(&base[row[u] >= 0 ? row[u] : 4096 + (int)__lane_id()], 1);
+  for (int u = 0; u < WROW_IPT; ++u) pos[u] = atomicAdd(&base[row[u] >= 0 ? row[u] : WROW_MAX + (int)__lane_id()], 1);
 #pragma unroll
   for (int u = 0; u < WROW_IPT; ++u) {
     const int64_t j = j0 + (int64_t)u * WB_BLOCK + threadIdx.x;
@@ -727,9 +808,9 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_
   }
 }
 
-void setup_weight_bins(ftcg_plan p, const double* kmin, const double* kmax) {
-  const WBinGeom g = wbin_geom(p, kmin, kmax);
-  p->wgeom = g;
+// buffers of the neighbour binning for the geometry in p->wgeom
+void setup_weight_bins(ftcg_plan p) {
+  const WBinGeom& g = p->wgeom;
   const int64_t m = p->m;
   const int64_t nbins = (int64_t)g.nb[0] * g.nb[1];
   p->wb_off.ensure(sizeof(int32_t) * (nbins + 1));
@@ -737,10 +818,23 @@ void setup_weight_bins(ftcg_plan p, const double* kmin, const double* kmax) {
   p->ws_k.ensure(sizeof(double) * m * p->dim * 3);
   p->ws_idx.ensure(sizeof(int32_t) * m);
   p->ws_inv.ensure(sizeof(int32_t) * m);
-  if (p->dim == 2) {
-    p->wb_rowoff.ensure(sizeof(int32_t) * (g.nb[0] + 1));
-    p->wb_rowbuf.ensure(sizeof(RowRec) * m);
-  }
+}
+
+// steps 1-3 of the 2D binning, with the geometry the input check left in
+// device memory: rows are counted, the first nrows row counters scanned
+// (WROW_MAX when the host has not read the geometry yet: rows past the
+// geometry's count stay empty) and the samples placed in their row's range
+void wrow_bin(ftcg_plan p, const double* k, int nrows) {
+  const int64_t m = p->m;
+  hipStream_t s = p->stream;
+  const WBinGeom* gd = &p->geo.as<CheckOut>()->g;
+  int32_t* row_cnt = p->wb_cnt.as<int32_t>();   // zeroed by the input check
+  int32_t* row_off = p->wb_rowoff.as<int32_t>();
+  const unsigned nb = (unsigned)((m + WROW_IPT * WB_BLOCK - 1) / (WROW_IPT * WB_BLOCK));
+  hipLaunchKernelGGL(k_wrow_count, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, gd, row_cnt);
+  exclusive_scan_i32(row_cnt, row_off, nrows, p->scan_tmp.as<int32_t>(), s, row_cnt);
+  hipLaunchKernelGGL(k_wrow_scatter, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, gd, row_cnt, p->wb_rowbuf.as<RowRec>());
+  FTCG_HIP(hipGetLastError());
 }
 
 // step 4 of the 2D binning (rows placed by steps 1-3, here or fused with the
@@ -760,38 +854,25 @@ void sort_weight_rows(ftcg_plan p) {
   p->ws_sum_fresh = true;
 }
 
-void build_weight_bins(ftcg_plan p, const double* k, const double* kmin, const double* kmax) {
-  setup_weight_bins(p, kmin, kmax);
+// 1D neighbour binning (after the host has read the geometry)
+void build_weight_bins_1d(ftcg_plan p, const double* k) {
+  setup_weight_bins(p);
   const WBinGeom g = p->wgeom;
   const int64_t m = p->m;
-  const int dim = p->dim;
   const int64_t nbins = (int64_t)g.nb[0] * g.nb[1];
   hipStream_t s = p->stream;
   int32_t* off = p->wb_off.as<int32_t>();
   timing_begin(p, STEP_WBIN);
-  if (dim == 2) {
-    // row counters: zeroed by the input check (WROW_CNT_ZERO entries)
-    int32_t* row_cnt = p->wb_cnt.as<int32_t>();
-    p->scan_tmp.ensure(scan_tmp_bytes(g.nb[0]));
-    int32_t* row_off = p->wb_rowoff.as<int32_t>();
-    const unsigned nb = (unsigned)((m + WROW_IPT * WB_BLOCK - 1) / (WROW_IPT * WB_BLOCK));
-    hipLaunchKernelGGL(k_wrow_count, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, row_cnt);
-    exclusive_scan_i32(row_cnt, row_off, g.nb[0], p->scan_tmp.as<int32_t>(), s, row_cnt);
-    hipLaunchKernelGGL(k_wrow_scatter, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, row_cnt,
-                       p->wb_rowbuf.as<RowRec>());
-    sort_weight_rows(p);
-  } else {
-    const size_t cnt_bytes = sizeof(int32_t) * ((nbins + 4) & ~int64_t(3));  // 16-byte multiple: one fill
-    p->wb_cnt.ensure(cnt_bytes);
-    p->scan_tmp.ensure(scan_tmp_bytes(nbins));
-    int32_t* cnt = p->wb_cnt.as<int32_t>();
-    const unsigned nb = (unsigned)((m + WB_BLOCK - 1) / WB_BLOCK);
-    FTCG_HIP(hipMemsetAsync(cnt, 0, cnt_bytes, s));
-    hipLaunchKernelGGL(k_wbin_count<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, cnt, p->wb_of.as<int32_t>());
-    exclusive_scan_i32(cnt, off, nbins, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
-    hipLaunchKernelGGL(k_wbin_scatter<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
-                       p->ws_k.as<WSample<1>>(), p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>());
-  }
+  const size_t cnt_bytes = sizeof(int32_t) * ((nbins + 4) & ~int64_t(3));  // 16-byte multiple: one fill
+  p->wb_cnt.ensure(cnt_bytes);
+  p->scan_tmp.ensure(scan_tmp_bytes(nbins));
+  int32_t* cnt = p->wb_cnt.as<int32_t>();
+  const unsigned nb = (unsigned)((m + WB_BLOCK - 1) / WB_BLOCK);
+  FTCG_HIP(hipMemsetAsync(cnt, 0, cnt_bytes, s));
+  hipLaunchKernelGGL(k_wbin_count<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, g, cnt, p->wb_of.as<int32_t>());
+  exclusive_scan_i32(cnt, off, nbins, p->scan_tmp.as<int32_t>(), s, cnt);  // cnt becomes the cursor
+  hipLaunchKernelGGL(k_wbin_scatter<1>, dim3(nb), dim3(WB_BLOCK), 0, s, k, m, p->wb_of.as<int32_t>(), cnt,
+                     p->ws_k.as<WSample<1>>(), p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>());
   FTCG_HIP(hipGetLastError());
   timing_end(p, STEP_WBIN);
   p->have_wbins = true;
