@@ -328,6 +328,37 @@ def test_nonfinite_points_rejected():
         assert st == L.FTCG_ESTATE
 
 
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf, 2.0 ** 41, -1e300])
+@pytest.mark.parametrize("n,dim,weights", [(32, 2, "plain"), (4096, 2, "plain"), (64, 1, "plain"),
+                                           (32, 2, "none")])
+def test_rejected_points_then_recovery(bad, n, dim, weights):
+    # the binning passes enqueued before the host reads the check run on the
+    # rejected points too (fused tile/bin-row binning on the small 2D grid,
+    # tile counting on the 65 536-tile grid, the whole tile binning in 1D and
+    # without weights); the call reports FTCG_EINVAL, and the plan then takes
+    # valid points and matches the oracle
+    from paper_1706_08575_amd import _lib as L
+    from paper_1706_08575_amd.ftcg import Plan
+    rng = np.random.default_rng(5)
+    m = 600
+    k = rng.uniform(-12.0, 12.0, size=(m, dim))
+    kb = k.copy()
+    kb[17, dim - 1] = bad
+    f = S.random_values(6, m)
+    with Plan(n, dim=dim, dtype="f64", weights=weights) as P:
+        with pytest.raises(L.FtcgError) as e:
+            P.set_points(dev(kb))
+        assert e.value.status == L.FTCG_EINVAL
+        P.set_points(dev(k))
+        a = host(P.get_weights())
+        if n <= 64:
+            img = host(P.execute(dev(f, torch.complex128)))
+    a_ref = O.frame_weights(k, 8.0) if weights == "plain" else np.ones(m)
+    assert np.max(np.abs(a - a_ref) / a_ref) < 1e-10
+    if n <= 64:
+        assert O.rel_l2(img, O.ftcg_image(k, f, a_ref, n)) < TOL_F64
+
+
 def test_repeat_is_stable():
     # two executes of one plan agree to float32 rounding (LDS accumulation
     # order may differ between runs)
