@@ -391,8 +391,11 @@ def main():
     # plan's second stream overlap the others)
     stage_ms = {s: ms / args.steps for s, (ms, c) in stages.items()}
     # roofline of the dominant kernel (among the steps with a work model)
+    # stages of one dominant kernel each (the binning stages run several
+    # short kernels: input check and its reduction, count, scan, scatter)
     modelled = [s_ for s_ in stage_ms if s_ == "weights" or
-                step_bytes(s_, m, info["n_records"], n, G, dim, dtype) is not None]
+                (s_ not in ("bin", "weight_bin") and
+                 step_bytes(s_, m, info["n_records"], n, G, dim, dtype) is not None)]
     dom = max(modelled, key=stage_ms.get)
     roof = None
     if dom == "weights":
