@@ -239,7 +239,8 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     }
     auto* part = p->check_part.as<unsigned long long>();
     const int nparts = launch_check_points(p, k_dev, m, part, zero_ptr, zero_n, zero_b, zero_nb);
-    launch_check_reduce(p, part, nparts);
+    const int seq = ++p->check_seq;
+    launch_check_reduce(p, part, nparts, seq);
     timing_end(p, STEP_BIN);
     FTCG_HIP(hipEventRecord(p->ev_check, p->stream));
     // 2) binning passes that need no host decision are enqueued before the
@@ -281,6 +282,7 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     }
     FTCG_HIP(hipEventSynchronize(p->ev_check));
     const CheckOut chk = *p->host_geo;
+    if (chk.seq != seq) throw StatusError{FTCG_EHIP};   // the result of an earlier call: not visible yet
     if (chk.bad) throw StatusError{FTCG_EINVAL};
     p->wgeom = chk.g;
     // 3) weights (caller order)

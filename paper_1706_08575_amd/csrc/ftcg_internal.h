@@ -95,7 +95,7 @@ struct CheckOut {
   WBinGeom g;
   double kmin[2], kmax[2];
   int bad;   // a coordinate is non-finite or beyond 2^40 in magnitude
-  int pad;
+  int seq;   // number of the set_points call it answers (checked by the host)
 };
 
 // a sample in bin order: coordinates, then sin(pi k_a), cos(pi k_a) per axis
@@ -261,6 +261,7 @@ struct ftcg_plan_s {
   ftcg::DevBuf geo;
   ftcg::CheckOut* host_geo = nullptr;
   hipEvent_t ev_check = nullptr;
+  int check_seq = 0;
 };
 
 namespace ftcg {
@@ -273,7 +274,7 @@ constexpr int CHECK_PARTS = 1024;         // input-check workgroups at most
 int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long long* part, int32_t* zero_a,
                         int64_t zero_na, int32_t* zero_b, int64_t zero_nb);
 // reduces the partials into p->geo and p->host_geo (one workgroup)
-void launch_check_reduce(ftcg_plan p, const unsigned long long* part, int nparts);
+void launch_check_reduce(ftcg_plan p, const unsigned long long* part, int nparts, int seq);
 void bin_points_k(ftcg_plan p, const double* k);   // fills recs, alpha_s, tile_off
 void bin_count_k(ftcg_plan p, const double* k);    // its counting + scan (tile_off, cursors)
 void bin_scatter_k(ftcg_plan p, const double* k);  // its scatter (recs, alpha_s)

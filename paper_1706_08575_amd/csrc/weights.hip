@@ -520,7 +520,7 @@ __device__ inline double decode_ordered_dev(unsigned long long o) {
 
 constexpr int CR_BLOCK = 256;
 __global__ __launch_bounds__(CR_BLOCK) void k_check_reduce(const unsigned long long* __restrict__ part, int nparts,
-                                                           int dim, int64_t m, double R,
+                                                           int dim, int64_t m, double R, int seq,
                                                            CheckOut* __restrict__ out_dev,
                                                            CheckOut* __restrict__ out_host) {
   __shared__ unsigned long long sred[5][CR_BLOCK / 64];
@@ -594,13 +594,13 @@ __global__ __launch_bounds__(CR_BLOCK) void k_check_reduce(const unsigned long l
   }
   o.g = g;
   o.bad = bad ? 1 : 0;
-  o.pad = 0;
+  o.seq = seq;
   *out_dev = o;
   *out_host = o;
 }
 
-void launch_check_reduce(ftcg_plan p, const unsigned long long* part, int nparts) {
-  hipLaunchKernelGGL(k_check_reduce, dim3(1), dim3(CR_BLOCK), 0, p->stream, part, nparts, p->dim, p->m, p->R,
+void launch_check_reduce(ftcg_plan p, const unsigned long long* part, int nparts, int seq) {
+  hipLaunchKernelGGL(k_check_reduce, dim3(1), dim3(CR_BLOCK), 0, p->stream, part, nparts, p->dim, p->m, p->R, seq,
                      p->geo.as<CheckOut>(), p->host_geo);
   FTCG_HIP(hipGetLastError());
 }
