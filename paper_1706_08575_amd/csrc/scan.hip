@@ -113,8 +113,11 @@ __device__ inline int32_t wave_inclusive_scan(int32_t v) {
 // entries; entry e sits at LDS word e + e / 16 (conflict-free at stride 16)
 __device__ inline int ss_pad(int e) { return e + (e >> 4); }
 
+// ITEMS entries per thread and chunk (ITEMS, or fewer for short arrays,
+// which then pass through less LDS)
+template <int ITEMS>
 __device__ void scan_single_block(const int32_t* in, int64_t n, int32_t* __restrict__ out, int32_t* cursor) {
-  constexpr int CH = SS_BLOCK * SS_ITEMS;
+  constexpr int CH = SS_BLOCK * ITEMS;
   __shared__ int32_t buf[CH + CH / 16];
   __shared__ int32_t wsum[SS_BLOCK / 64];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -122,16 +125,16 @@ __device__ void scan_single_block(const int32_t* in, int64_t n, int32_t* __restr
   for (int64_t c0 = 0; c0 < n; c0 += CH) {
     const int64_t len = n - c0 < CH ? n - c0 : CH;
 #pragma unroll
-    for (int i = 0; i < SS_ITEMS; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
       const int e = i * SS_BLOCK + t;
       buf[ss_pad(e)] = e < len ? in[c0 + e] : 0;
     }
     __syncthreads();
-    int32_t v[SS_ITEMS];
+    int32_t v[ITEMS];
     int32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < SS_ITEMS; ++i) {
-      v[i] = buf[ss_pad(t * SS_ITEMS + i)];
+    for (int i = 0; i < ITEMS; ++i) {
+      v[i] = buf[ss_pad(t * ITEMS + i)];
       s += v[i];
     }
     const int32_t incl = wave_inclusive_scan(s);
@@ -146,14 +149,14 @@ __device__ void scan_single_block(const int32_t* in, int64_t n, int32_t* __restr
     }
     int32_t run = carry + wpre + incl - s;
 #pragma unroll
-    for (int i = 0; i < SS_ITEMS; ++i) {
-      buf[ss_pad(t * SS_ITEMS + i)] = run;
+    for (int i = 0; i < ITEMS; ++i) {
+      buf[ss_pad(t * ITEMS + i)] = run;
       run += v[i];
     }
     carry += tot;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < SS_ITEMS; ++i) {
+    for (int i = 0; i < ITEMS; ++i) {
       const int e = i * SS_BLOCK + t;
       if (e < len) {
         const int32_t x = buf[ss_pad(e)];
@@ -166,26 +169,35 @@ __device__ void scan_single_block(const int32_t* in, int64_t n, int32_t* __restr
   if (t == 0) out[n] = carry;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(SS_BLOCK) void k_scan_single(const int32_t* in, int64_t n, int32_t* __restrict__ out,
                                                           int32_t* cursor) {
-  scan_single_block(in, n, out, cursor);
+  scan_single_block<ITEMS>(in, n, out, cursor);
 }
 
 // two independent single-workgroup scans in one launch (workgroup b scans
 // array b)
+template <int ITEMS>
 __global__ __launch_bounds__(SS_BLOCK) void k_scan_pair(const int32_t* in0, int64_t n0, int32_t* __restrict__ out0,
                                                         int32_t* cursor0, const int32_t* in1, int64_t n1,
                                                         int32_t* __restrict__ out1, int32_t* cursor1) {
   if (blockIdx.x == 0)
-    scan_single_block(in0, n0, out0, cursor0);
+    scan_single_block<ITEMS>(in0, n0, out0, cursor0);
   else
-    scan_single_block(in1, n1, out1, cursor1);
+    scan_single_block<ITEMS>(in1, n1, out1, cursor1);
 }
 
 void exclusive_scan_pair_i32(const int32_t* in0, int32_t* out0, int64_t n0, int32_t* cursor0, const int32_t* in1,
                              int32_t* out1, int64_t n1, int32_t* cursor1, hipStream_t s) {
   if (n0 > SCAN_SINGLE_MAX || n1 > SCAN_SINGLE_MAX) throw StatusError{FTCG_EUNSUPPORTED};
-  hipLaunchKernelGGL(k_scan_pair, dim3(2), dim3(SS_BLOCK), 0, s, in0, n0, out0, cursor0, in1, n1, out1, cursor1);
+  // arrays of at most 4 entries per thread (the 512^2 raster's tiles and
+  // bin rows) take one pass through 16 KiB of LDS instead of 64 KiB
+  if (n0 <= 4 * SS_BLOCK && n1 <= 4 * SS_BLOCK)
+    hipLaunchKernelGGL(k_scan_pair<4>, dim3(2), dim3(SS_BLOCK), 0, s, in0, n0, out0, cursor0, in1, n1, out1,
+                       cursor1);
+  else
+    hipLaunchKernelGGL(k_scan_pair<SS_ITEMS>, dim3(2), dim3(SS_BLOCK), 0, s, in0, n0, out0, cursor0, in1, n1, out1,
+                       cursor1);
   FTCG_HIP(hipGetLastError());
 }
 
@@ -195,8 +207,13 @@ size_t scan_tmp_bytes(int64_t n) {
 }
 
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s, int32_t* cursor) {
+  if (n <= 4 * SS_BLOCK) {   // one pass through 16 KiB of LDS
+    hipLaunchKernelGGL(k_scan_single<4>, dim3(1), dim3(SS_BLOCK), 0, s, in, n, out, cursor);
+    FTCG_HIP(hipGetLastError());
+    return;
+  }
   if (n <= SCAN_SINGLE_MAX) {
-    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SS_BLOCK), 0, s, in, n, out, cursor);
+    hipLaunchKernelGGL(k_scan_single<SS_ITEMS>, dim3(1), dim3(SS_BLOCK), 0, s, in, n, out, cursor);
     FTCG_HIP(hipGetLastError());
     return;
   }
