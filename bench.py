@@ -410,9 +410,10 @@ def main():
         roof = {"kernel": kname, "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": tr["bytes"] if tr else None,
                 "work_per_launch": f"{pairs} ordered in-box pairs x {FLOPS_PER_PAIR[dim]} FP64 flops"
-                                   + (" (2D kernel forms each unordered pair once; stage = it + the"
-                                      " finish: bin order to caller order, and on grids of at most 4096"
-                                      " tiles the records' weights)" if dim == 2 else ""),
+                                   + (" (2D kernel forms each unordered pair once; stage = it, plus on"
+                                      " grids of more than 4096 tiles its bin-order to caller-order finish;"
+                                      " on the others the spread forms the weights from the sums)"
+                                      if dim == 2 else ""),
                 "algorithmic_bytes_per_launch": m * (48 + 4 + 8)}
     else:
         b = step_bytes(dom, m, info["n_records"], n, G, dim, dtype)

@@ -216,6 +216,7 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     p->have_points = false;
     p->have_weights = false;
     p->finish_recs = false;
+    p->weights_deferred = false;
     p->m = m;
     // 1) input check: finiteness, bounding box and the neighbour-bin
     //    geometry, reduced on the device; the check also zeroes the tile and
@@ -344,6 +345,7 @@ ftcg_status ftcg_get_weights(ftcg_plan p, double* alpha_dev, int* used_fallback_
   if (!p || !alpha_dev) return FTCG_EINVAL;
   if (!p->have_points || !p->have_weights) return FTCG_ESTATE;
   return guarded([&] {
+    finish_deferred_weights(p);
     FTCG_HIP(hipMemcpyAsync(alpha_dev, p->alpha.p, sizeof(double) * p->m, hipMemcpyDeviceToDevice, p->stream));
     if (used_fallback_host) {
       FTCG_HIP(hipStreamSynchronize(p->stream));

@@ -272,6 +272,7 @@ ftcg_status ftcg_batch_set_points(ftcg_batch_s* b, const int64_t* m_host, const 
       ftcg_plan p = b->plans[i];
       ftcg_status s = ftcg_set_points(p, m_host[i], k_dev + 2 * off);
       if (s != FTCG_OK) throw StatusError{s};
+      finish_deferred_weights(p);   // the batched spread reads the records' weights
       b->m[i] = m_host[i];
       BatchItem& it = b->items[i];
       it.recs = p->recs.as<Rec<float>>();

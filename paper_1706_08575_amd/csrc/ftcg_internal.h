@@ -89,6 +89,11 @@ struct WBinGeom {
 // bin rows (2D) at most: the row counters and the row scan have this size
 constexpr int WROW_MAX = 4096;
 
+// pi, and the self term pi^DIM of the frame-weight sums (alpha = pi^DIM / sum)
+constexpr double WPI = 3.141592653589793238462643383279502884;
+template <int DIM>
+constexpr double wscale() { return DIM == 1 ? WPI * WPI : WPI * WPI * WPI * WPI; }
+
 // the input check reduced on the device: bounding box, the neighbour-bin
 // geometry derived from it, and whether the points are rejected
 struct CheckOut {
@@ -234,6 +239,11 @@ struct ftcg_plan_s {
   // set by the fused binning: the finish of the symmetric weight sum also
   // writes the record-order weights (through ws_inv) and then clears it
   bool finish_recs = false;
+  // the symmetric sum's finish is pending (fused-binning grids): the
+  // fixed-point spread forms each record's weight from ws_sum itself, and
+  // finish_deferred_weights writes alpha and the records' weights when
+  // anything else needs them
+  bool weights_deferred = false;
   ftcg::WBinGeom wgeom{};
   bool have_wbins = false;
   bool weights_only = false;  // internal plans that only compute weights (no tile binning)
@@ -290,6 +300,7 @@ void setup_weight_bins(ftcg_plan p);                 // buffers for the geometry
 void sort_weight_rows(ftcg_plan p);                  // 2D bins from the rows (+ sin/cos)
 void build_weight_bins_1d(ftcg_plan p, const double* k);   // 1D sorted neighbour bins
 void run_plain_weights(ftcg_plan p);                // alpha (caller order) from the bins
+void finish_deferred_weights(ftcg_plan p);          // no-op unless p->weights_deferred
 // plain weights of the samples idx[0..n) (caller indices) into out[0..n)
 void plain_weights_at(ftcg_plan p, const double* k, const int32_t* idx, int64_t n, double* out);
 void fill_ones(double* a, int64_t m, hipStream_t s);

@@ -165,13 +165,24 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d(const Rec<real>* __re
 // samples: 0.73 -> 0.59 ms; on small grids the LDS atomics bound the loop).
 constexpr int FX_STAGE = 256;   // 6 KiB: keeps 7 workgroups of tile 32, W = 6 per CU
 
-template <int W, int T>
+// SUMS: the records carry no weights yet; record r of sample j takes
+// alpha_j = pi^2 pi^2 / wsum[inv[j]] (bin-order sums of the symmetric weight
+// kernel, the same float64 division its finish does), rounded to float32
+template <int W, int T, bool SUMS>
 __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* __restrict__ recs,
                                                               const float* __restrict__ alpha_s,
+                                                              const double* __restrict__ wsum,
+                                                              const int32_t* __restrict__ inv,
                                                               const int32_t* __restrict__ tile_off,
                                                               const float2* __restrict__ fhat,
                                                               float2* __restrict__ grid, int64_t G, int nt,
                                                               float beta) {
+  auto weight = [&](int r, int src) -> float {
+    if constexpr (SUMS)
+      return (float)(wscale<2>() / wsum[inv[src]]);
+    else
+      return alpha_s[r];
+  };
   constexpr int L = 2 * W;              // lanes per record / taps per axis
   constexpr int PAD = 2 * W - 1;        // halo rows each side
   constexpr int TP = T + 1;             // row pitch (64-bit words)
@@ -204,7 +215,7 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
   float mx = 0.f;
   for (int r = beg + tid; r < end; r += SPREAD_BLOCK) {
     const Rec<float> rec = recs[r];
-    const float a = alpha_s[r];
+    const float a = weight(r, rec.src);
     const float2 v = fhat[rec.src];
     if (r - beg < first) {
       sgeo[r - beg] = make_float4(rec.f0, rec.f1, __int_as_float(rec.c01), a);
@@ -237,8 +248,9 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
       a = sgeo[r - beg].w;
       v = sval[r - beg];
     } else {
-      a = alpha_s[r];
-      v = fhat[recs[r].src];
+      const int src = recs[r].src;
+      a = weight(r, src);
+      v = fhat[src];
     }
     qsum += (long long)ceilf(fmaxf(fabsf(v.x * a), fabsf(v.y * a)) * qs) + 1;
   }
@@ -287,7 +299,7 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
         __syncthreads();
         for (int r = tid; r < cn; r += SPREAD_BLOCK) {
           const Rec<float> rec = recs[cb + r];
-          sgeo[r] = make_float4(rec.f0, rec.f1, __int_as_float(rec.c01), alpha_s[cb + r]);
+          sgeo[r] = make_float4(rec.f0, rec.f1, __int_as_float(rec.c01), weight(cb + r, rec.src));
           sval[r] = fhat[rec.src];
         }
         __syncthreads();
@@ -305,20 +317,20 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
       const int r = base + s;
       if (s < RPW && r < end) {
         const Rec<float> rec = recs[r];
-        splat(rec.f0, rec.f1, rec.c01, alpha_s[r], fhat[rec.src]);
+        splat(rec.f0, rec.f1, rec.c01, weight(r, rec.src), fhat[rec.src]);
       }
     }
   }
   __syncthreads();
-  const float inv = bound / (2147483648.f - 16777216.f);
+  const float unscale = bound / (2147483648.f - 16777216.f);
   for (int idx = tid; idx < T * T; idx += SPREAD_BLOCK) {
     const int row = idx / T, col = idx - (idx / T) * T;
     const unsigned long long vv = acc[(row + PAD) * TP + col];
     const int re = (int)(unsigned)(vv & 0xffffffffull);
     const int im = (int)((long long)(vv - (unsigned long long)(long long)re) >> 32);
     float2 o;
-    o.x = (float)re * inv;
-    o.y = (float)im * inv;
+    o.x = (float)re * unscale;
+    o.y = (float)im * unscale;
     out[(int64_t)row * G + col] = o;
   }
 }
@@ -533,9 +545,16 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread1d(const Rec<real>* __re
 
 template <int W, int T>
 static void launch_fx(ftcg_plan p, const void* fhat, void* grid) {
-  hipLaunchKernelGGL((k_spread2d_fx<W, T>), dim3((unsigned)p->ntiles), dim3(SPREAD_BLOCK), 0, p->stream,
-                     p->recs.as<Rec<float>>(), p->alpha_s.as<float>(), p->tile_off.as<int32_t>(),
-                     static_cast<const float2*>(fhat), static_cast<float2*>(grid), p->G, (int)p->nt, (float)p->beta);
+  if (p->weights_deferred)
+    hipLaunchKernelGGL((k_spread2d_fx<W, T, true>), dim3((unsigned)p->ntiles), dim3(SPREAD_BLOCK), 0, p->stream,
+                       p->recs.as<Rec<float>>(), p->alpha_s.as<float>(), p->ws_sum.as<double>(),
+                       p->ws_inv.as<int32_t>(), p->tile_off.as<int32_t>(), static_cast<const float2*>(fhat),
+                       static_cast<float2*>(grid), p->G, (int)p->nt, (float)p->beta);
+  else
+    hipLaunchKernelGGL((k_spread2d_fx<W, T, false>), dim3((unsigned)p->ntiles), dim3(SPREAD_BLOCK), 0, p->stream,
+                       p->recs.as<Rec<float>>(), p->alpha_s.as<float>(), nullptr, nullptr,
+                       p->tile_off.as<int32_t>(), static_cast<const float2*>(fhat), static_cast<float2*>(grid),
+                       p->G, (int)p->nt, (float)p->beta);
 }
 
 template <int W>
@@ -555,9 +574,10 @@ static void launch_spread_w(ftcg_plan p, const void* fhat, void* grid) {
   using cx = typename Cx<real>::t;
   const int T = p->tile;
   if (std::is_same<real, float>::value && p->dim == 2 && p->accum == ACCUM_FIXED) {
-    launch_fx_t<W>(p, fhat, grid);
+    launch_fx_t<W>(p, fhat, grid);   // forms deferred weights itself
     return;
   }
+  finish_deferred_weights(p);          // the other kernels read the records' weights
   if (std::is_same<real, float>::value && p->dim == 2 && p->accum == ACCUM_MFMA) {
     if (T != 64) throw StatusError{FTCG_EUNSUPPORTED};
     hipLaunchKernelGGL((k_spread2d_mfma<W>), dim3((unsigned)p->ntiles), dim3(SPREAD_BLOCK), 0, p->stream,

@@ -81,10 +81,7 @@ __device__ inline double rcp64(double x) {
 // (pi eps)^2 stay normal numbers. This keeps the loop body to plain float64
 // arithmetic.
 constexpr double WEPS = 0x1p-500;
-constexpr double WPI = 3.141592653589793238462643383279502884;
 constexpr double WPI_EPS = WPI * WEPS;
-template <int DIM>
-constexpr double wscale() { return DIM == 1 ? WPI * WPI : WPI * WPI * WPI * WPI; }
 
 // pi^DIM T_in by the select-free form, or a value whose square is 0 when
 // ||k_i - k_n||_inf > R
@@ -911,17 +908,8 @@ static void launch_weights_sym(ftcg_plan p) {
   const int chunk = cx * std::max(1, g.nb[0] / 64);
   hipLaunchKernelGGL((k_frame_weights_sym<WT, S>), dim3((unsigned)nb), dim3(WB_BLOCK), 0, p->stream,
                      p->ws_k.as<WSample<2>>(), p->wb_off.as<int32_t>(), g, cx, chunk, wsum);
-  if (p->finish_recs) {
-    const unsigned fb = (unsigned)std::min<int64_t>(2048, (2 * m + WB_BLOCK - 1) / WB_BLOCK);
-    const int32_t* nrec = p->tile_off.as<int32_t>() + p->ntiles;
-    if (p->dtype == FTCG_F64)
-      hipLaunchKernelGGL(k_weights_from_sums_recs<double>, dim3(fb), dim3(WB_BLOCK), 0, p->stream, wsum,
-                         p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>(), m, p->alpha.as<double>(),
-                         p->recs.as<Rec<double>>(), nrec, p->alpha_s.as<double>());
-    else
-      hipLaunchKernelGGL(k_weights_from_sums_recs<float>, dim3(fb), dim3(WB_BLOCK), 0, p->stream, wsum,
-                         p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>(), m, p->alpha.as<double>(),
-                         p->recs.as<Rec<float>>(), nrec, p->alpha_s.as<float>());
+  if (p->finish_recs) {   // finished on demand (finish_deferred_weights) or inside the spread
+    p->weights_deferred = true;
     p->finish_recs = false;
     return;
   }
@@ -944,6 +932,24 @@ static void launch_weights_1d(ftcg_plan p) {
   const unsigned nb = (unsigned)((groups + WB_BLOCK - 1) / WB_BLOCK);
   hipLaunchKernelGGL((k_frame_weights_1d<WT>), dim3(nb), dim3(WB_BLOCK), 0, p->stream, p->ws_k.as<WSample<1>>(),
                      p->ws_idx.as<int32_t>(), p->wb_off.as<int32_t>(), p->m, p->wgeom, p->alpha.as<double>());
+}
+
+void finish_deferred_weights(ftcg_plan p) {
+  if (!p->weights_deferred) return;
+  const int64_t m = p->m;
+  const double* wsum = p->ws_sum.as<double>();
+  const unsigned fb = (unsigned)std::min<int64_t>(2048, (2 * m + WB_BLOCK - 1) / WB_BLOCK);
+  const int32_t* nrec = p->tile_off.as<int32_t>() + p->ntiles;
+  if (p->dtype == FTCG_F64)
+    hipLaunchKernelGGL(k_weights_from_sums_recs<double>, dim3(fb), dim3(WB_BLOCK), 0, p->stream, wsum,
+                       p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>(), m, p->alpha.as<double>(),
+                       p->recs.as<Rec<double>>(), nrec, p->alpha_s.as<double>());
+  else
+    hipLaunchKernelGGL(k_weights_from_sums_recs<float>, dim3(fb), dim3(WB_BLOCK), 0, p->stream, wsum,
+                       p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>(), m, p->alpha.as<double>(),
+                       p->recs.as<Rec<float>>(), nrec, p->alpha_s.as<float>());
+  FTCG_HIP(hipGetLastError());
+  p->weights_deferred = false;
 }
 
 // samples per lane: the plan's tuning, else in 2D 2 from 2^20 samples (each
