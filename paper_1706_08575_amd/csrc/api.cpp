@@ -289,8 +289,10 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     // 3) weights (caller order)
     p->alpha.ensure(sizeof(double) * m);
     const bool computed = p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED;
-    // records already written: in 2D the finish of the plain weight sum
-    // weights them (through the caller-to-bin map the bin sort then writes)
+    // records already written, 2D plain weights: the symmetric sum's finish
+    // is deferred (the fixed-point spread forms the records' weights from the
+    // sums through the caller-to-bin map the bin sort then writes;
+    // finish_deferred_weights serves every other reader)
     const bool want_finish = early_scatter && p->dim == 2 && p->wmode == FTCG_W_PLAIN;
     if (computed) {
       if (p->wmode == FTCG_W_LEARNED && !p->mlp) throw StatusError{FTCG_ESTATE};
@@ -317,12 +319,15 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     // 4) the records' weights
     if (tiles) {
       const bool finished = want_finish && !p->finish_recs;
-      timing_begin(p, STEP_BIN);
-      if (!early_scatter)
+      if (!early_scatter) {
+        timing_begin(p, STEP_BIN);
         bin_scatter_k(p, k_dev);   // with the weights when there are any
-      else if (computed && !finished)
+        timing_end(p, STEP_BIN);
+      } else if (computed && !finished) {
+        timing_begin(p, STEP_BIN);
         refill_alpha_dev(p);
-      timing_end(p, STEP_BIN);
+        timing_end(p, STEP_BIN);
+      }
     }
     p->finish_recs = false;
     p->nrec = -1;  // on the device (tile_off[ntiles]); read only when asked for
