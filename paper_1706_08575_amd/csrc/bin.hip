@@ -393,7 +393,9 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_count(const double* __restri
   }
 }
 
-template <class real>
+// ONE: a single round per workgroup (rounds == 1), whose keys stay in
+// registers from the count to the placement instead of being recomputed
+template <class real, bool ONE>
 __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_scatter(const double* __restrict__ k, int64_t m, TileGeom tg,
                                                             const WBinGeom* __restrict__ wgp,
                                                             int32_t* __restrict__ tile_cursor,
@@ -407,9 +409,9 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_scatter(const double* __rest
   const int nrow = wg.nb[0];
   for (int i = threadIdx.x; i < ntiles + nrow; i += BIN_BLOCK) sm[i] = 0;
   __syncthreads();
+  double u[BIN_IPT][2], x[BIN_IPT][2];
+  int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4], row[BIN_IPT], col[BIN_IPT];
   for (int rd = 0; rd < rounds; ++rd) {
-    double u[BIN_IPT][2], x[BIN_IPT][2];
-    int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4], row[BIN_IPT], col[BIN_IPT];
     bin2_keys(k, m, tg, wg, ((int64_t)blockIdx.x * rounds + rd) * BIN_IPT * BIN_BLOCK, u, c, key, l0, l1, row, col,
               x);
 #pragma unroll
@@ -432,9 +434,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_scatter(const double* __rest
   __syncthreads();
   for (int rd = 0; rd < rounds; ++rd) {
     const int64_t j0 = ((int64_t)blockIdx.x * rounds + rd) * BIN_IPT * BIN_BLOCK;
-    double u[BIN_IPT][2], x[BIN_IPT][2];
-    int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4], row[BIN_IPT], col[BIN_IPT];
-    bin2_keys(k, m, tg, wg, j0, u, c, key, l0, l1, row, col, x);
+    if constexpr (!ONE) bin2_keys(k, m, tg, wg, j0, u, c, key, l0, l1, row, col, x);
     int pos[BIN_IPT][4], rpos[BIN_IPT];
 #pragma unroll
     for (int i = 0; i < BIN_IPT; ++i) {
@@ -593,8 +593,12 @@ static void bin_points_fused_t(ftcg_plan p, const double* k) {
                      rcnt, rounds);
   exclusive_scan_pair_i32(tcnt, p->tile_off.as<int32_t>(), p->ntiles, tcnt, rcnt, p->wb_rowoff.as<int32_t>(),
                           WROW_MAX, rcnt, s);
-  hipLaunchKernelGGL(k_bin2_scatter<real>, dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, tg, wg, tcnt, (int)p->ntiles,
-                     rcnt, rounds, p->recs.as<Rec<real>>(), p->wb_rowbuf.as<RowRec>());
+  if (rounds == 1)
+    hipLaunchKernelGGL((k_bin2_scatter<real, true>), dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, tg, wg, tcnt,
+                       (int)p->ntiles, rcnt, rounds, p->recs.as<Rec<real>>(), p->wb_rowbuf.as<RowRec>());
+  else
+    hipLaunchKernelGGL((k_bin2_scatter<real, false>), dim3(nb), dim3(BIN_BLOCK), lds, s, k, m, tg, wg, tcnt,
+                       (int)p->ntiles, rcnt, rounds, p->recs.as<Rec<real>>(), p->wb_rowbuf.as<RowRec>());
   FTCG_HIP(hipGetLastError());
 }
 
