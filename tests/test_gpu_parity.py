@@ -359,6 +359,26 @@ def test_rejected_points_then_recovery(bad, n, dim, weights):
         assert O.rel_l2(img, O.ftcg_image(k, f, a_ref, n)) < TOL_F64
 
 
+@pytest.mark.parametrize("tile", [32, 128])
+def test_deferred_weights_match_finished(sas512, tile):
+    # on fused-binning grids the fixed-point spread forms each record's weight
+    # from the weight sums; after get_weights the records carry the finished
+    # weights and the spread reads those: the same float64 division, so the
+    # two images agree bitwise (one set_points, one set of sums)
+    k, f, a_ref, ref = sas512
+    from paper_1706_08575_amd.ftcg import Plan
+    with Plan(512, dim=2, dtype="f32", weights="plain") as P:
+        P.set_tuning(tile, "fixed", 1)
+        P.set_points(dev(k))
+        ff = dev(f, torch.complex64)
+        img_deferred = host(P.execute(ff))
+        a = host(P.get_weights())
+        img_finished = host(P.execute(ff))
+    assert np.array_equal(img_deferred, img_finished)
+    assert np.max(np.abs(a - a_ref) / a_ref) < 1e-10
+    assert O.rel_l2(img_deferred, ref) < TOL_F32
+
+
 def test_repeat_is_stable():
     # two executes of one plan agree to float32 rounding (LDS accumulation
     # order may differ between runs)
