@@ -321,9 +321,14 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
                                                                 const int32_t* __restrict__ boff, WBinGeom g,
                                                                 int cx, int chunk, double* __restrict__ wsum) {
   constexpr int RUN = WB_BLOCK * WT / S;
-  __shared__ __align__(16) WSample<2> cand[WCH];
-  __shared__ double cacc[WCH];
-  for (int i = threadIdx.x; i < WCH; i += WB_BLOCK) cacc[i] = 0.0;   // ordered by the first chunk's barriers
+  // candidates per LDS chunk: 256 with one sample per lane (14 KiB with the
+  // slot sums: occupancy 7 instead of 5, 2^17 samples 0.040 -> 0.038 ms),
+  // 512 with two (0.366 against 0.388 ms at 2^20, 1.59 against 2.18 ms at
+  // 2^23, where the wider runs fill the chunk)
+  constexpr int CH = WT == 1 ? 256 : WCH;
+  __shared__ __align__(16) WSample<2> cand[CH];
+  __shared__ double cacc[CH];
+  for (int i = threadIdx.x; i < CH; i += WB_BLOCK) cacc[i] = 0.0;   // ordered by the first chunk's barriers
   const int64_t lid = xcd_block_chunk(blockIdx.x, gridDim.x, chunk);
   const int b0 = (int)(lid / cx), bx = (int)(lid % cx);
   const int nb1 = g.nb[1];
@@ -383,8 +388,8 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
           me = min(ms + part, fe);
         }
       }
-      for (int q0 = gs; q0 < ge; q0 += WCH) {
-        const int q1 = min(q0 + WCH, ge);
+      for (int q0 = gs; q0 < ge; q0 += CH) {
+        const int q1 = min(q0 + CH, ge);
         __syncthreads();   // the previous chunk has been consumed and flushed
         {
           const float4* src = reinterpret_cast<const float4*>(ss + q0);
