@@ -189,6 +189,42 @@ def spread(k: np.ndarray, c: np.ndarray, n: int, sigma: float = 2.0, W: int = 6,
     return (re + 1j * im).reshape((G,) * d)
 
 
+def spread_window(k: np.ndarray, c: np.ndarray, n: int, r0: int, c0: int, h: int, w: int,
+                  sigma: float = 2.0, W: int = 6) -> np.ndarray:
+    """The same H as spread() (eq:twodcgmatrix, 2D), only on the window of grid
+    rows r0 .. r0+h-1 and columns c0 .. c0+w-1 (0 <= r0, r0+h <= G, likewise
+    for columns): the samples whose taps can reach the window are selected
+    first (by their grid position u taken modulo G), then their taps are
+    formed exactly as in spread() and those landing in the window summed.
+    For checks of grids too large to hold in float64."""
+    k = np.asarray(k, dtype=np.float64)
+    c = np.asarray(c, dtype=np.complex128)
+    G = grid_size(n, sigma)
+    beta = kernel_beta(sigma, W)
+    u = np.mod(sigma * k + G / 2, G)
+
+    def near(ua, lo, span):
+        # some integer g with |g - u| <= W lies in lo .. lo+span-1 (mod G)
+        d = np.mod(ua - (lo - W), G)
+        return d <= span - 1 + 2 * W
+
+    sel = np.nonzero(near(u[:, 0], r0, h) & near(u[:, 1], c0, w))[0]
+    out = np.zeros((h, w), dtype=np.complex128)
+    if sel.size == 0:
+        return out
+    uu = sigma * k[sel] + G / 2
+    i0, w0 = _axis_taps(uu[:, 0], W, beta, G)
+    i1, w1 = _axis_taps(uu[:, 1], W, beta, G)
+    rr = np.mod(i0 - r0, G)
+    cc = np.mod(i1 - c0, G)
+    inside = (rr[:, :, None] < h) & (cc[:, None, :] < w)
+    val = (w0[:, :, None] * w1[:, None, :]) * c[sel][:, None, None]
+    flat = (rr[:, :, None] * w + cc[:, None, :])[inside]
+    re = np.bincount(flat, weights=val.real[inside], minlength=h * w)
+    im = np.bincount(flat, weights=val.imag[inside], minlength=h * w)
+    return (re + 1j * im).reshape(h, w)
+
+
 # ----------------------------------------------------------------------------
 # steps 3-4: inverse FFT, divide by w (deapodize), crop (psi_m = e^{2 pi i m x}/w(x))
 # ----------------------------------------------------------------------------

@@ -232,6 +232,24 @@ def test_weights_tree_vs_dense_masked():
     assert np.max(np.abs(O.frame_weights_at(k, idx, R) - ref[idx]) / ref[idx]) < 1e-13
 
 
+def test_spread_window_is_a_window_of_spread():
+    # the windowed spread equals the full (pinned) spread on its window, for
+    # interior windows, windows on the periodic seam and samples outside the
+    # k-box, and is zero where no sample reaches
+    rng = np.random.default_rng(81)
+    n = 32
+    G = 64
+    k = rng.uniform(-0.7 * n, 0.7 * n, size=(900, 2))
+    k[:30] = n / 2 - 0.02 * rng.random((30, 2))          # u next to G (taps wrap)
+    c = S.random_values(82, k.shape[0])
+    H = O.spread(k, c, n)
+    for r0, c0, h, w in ((0, 0, 16, 16), (24, 40, 8, 24), (48, 48, 16, 16), (60, 0, 4, 64), (0, 0, G, G)):
+        Hw = O.spread_window(k, c, n, r0, c0, h, w)
+        assert np.max(np.abs(Hw - H[r0:r0 + h, c0:c0 + w])) < 1e-13 * np.max(np.abs(H))
+    kk = np.array([[0.1, 0.2]])
+    assert np.all(O.spread_window(kk, np.ones(1), n, 0, 0, 8, 8) == 0)
+
+
 # ---------------------------------------------------------------------------
 # the pins have teeth: each planted mistake in the oracle fails at least one pin
 # ---------------------------------------------------------------------------
