@@ -31,12 +31,14 @@ if ROOT not in sys.path:
 METRIC = "Msamples/s gridded + images/s at rel L2 <=1e-4 vs FP64 oracle (plain vs batched/learned)"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-# float64 operations per in-box neighbour pair of the weight sum (eq:difopt
-# with the Gram entries as sinc products), per axis: the difference (1),
-# sin(pi d) by the product formula (2 multiplies + 1 subtraction), pi d (1);
-# then per pair: product of the axis numerators and of the denominators in 2D
-# (2), the division (1), the square (1) and the accumulation (1)
-FLOPS_PER_PAIR = {1: 1 * 5 + 3, 2: 2 * 5 + 5}
+SPREAD_HBM_TARGET = 0.5
+# Work unit of the frame-weight sum (eq:difopt with the Gram entries as sinc
+# products): one ordered in-box pair (i, n), i != n, of the 2D sum costs
+# about 20 float64 operations (per axis the difference, sin(pi d) from the
+# per-sample sine and cosine, pi d; then the products, the division, the
+# square and the accumulation). The formula itself counts 15 per ordered
+# pair; 20 is the figure the work is planned against. In 1D: 8.
+FLOPS_PER_PAIR = {1: 8, 2: 20}
 
 WORKLOADS = {
     # name: (description, builder)
@@ -119,29 +121,33 @@ def measured_traffic(kernel: str, workload: str):
 
 
 def count_box_pairs(k, R, sample=None):
-    """Number of ordered pairs (i, n) with ||k_i - k_n||_inf <= R (self included),
-    exact or estimated from a random subset of n."""
+    """Number of ordered pairs (i, n), i != n, with ||k_i - k_n||_inf <= R,
+    exact or estimated from a seeded random subset of n."""
     from scipy.spatial import cKDTree
     tree = cKDTree(k)
     if sample is None or sample >= len(k):
-        return int(np.sum(tree.query_ball_point(k, r=R, p=np.inf, return_length=True)))
+        return int(np.sum(tree.query_ball_point(k, r=R, p=np.inf, return_length=True))) - len(k)
     rng = np.random.default_rng(0)
     idx = rng.choice(len(k), size=sample, replace=False)
     c = tree.query_ball_point(k[idx], r=R, p=np.inf, return_length=True)
-    return int(round(np.mean(c) * len(k)))
+    return int(round((np.mean(c) - 1.0) * len(k)))
 
 
 def cpu_baseline(name, k, f, n, R=8.0):
-    """The oracle as it stands, single-threaded, on a bounded sample."""
+    """The oracle as it stands on a bounded sample: its weights (k-d tree +
+    numpy) and spreading (numpy bincount) run on one thread, its FFT
+    (scipy.fft) on all host cores."""
     import oracle as O
     m = len(f)
+    workers = os.cpu_count() or 1
     t0 = time.perf_counter()
     if m <= 200_000:
         a = O.frame_weights(k, R)
-        img = O.ftcg_image(k, f, a, n)
+        img = O.ftcg_image(k, f, a, n, workers=workers)
         dt = time.perf_counter() - t0
-        return {"value": m / dt / 1e6, "unit": "Msamples/s", "cores": 1, "kind": "oracle",
-                "sample": f"whole workload: {m} samples, {n}^{k.shape[1]} image (weights + spread + FFT + deapod)",
+        return {"value": m / dt / 1e6, "unit": "Msamples/s", "cores": workers, "kind": "oracle",
+                "sample": f"whole workload: {m} samples, {n}^{k.shape[1]} image (weights + spread on one "
+                          f"thread, FFT + deapod on {workers})",
                 "seconds": dt}, img, a
     # large workloads: weights of a contiguous 1/64 of the samples (their
     # neighbour sums use the whole raster), spreading of the same subset onto
@@ -156,14 +162,37 @@ def cpu_baseline(name, k, f, n, R=8.0):
     H = O.spread(k[sub], a_sub * f[sub], n)
     t_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    O.grid_to_image(H, n)
+    O.grid_to_image(H, n, workers=workers)
     t_f = time.perf_counter() - t0
     per_sample = (t_w + t_s) / len(idx)
     total = per_sample * m + t_f
-    return {"value": m / total / 1e6, "unit": "Msamples/s", "cores": 1, "kind": "oracle",
-            "sample": f"weights + spreading of {len(idx)} of {m} samples (scaled x{m / len(idx):.0f}) "
-                      f"+ one full {2 * n}^2 FFT/deapod; measured {t_w + t_s + t_f:.1f} s",
-            "seconds_projected": total}, None, None
+    return {"value": m / total / 1e6, "unit": "Msamples/s", "cores": workers, "kind": "oracle",
+            "sample": f"weights + spreading (one thread) of {len(idx)} of {m} samples (scaled "
+                      f"x{m / len(idx):.0f}) + one full {2 * n}^2 FFT/deapod on {workers} threads; "
+                      f"measured {t_w + t_s + t_f:.1f} s",
+            "seconds_projected": total, "stage_seconds": {"weights_sample": t_w, "spread_sample": t_s,
+                                                          "fft_full": t_f}}, None, None
+
+
+def sampled_parity(k, f, alpha_gpu, img, n, pixels=24, weights=256, seed=4096, R=8.0):
+    """Errors of a full-size run the oracle cannot redo whole: weights of
+    seeded samples against the oracle's per-sample sum, and seeded pixels
+    plus the brightest ones against the oracle's exact weighted sum (fed the
+    GPU's weights, which the first check validates)."""
+    import oracle as O
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(len(f), weights, replace=False)
+    a_ref = O.frame_weights_at(k, idx, R)
+    werr = float(np.max(np.abs(alpha_gpu[idx] - a_ref) / a_ref))
+    top = np.argsort(np.abs(img).ravel())[-4:]
+    pix = np.concatenate([rng.integers(0, n * n, pixels), top])
+    p0, p1 = pix // n, pix % n
+    x = np.stack([(p0 - n // 2) / n, (p1 - n // 2) / n], axis=1)
+    ref = O.nudft_at(k, alpha_gpu * f, x)
+    got = img[p0, p1]
+    return {"weights_max_rel_err": werr, "weights_checked": weights,
+            "image_rel_l2_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "pixels_checked": int(len(pix)), "reference": "oracle.nudft_at with the GPU weights (exact sum)"}
 
 
 MODEL_PATH = os.path.join(ROOT, "paper_1706_08575_amd", "models", "mlp_sas.bin")
@@ -213,21 +242,28 @@ def bench_batched(steps: int, warmup: int, tune: bool = True) -> dict:
     torch.cuda.synchronize()
     sec_exec = (time.perf_counter() - tb) / steps
     info = B.info()
-    # parity on the two smallest items against the oracle
+    # parity against the oracle: the two densest items (samples per pixel,
+    # where the fixed-point tiles hold the most records), fed the GPU's
+    # weights, and the smallest item, with the oracle's own weights
     import oracle as O
-    order = np.argsort(m)[:2]
+    w_all = B.get_weights().cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum(m)])
+    dens = np.array(m, dtype=np.float64) / np.array(sizes, dtype=np.float64) ** 2
     errs = {}
-    for i in order:
+    for i in list(np.argsort(dens)[-2:]) + [int(np.argmin(m))]:
         k, f = data[i][0], data[i][1]
-        ref = O.ftcg_image(k, f, O.frame_weights(k, 8.0), sizes[i])
-        errs[int(i)] = O.rel_l2(B.image(out, int(i)).cpu().numpy(), ref)
+        a = w_all[offs[i]:offs[i + 1]] if dens[i] > 1.0 else O.frame_weights(k, 8.0)
+        ref = O.ftcg_image(k, f, a, sizes[i], workers=os.cpu_count() or 1)
+        errs[int(i)] = {"n": sizes[i], "m": m[i], "samples_per_pixel": float(dens[i]),
+                        "rel_l2": O.rel_l2(B.image(out, int(i)).cpu().numpy(), ref),
+                        "oracle_weights": "GPU's (checked separately)" if dens[i] > 1.0 else "oracle's"}
     B.close()
     mt = int(sum(m))
     return {"workload": "batch64_sas", "items": len(items), "samples": mt, "ms_per_step": sec * 1e3,
             "images_per_s": len(items) / sec, "msamples_per_s": mt / sec / 1e6,
             "execute_only_ms": sec_exec * 1e3, "execute_only_images_per_s": len(items) / sec_exec,
             "tuned_tile_chunk": tuned, "tasks": info["tasks"], "split_tiles": info["split_tiles"],
-            "records": info["records"], "rel_l2_vs_oracle_smallest_items": errs,
+            "records": info["records"], "rel_l2_vs_oracle_items": errs,
             "input_generation_s": t_gen}
 
 
@@ -301,11 +337,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sas512_plain", choices=sorted(WORKLOADS))
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="sas4096_precision", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--accum", default=None, choices=["fixed", "f64", "mfma"])
+    ap.add_argument("--accum", default=None, choices=["fixed", "f64"])
     ap.add_argument("--copies", type=int, default=1)
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and learned forms")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -387,51 +423,56 @@ def main():
         del x, y
 
     # ms per step in each stage (a stage may be timed in several intervals
-    # per step: the binning before and after the weights; stages on the
-    # plan's second stream overlap the others)
-    stage_ms = {s: ms / args.steps for s, (ms, c) in stages.items()}
-    # roofline of the dominant kernel (among the steps with a work model)
-    # stages of one dominant kernel each (the binning stages run several
-    # short kernels: input check and its reduction, count, scan, scatter)
-    modelled = [s_ for s_ in stage_ms if s_ == "weights" or
-                (s_ not in ("bin", "weight_bin") and
-                 step_bytes(s_, m, info["n_records"], n, G, dim, dtype) is not None)]
-    dom = max(modelled, key=stage_ms.get)
-    roof = None
+    # per step: the binning before and after the weights)
+    stage_ms = {s_: ms / args.steps for s_, (ms, c) in stages.items()}
+    stage_count = {s_: c for s_, (ms, c) in stages.items()}
+    # roofline of the dominant kernel among the stages that are one kernel
+    # each (the weight sum, the spread, the FFT passes; the binning stages
+    # run several short kernels)
+    single = [s_ for s_ in ("weights", "spread", "fft1", "fft2_deapod") if s_ in stage_ms]
+    dom = max(single, key=stage_ms.get)
     if dom == "weights":
         pairs = count_box_pairs(k, 8.0, sample=None if m <= 200_000 else 20000)
         flops = pairs * FLOPS_PER_PAIR[dim]
-        ach = flops / (stage_ms[dom] * 1e-3) / 1e12
-        # 2D: the symmetric kernel forms each unordered pair once; the work
-        # counted is the method's, every ordered in-box pair (both orders)
+        launch_ms = stage_ms[dom] * args.steps / stage_count[dom]     # mean event time of one launch
+        ach = flops / (launch_ms * 1e-3) / 1e12
         kname = "k_frame_weights_sym<" if dim == 2 else "k_frame_weights_1d<"
         tr = measured_traffic(kname, args.workload)
         kname = tr["kernel"] if tr else kname + "...>"
         roof = {"kernel": kname, "bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS, "traffic": tr["bytes"] if tr else None,
-                "work_per_launch": f"{pairs} ordered in-box pairs x {FLOPS_PER_PAIR[dim]} FP64 flops"
-                                   + (" (2D kernel forms each unordered pair once; stage = it, plus on"
-                                      " grids of more than 4096 tiles its bin-order to caller-order finish;"
-                                      " on the others the spread forms the weights from the sums)"
-                                      if dim == 2 else ""),
-                "algorithmic_bytes_per_launch": m * (48 + 4 + 8)}
+                "launch_ms": launch_ms,
+                "work_per_launch": f"{pairs} ordered in-box pairs (i != n) x {FLOPS_PER_PAIR[dim]} FP64 flops"
+                                   + (" (the symmetric kernel forms each unordered pair once)" if dim == 2 else ""),
+                "algorithmic_bytes_per_launch": m * (48 + 8)}
     else:
         b = step_bytes(dom, m, info["n_records"], n, G, dim, dtype)
-        ach = b / (stage_ms[dom] * 1e-3) / 1e9
-        kname = {"spread": "k_spread2d" if dim == 2 else "k_spread1d", "fft1": "k_fft_rows (pass 1)",
-                 "fft2_deapod": "k_fft_rows (pass 2)", "bin": "binning kernels"}.get(dom, dom)
+        launch_ms = stage_ms[dom] * args.steps / stage_count[dom]
+        ach = b / (launch_ms * 1e-3) / 1e9
+        kname = {"spread": "k_spread2d_fx" if dim == 2 else "k_spread1d", "fft1": "k_fft_rows (pass 1)",
+                 "fft2_deapod": "k_fft_rows (pass 2)"}.get(dom, dom)
+        tr = measured_traffic(kname + "<", args.workload) if dom == "spread" else None
         roof = {"kernel": kname, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": b}
+                "frac": ach / HBM_PEAK_GBS, "traffic": tr["bytes"] if tr else None, "launch_ms": launch_ms,
+                "bytes_per_launch": b}
     # every HBM-bound step, for reference
     steps_hbm = {}
-    for s in ("spread", "fft1", "fft2_deapod", "bin", "weight_bin"):
-        if s in stage_ms:
-            b = step_bytes(s, m, info["n_records"], n, G, dim, dtype)
-            steps_hbm[s] = {"ms": stage_ms[s], "GB/s": b / (stage_ms[s] * 1e-3) / 1e9,
-                            "frac_hbm": b / (stage_ms[s] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    for s_ in ("spread", "fft1", "fft2_deapod", "bin", "weight_bin"):
+        if s_ in stage_ms:
+            b = step_bytes(s_, m, info["n_records"], n, G, dim, dtype)
+            steps_hbm[s_] = {"ms": stage_ms[s_], "GB/s": b / (stage_ms[s_] * 1e-3) / 1e9,
+                             "frac_hbm": b / (stage_ms[s_] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    spread_target = None
+    if "spread" in steps_hbm:
+        fr = steps_hbm["spread"]["frac_hbm"]
+        spread_target = {"frac_hbm": fr, "target": SPREAD_HBM_TARGET, "met": fr >= SPREAD_HBM_TARGET,
+                         "ms": stage_ms["spread"], "ms_at_target": step_bytes("spread", m, info["n_records"], n, G,
+                                                                               dim, dtype) / (SPREAD_HBM_TARGET *
+                                                                                              HBM_PEAK_GBS * 1e6)}
 
     cpu = None
     rel = None
+    parity = None
     if not args.no_cpu:
         cpu, img_ref, a_ref = cpu_baseline(args.workload, k, f, n)
         if img_ref is not None:
@@ -439,6 +480,10 @@ def main():
             rel = O.rel_l2(img, img_ref)
             rel_w = float(np.max(np.abs(alpha - a_ref) / a_ref))
             cpu["weights_max_rel_err"] = rel_w
+            parity = {"image_rel_l2": rel, "weights_max_rel_err": rel_w, "reference": "whole oracle image"}
+        elif dim == 2:
+            parity = sampled_parity(k, f, alpha, img, n)
+            rel = parity["image_rel_l2_sampled"]
 
     forms = None
     if not args.no_forms:
@@ -466,8 +511,10 @@ def main():
         "images_per_s": 1.0 / sec,
         "spread_msamples_per_s": m / (stage_ms["spread"] * 1e-3) / 1e6 if "spread" in stage_ms else None,
         "rel_l2_vs_oracle": rel,
+        "parity": parity,
         "stage_ms": stage_ms,
         "hbm_steps": steps_hbm,
+        "spread_vs_hbm_target": spread_target,
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": forms,

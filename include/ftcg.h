@@ -67,7 +67,9 @@ typedef enum {
   FTCG_W_PLAIN = 0,       /* frame-optimal diagonal weights, computed on the GPU in float64 */
   FTCG_W_LEARNED = 1,     /* weights predicted by the plan's MLP, audited against FTCG_W_PLAIN */
   FTCG_W_USER = 2,        /* caller supplies alpha with ftcg_set_weights */
-  FTCG_W_NONE = 3         /* alpha_j = 1 */
+  FTCG_W_NONE = 3,        /* alpha_j = 1 */
+  FTCG_W_BAND = 4         /* the (2r-1)-banded FTCG coefficient matrix C of eq:ftcg / eq:cr,
+                             computed on the GPU in float64 (ftcg_plan_set_band) */
 } ftcg_wmode;
 
 /* Human-readable name of a status code (static storage). */
@@ -91,7 +93,10 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
                              double oversampling, ftcg_dtype dtype, ftcg_wmode wmode,
                              double weight_radius, void* hip_stream);
 
-/* Release the plan and its device workspace (synchronises the plan's stream). */
+/* Release the plan and its device workspace (synchronises the plan's stream).
+ * Ends the lifetime of the operators Omega, D and the FFT plan of eq:cgmatrix
+ * held for one raster; nothing of the method is computed. FTCG_EINVAL for a
+ * NULL plan; the handle is invalid afterwards. */
 ftcg_status ftcg_plan_destroy(ftcg_plan plan);
 
 /* Set the sample locations (the raster {lambda_j}, Sec. III-A / Sec. IV eq:twoddataframe).
@@ -103,18 +108,60 @@ ftcg_status ftcg_plan_destroy(ftcg_plan plan);
  * for that check alone, while the binning passes already run). */
 ftcg_status ftcg_set_points(ftcg_plan plan, int64_t m, const double* k_dev);
 
-/* FTCG_W_USER only: alpha_dev is a device float64 array of m weights. */
+/* Caller-supplied quadrature weights: the diagonal D = diag(alpha) of
+ * eq:cgmatrix / eq:D_alpha (2D: D_2 of eq:twodcgmatrix), used as given.
+ *   alpha_dev : device float64 array of m weights in caller sample order,
+ *               read (copied into the plan) before the call's work ends.
+ * FTCG_W_USER plans only (else FTCG_ESTATE), after ftcg_set_points (else
+ * FTCG_ESTATE); FTCG_EINVAL for NULL. Enqueues only. */
 ftcg_status ftcg_set_weights(ftcg_plan plan, const double* alpha_dev);
 
-/* Copy the weights in use (m float64, sample order) to alpha_dev (device).
- * used_fallback_host (may be NULL) receives 1 when a FTCG_W_LEARNED plan fell
- * back to the plain weights, else 0 (synchronises the stream). */
+/* Copy the quadrature weights in use, the diagonal of D (eq:D_alpha; for
+ * FTCG_W_PLAIN the column-wise optimum of eq:difopt), to alpha_dev.
+ *   alpha_dev          : device float64 array of m entries (caller order),
+ *                        owned by the caller, written entirely.
+ *   used_fallback_host : host int (may be NULL); receives 1 when a
+ *                        FTCG_W_LEARNED plan fell back to the plain weights,
+ *                        else 0 (then the call synchronises the stream).
+ * FTCG_ESTATE before the points (and, for FTCG_W_USER, the weights) are set. */
 ftcg_status ftcg_get_weights(ftcg_plan plan, double* alpha_dev, int* used_fallback_host);
 
-/* Run weighting, spreading, inverse FFT, deapodization and crop.
- *   fhat_dev  : device, m complex values (complex128 / complex64 by dtype).
- *   image_dev : device, n^dim complex values, row-major, written entirely. */
+/* The reconstruction A_cg(f) at the n^dim pixels: gamma = Omega D fhat
+ * (weighting and spreading, eq:cgmatrix; 2D eq:twodcgmatrix), the sum over
+ * psi_m = e^{2 pi i m x} / w(x) as an inverse FFT of the oversampled grid,
+ * division by w (deapodization) and crop (eq:ffind, eq:twodcg).
+ *   fhat_dev  : device, m complex values in caller sample order
+ *               (complex128 / complex64 by dtype), read only.
+ *   image_dev : device, n^dim complex values, row-major, written entirely.
+ * FTCG_ESTATE before ftcg_set_points (and, for FTCG_W_USER, the weights);
+ * FTCG_EINVAL for NULL pointers. Enqueues only (no host synchronisation). */
 ftcg_status ftcg_execute(ftcg_plan plan, const void* fhat_dev, void* image_dev);
+
+/* Banded FTCG coefficient matrix (FTCG_W_BAND plans; Sec. III-C eq:ftcg,
+ * eq:cr, eq:dif3; 2D Sec. IV eq:twodftcg): tau = Omega C fhat with C the
+ * (2r-1)-banded matrix that minimises ||T C - I||_F column by column, T the
+ * truncated Gram matrix of the data frame (the T of the diagonal weights),
+ * the band J(n) = {n - r + 1, ..., n + r - 1} taken in the caller's sample
+ * order (for a raster acquired pulse by pulse, neighbouring samples of a
+ * pulse). Column n solves the normal equations of its least-squares problem
+ * by a float64 Cholesky factorisation; r = 1 gives the diagonal weights of
+ * FTCG_W_PLAIN.
+ *   ftcg_plan_set_band : r in 1..16 (default 1); takes effect at the next
+ *                        ftcg_set_points. FTCG_ESTATE for other weight modes.
+ *   ftcg_set_points    : also computes C (one host synchronisation); returns
+ *                        FTCG_EINVAL when a column's normal matrix is not
+ *                        positive definite (T[:, J(n)] without full column
+ *                        rank, e.g. two samples at one location within r
+ *                        positions of each other).
+ *   ftcg_execute       : forms c = C fhat in float64 (rounded to the plan's
+ *                        precision), then spreads c with weight 1.
+ *   ftcg_get_band      : copies C by columns to c_dev (device float64,
+ *                        m x (2r-1), entry [n][p] = C[n - r + 1 + p, n], 0
+ *                        where that row is outside 0..m-1); r_host (may be
+ *                        NULL) receives r.
+ * ftcg_get_weights returns FTCG_ESTATE for FTCG_W_BAND plans. */
+ftcg_status ftcg_plan_set_band(ftcg_plan plan, int r);
+ftcg_status ftcg_get_band(ftcg_plan plan, double* c_dev, int* r_host);
 
 /* Steps of ftcg_execute, for per-step checks:
  *   ftcg_spread_only writes the oversampled grid H (G^dim complex, row-major,
@@ -129,33 +176,29 @@ ftcg_status ftcg_grid_to_image(ftcg_plan plan, const void* grid_dev, void* image
 ftcg_status ftcg_plan_info(ftcg_plan plan, int64_t* grid_size, int64_t* n_records,
                            int64_t* n_tiles, int* tile);
 
-/* Tile accumulation of the spreading step.
+/* Tile accumulation of the spreading step (Omega D fhat of eq:cgmatrix).
  *   FTCG_ACCUM_FIXED : float32 plans only (their default). Taps are scaled by a
- *                      per-tile bound and accumulated exactly as packed int32
- *                      (re, im) pairs with one 64-bit LDS integer add per tap;
- *                      results are bitwise reproducible, error <= 2^-31 of the
- *                      tile bound per tap.
+ *                      per-tile bound, rounded to the nearest integer and
+ *                      accumulated exactly as packed int32 (re, im) pairs with
+ *                      one 64-bit LDS integer add per tap; results are bitwise
+ *                      reproducible, error <= half of 2^-31 of the tile bound
+ *                      per tap (unbiased).
  *   FTCG_ACCUM_F64   : taps accumulated with float64 LDS atomics (the default
  *                      and only mode of float64 plans); lds_copies > 1 gives
  *                      each wavefront its own partial tile, combined at the
- *                      flush with compensated (TwoSum) addition.
- *   FTCG_ACCUM_MFMA  : 2D float32 plans, tile 64 only. Every 16 x 16 block of
- *                      a tile is the sum over its records of (row taps x value)
- *                      times (column taps), formed four records at a time on
- *                      the float32 matrix cores with float32 accumulation in
- *                      registers (no LDS tile, no atomics). */
-typedef enum { FTCG_ACCUM_FIXED = 0, FTCG_ACCUM_F64 = 1, FTCG_ACCUM_MFMA = 2 } ftcg_accum;
+ *                      flush with compensated (TwoSum) addition. */
+typedef enum { FTCG_ACCUM_FIXED = 0, FTCG_ACCUM_F64 = 1 } ftcg_accum;
 
 /* Tuning knobs (take effect at the next ftcg_set_points; the points must be
  * set again):
  *   tile       : tile edge in grid cells (16, 32, 64, 128; 0 = automatic:
- *                32 in 2D (64 with FTCG_ACCUM_MFMA), min(G, 1024) in 1D);
+ *                32 in 2D, min(G, 1024) in 1D);
  *                FTCG_ACCUM_F64 supports tile <= 64 and
  *                lds_copies * 16 * tile * (tile + 1) <= 160 KiB.
- *   accum      : ftcg_accum (FTCG_ACCUM_FIXED needs a float32 plan,
- *                FTCG_ACCUM_MFMA a 2D float32 plan with tile 64 and G >= 64).
+ *   accum      : ftcg_accum (FTCG_ACCUM_FIXED needs a float32 plan).
  *   lds_copies : 1, 2 or 4 (FTCG_ACCUM_F64 only; must be 1 otherwise).
- * Returns FTCG_EUNSUPPORTED for combinations that do not fit LDS. */
+ * Returns FTCG_EUNSUPPORTED for combinations that do not fit LDS and
+ * FTCG_EINVAL for values outside these sets. */
 ftcg_status ftcg_plan_set_tuning(ftcg_plan plan, int tile, int accum, int lds_copies);
 
 /* Launch shape of the frame-weight sum (Sec. III-C, eq:difopt), taking effect
@@ -174,14 +217,17 @@ ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan plan, int samples_per_lane, in
 /* Per-step timing with HIP events on the plan's stream.
  * enable != 0 records events around every step of later calls; ftcg_plan_timing
  * synchronises the stream and returns, for each step s in
- * {0 input check + tile binning, 1 frame-weight sum kernel and its finish,
+ * {0 input check + tile binning, 1 frame-weight sum kernel (alone),
  *  2 spread, 3 fft pass 1, 4 fft pass 2 + deapodize + crop, 5 neighbour binning
- *  for weights, 6 learned-weight inference, 7 learned-weight audit},
+ *  for weights, 6 learned-weight inference, 7 learned-weight audit,
+ *  8 weights from the sums (and the sums' preset), 9 banded C: band of T^2,
+ *  10 banded C: normal equations, 11 banded C: c = C fhat},
  * the summed milliseconds ms[s] and the number of timed intervals count[s]
- * (arrays of 8 entries; unused entries are 0), then resets the sums. A step
- * can be timed in several intervals per call (step 0: the input check, then
- * the binning after the host has read the check's result; the host's wait
- * in between is in no step). */
+ * (host arrays of FTCG_TIMING_STEPS entries; unused entries are 0), then
+ * resets the sums. A step can be timed in several intervals per call (step 0:
+ * the input check, then the binning after the host has read the check's
+ * result; the host's wait in between is in no step). */
+#define FTCG_TIMING_STEPS 16
 ftcg_status ftcg_plan_enable_timing(ftcg_plan plan, int enable);
 ftcg_status ftcg_plan_timing(ftcg_plan plan, double* ms, int64_t* count);
 

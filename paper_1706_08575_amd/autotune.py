@@ -1,10 +1,13 @@
-"""Autotuner for the spreading launch: tile edge and accumulation (LDS
-integers or matrix cores; for batches, tile and records per task) chosen by
-timing candidates on the caller's own data, remembered in a JSON cache keyed
-by the workload's shape.
+"""Autotuner for the spreading launch: tile edge (for batches, tile and
+records per task) chosen by timing candidates on the caller's own data,
+remembered in a JSON cache keyed by the workload's shape.
 
-Keys: single plans by (precision, W, sigma, n, log2 of samples per grid cell
-rounded to half steps); batches by the same key over the batch's item mix.
+Keys are plain strings: single plans by (dimension, precision, W, sigma, n,
+log2 of samples per grid cell rounded to half steps); batches by (W, sigma,
+R) and the sorted list of (n, density bucket) of their items, written out.
+The neighbour-bin shape of the weight sum is not tuned here: it follows
+from the raster's mean density (about 4.5 samples per bin), a rule measured
+once on the SAS rasters.
 The cache lives at $FTCG_TUNING_CACHE (default: ~/.cache/ftcg_tuning.json);
 every measurement is the mean of the library's own event timings of the
 spreading step over `reps` executions after one warm-up.
@@ -52,16 +55,14 @@ def density_bucket(m: int, n: int, sigma: float) -> float:
     return round(2.0 * math.log2(max(m, 1) / cells)) / 2.0
 
 
-def plan_key(dtype: str, W: int, sigma: float, n: int, m: int) -> str:
-    return f"plan/{dtype}/W{W}/s{sigma:g}/n{n}/d{density_bucket(m, n, sigma):+.1f}"
+def plan_key(dim: int, dtype: str, W: int, sigma: float, n: int, m: int) -> str:
+    return f"plan/d{dim}/{dtype}/W{W}/s{sigma:g}/n{n}/dens{density_bucket(m, n, sigma):+.1f}"
 
 
-def batch_key(W: int, sigma: float, sizes, ms) -> str:
+def batch_key(W: int, sigma: float, R: float, sizes, ms) -> str:
     mix = sorted((int(n), density_bucket(int(m), int(n), sigma)) for n, m in zip(sizes, ms))
-    h = 0
-    for n, d in mix:
-        h = (h * 1000003 + hash((n, d))) & 0xFFFFFFFFFFFF
-    return f"batch/W{W}/s{sigma:g}/items{len(mix)}/{h:012x}"
+    items = ",".join(f"{n}:{d:+.1f}" for n, d in mix)
+    return f"batch/W{W}/s{sigma:g}/R{R:g}/items{len(mix)}/{items}"
 
 
 def _spread_ms(obj, run, reps: int) -> float:
@@ -79,11 +80,10 @@ def _spread_ms(obj, run, reps: int) -> float:
 
 def tune_plan(plan, k: torch.Tensor, fhat: torch.Tensor, tiles=PLAN_TILES, reps: int = 3, use_cache: bool = True):
     """Pick the spreading launch of `plan` for raster k, values fhat: the tile
-    edge with the plan's LDS accumulation, and for 2D float32 plans also the
-    matrix-core accumulation (tile 64). Leaves the plan tuned and with its
+    edge with the plan's LDS accumulation. Leaves the plan tuned and with its
     points set. Returns ((tile, accum), {"tile/accum": ms})."""
     dtype = "f32" if plan.cdtype == torch.complex64 else "f64"
-    key = plan_key(dtype, plan.W, plan.sigma, plan.n, int(k.shape[0]))
+    key = plan_key(plan.dim, dtype, plan.W, plan.sigma, plan.n, int(k.shape[0]))
     cache = _load() if use_cache else {}
     if use_cache and key in cache and "accum" in cache[key]:
         tile, accum = int(cache[key]["tile"]), cache[key]["accum"]
@@ -92,8 +92,6 @@ def tune_plan(plan, k: torch.Tensor, fhat: torch.Tensor, tiles=PLAN_TILES, reps:
         return (tile, accum), cache[key].get("ms", {})
     base = "fixed" if dtype == "f32" else "f64"
     cands = [(t, base) for t in tiles if t >= 2 * plan.W]
-    if dtype == "f32" and plan.dim == 2:
-        cands.append((64, "mfma"))
     times = {}
     for t, accum in cands:
         try:
@@ -116,7 +114,7 @@ def tune_batch(batch, m, k: torch.Tensor, fhat: torch.Tensor, tiles=BATCH_TILES,
                reps: int = 3, use_cache: bool = True):
     """Pick (tile, records per task) of a Batch by timing whole executions.
     Leaves the batch tuned with its points set. Returns ((tile, chunk), {(tile, chunk): ms})."""
-    key = batch_key(6, 2.0, batch.sizes, m)
+    key = batch_key(batch.W, batch.sigma, batch.R, batch.sizes, m)
     cache = _load() if use_cache else {}
     if use_cache and key in cache:
         tile, chunk = int(cache[key]["tile"]), int(cache[key]["chunk"])

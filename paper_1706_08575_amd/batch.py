@@ -16,6 +16,7 @@ class Batch:
     def __init__(self, sizes, W: int = 6, sigma: float = 2.0, weights: str = "plain", R: float = 8.0,
                  stream=None, device=None):
         self.sizes = [int(n) for n in sizes]
+        self.W, self.sigma, self.R = int(W), float(sigma), float(R)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         wmode = {"plain": L.FTCG_W_PLAIN, "learned": L.FTCG_W_LEARNED, "user": L.FTCG_W_USER,
                  "none": L.FTCG_W_NONE}[weights]

@@ -53,7 +53,7 @@ static int auto_tile(ftcg_plan p) {
 }
 
 static void setup_tiles(ftcg_plan p) {
-  int t = p->tile_req ? p->tile_req : (p->accum == ACCUM_MFMA ? 64 : auto_tile(p));
+  int t = p->tile_req ? p->tile_req : auto_tile(p);
   if (t > p->G) t = (int)p->G;
   p->tile = t;
   p->nt = p->G / t;
@@ -136,7 +136,7 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
   if (half_width < 2 || half_width > 8) return FTCG_EINVAL;
   if (!(oversampling >= 1.25 && oversampling <= 4.0)) return FTCG_EINVAL;
   if (dtype != FTCG_F32 && dtype != FTCG_F64) return FTCG_EINVAL;
-  if (wmode < FTCG_W_PLAIN || wmode > FTCG_W_NONE) return FTCG_EINVAL;
+  if (wmode < FTCG_W_PLAIN || wmode > FTCG_W_BAND) return FTCG_EINVAL;
   if (!(weight_radius > 0.0 && weight_radius <= 64.0)) return FTCG_EINVAL;
   const double g = oversampling * (double)n0;
   if (fabs(g - nearbyint(g)) > 1e-9) return FTCG_EINVAL;
@@ -192,7 +192,7 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
 ftcg_status ftcg_plan_destroy(ftcg_plan p) {
   if (!p) return FTCG_EINVAL;
   (void)hipStreamSynchronize(p->stream);
-  DevBuf* bufs[] = {&p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp, &p->tile_scan_tmp, &p->check_part, &p->geo,
+  DevBuf* bufs[] = {&p->band_P, &p->band_col, &p->band_row, &p->band_c, &p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp, &p->tile_scan_tmp, &p->check_part, &p->geo,
                     &p->flags,  &p->wb_cnt, &p->wb_off, &p->wb_rowoff, &p->wb_rowbuf, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->ws_inv, &p->ws_sum, &p->audit_buf,
                     &p->grid,   &p->fft_tmp, &p->deapod, &p->twiddle, &p->tile_order};
   for (DevBuf* b : bufs) b->release();
@@ -230,7 +230,8 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
       zero_ptr = p->tile_cnt.as<int32_t>();
       zero_n = p->ntiles + 1;
     }
-    const bool rows2d = p->dim == 2 && (p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED);
+    const bool band = p->wmode == FTCG_W_BAND;
+    const bool rows2d = p->dim == 2 && (p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED || band);
     int32_t* zero_b = nullptr;
     int64_t zero_nb = 0;
     if (rows2d) {
@@ -294,7 +295,7 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
     // sums through the caller-to-bin map the bin sort then writes;
     // finish_deferred_weights serves every other reader)
     const bool want_finish = early_scatter && p->dim == 2 && p->wmode == FTCG_W_PLAIN;
-    if (computed) {
+    if (computed || band) {
       if (p->wmode == FTCG_W_LEARNED && !p->mlp) throw StatusError{FTCG_ESTATE};
       p->finish_recs = want_finish;
       if (p->dim == 2) {
@@ -307,10 +308,16 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
       } else {
         build_weight_bins_1d(p, k_dev);
       }
-      if (p->wmode == FTCG_W_PLAIN)
+      if (p->wmode == FTCG_W_PLAIN) {
         run_plain_weights(p);
-      else
+      } else if (band) {
+        // the records carry weight 1; C is applied to the values before the
+        // spread (execute)
+        fill_ones(p->alpha.as<double>(), m, p->stream);
+        run_band_weights(p);
+      } else {
         run_learned_with_audit(p, k_dev);
+      }
       p->have_weights = true;
     } else if (p->wmode == FTCG_W_NONE) {
       fill_ones(p->alpha.as<double>(), m, p->stream);
@@ -323,7 +330,7 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
         timing_begin(p, STEP_BIN);
         bin_scatter_k(p, k_dev);   // with the weights when there are any
         timing_end(p, STEP_BIN);
-      } else if (computed && !finished) {
+      } else if ((computed || band) && !finished) {
         timing_begin(p, STEP_BIN);
         refill_alpha_dev(p);
         timing_end(p, STEP_BIN);
@@ -348,7 +355,7 @@ ftcg_status ftcg_set_weights(ftcg_plan p, const double* alpha_dev) {
 
 ftcg_status ftcg_get_weights(ftcg_plan p, double* alpha_dev, int* used_fallback_host) {
   if (!p || !alpha_dev) return FTCG_EINVAL;
-  if (!p->have_points || !p->have_weights) return FTCG_ESTATE;
+  if (!p->have_points || !p->have_weights || p->wmode == FTCG_W_BAND) return FTCG_ESTATE;
   return guarded([&] {
     finish_deferred_weights(p);
     FTCG_HIP(hipMemcpyAsync(alpha_dev, p->alpha.p, sizeof(double) * p->m, hipMemcpyDeviceToDevice, p->stream));
@@ -363,6 +370,10 @@ ftcg_status ftcg_spread_only(ftcg_plan p, const void* fhat_dev, void* grid_dev) 
   if (!p || !fhat_dev || !grid_dev) return FTCG_EINVAL;
   if (!p->have_points || !p->have_weights) return FTCG_ESTATE;
   return guarded([&] {
+    if (p->wmode == FTCG_W_BAND) {
+      band_apply(p, fhat_dev);
+      fhat_dev = p->band_c.p;
+    }
     timing_begin(p, STEP_SPREAD);
     spread(p, fhat_dev, grid_dev);
     timing_end(p, STEP_SPREAD);
@@ -378,10 +389,34 @@ ftcg_status ftcg_execute(ftcg_plan p, const void* fhat_dev, void* image_dev) {
   if (!p || !fhat_dev || !image_dev) return FTCG_EINVAL;
   if (!p->have_points || !p->have_weights) return FTCG_ESTATE;
   return guarded([&] {
+    if (p->wmode == FTCG_W_BAND) {
+      band_apply(p, fhat_dev);
+      fhat_dev = p->band_c.p;
+    }
     timing_begin(p, STEP_SPREAD);
     spread(p, fhat_dev, p->grid.p);
     timing_end(p, STEP_SPREAD);
     grid_to_image(p, p->grid.p, image_dev);
+  });
+}
+
+ftcg_status ftcg_plan_set_band(ftcg_plan p, int r) {
+  if (!p) return FTCG_EINVAL;
+  if (p->wmode != FTCG_W_BAND) return FTCG_ESTATE;
+  if (r < 1 || r > 16) return FTCG_EINVAL;
+  p->band_r = r;
+  p->have_points = false;
+  p->have_weights = false;
+  return FTCG_OK;
+}
+
+ftcg_status ftcg_get_band(ftcg_plan p, double* c_dev, int* r_host) {
+  if (!p || !c_dev) return FTCG_EINVAL;
+  if (p->wmode != FTCG_W_BAND || !p->have_points || !p->have_weights) return FTCG_ESTATE;
+  return guarded([&] {
+    FTCG_HIP(hipMemcpyAsync(c_dev, p->band_col.p, sizeof(double) * p->m * (2 * p->band_r - 1),
+                            hipMemcpyDeviceToDevice, p->stream));
+    if (r_host) *r_host = p->band_r;
   });
 }
 
@@ -429,12 +464,9 @@ ftcg_status ftcg_plan_set_tuning(ftcg_plan p, int tile, int accum, int lds_copie
   if (tile != 0 && tile != 16 && tile != 32 && tile != 64 && tile != 128 && !(p->dim == 1 && is_pow2(tile)))
     return FTCG_EINVAL;
   if (tile != 0 && tile < 2 * p->W) return FTCG_EINVAL;
-  if (accum != FTCG_ACCUM_FIXED && accum != FTCG_ACCUM_F64 && accum != FTCG_ACCUM_MFMA) return FTCG_EINVAL;
+  if (accum != FTCG_ACCUM_FIXED && accum != FTCG_ACCUM_F64) return FTCG_EINVAL;
   if (lds_copies != 1 && lds_copies != 2 && lds_copies != 4) return FTCG_EINVAL;
   if (accum == FTCG_ACCUM_FIXED && (p->dtype != FTCG_F32 || lds_copies != 1)) return FTCG_EUNSUPPORTED;
-  if (accum == FTCG_ACCUM_MFMA &&
-      (p->dtype != FTCG_F32 || p->dim != 2 || lds_copies != 1 || (tile != 0 && tile != 64) || p->G < 64))
-    return FTCG_EUNSUPPORTED;
   if (accum == FTCG_ACCUM_F64 && p->dim == 2) {
     const int64_t t = tile ? tile : 64;
     if (t > 64 || (size_t)lds_copies * 2 * t * (t + 1) * sizeof(double) > 160 * 1024) return FTCG_EUNSUPPORTED;

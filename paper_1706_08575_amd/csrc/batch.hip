@@ -153,10 +153,7 @@ __global__ __launch_bounds__(BATCH_BLOCK) void k_spread_persistent(const BatchTa
           unsigned long long* dst = acc + (c0 - W + 1 + PAD) * TP + col;
 #pragma unroll
           for (int j = 0; j < L; ++j) {
-            const int ir = (int)pr, ii = (int)pi;
-            const unsigned hi = (unsigned)ii + (unsigned)(ir >> 31);
-            const unsigned long long packed = ((unsigned long long)hi << 32) | (unsigned)ir;
-            __hip_atomic_fetch_add(dst + j * TP, packed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(dst + j * TP, fx_pack(pr, pi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             pr *= q;
             pi *= q;
             q *= e2b;

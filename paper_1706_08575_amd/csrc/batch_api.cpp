@@ -146,6 +146,7 @@ ftcg_status ftcg_batch_create(ftcg_batch_s** out, int n_items, const int64_t* n,
   if (!out || !n) return FTCG_EINVAL;
   *out = nullptr;
   if (n_items < 1 || n_items > 4096) return FTCG_EINVAL;
+  if (wmode == FTCG_W_BAND) return FTCG_EUNSUPPORTED;   // batches apply diagonal weights only
   ftcg_batch_s* b = new (std::nothrow) ftcg_batch_s();
   if (!b) return FTCG_ENOMEM;
   b->stream = static_cast<hipStream_t>(hip_stream);
@@ -364,13 +365,14 @@ ftcg_status ftcg_batch_execute(ftcg_batch_s* b, const void* fhat_dev, void* imag
 ftcg_status ftcg_batch_info(ftcg_batch_s* b, int64_t* n_tasks, int64_t* n_split_tiles, int64_t* n_records,
                             int64_t* n_tiles) {
   if (!b) return FTCG_EINVAL;
-  int64_t r = 0;
-  for (ftcg_plan p : b->plans) r += plan_nrec(p);
-  if (n_tasks) *n_tasks = b->ntasks;
-  if (n_split_tiles) *n_split_tiles = b->nsplit;
-  if (n_records) *n_records = r;
-  if (n_tiles) *n_tiles = b->ntiles;
-  return FTCG_OK;
+  return guard([&] {
+    int64_t r = 0;
+    for (ftcg_plan p : b->plans) r += plan_nrec(p);   // may throw HipError (reads the device)
+    if (n_tasks) *n_tasks = b->ntasks;
+    if (n_split_tiles) *n_split_tiles = b->nsplit;
+    if (n_records) *n_records = r;
+    if (n_tiles) *n_tiles = b->ntiles;
+  });
 }
 
 ftcg_status ftcg_batch_enable_timing(ftcg_batch_s* b, int enable) {

@@ -458,9 +458,21 @@ void batch_fft(ftcg_batch_s* b) {
   FTCG_HIP(hipGetLastError());
 }
 
+// sizes, stream and tables of one grid-to-image transform (from a plan, or
+// from the allocation-free entry point's static scratch)
+struct FftCtx {
+  int dim;
+  int64_t n, G;
+  hipStream_t stream;
+  const void* tw;        // two-level twiddle tables of the G-th roots of unity
+  const double* deapod;  // n float64 factors 1 / Phi(x_p / sigma)
+  void* tmp;             // n x G intermediate (2D)
+  ftcg_plan timed;       // plan whose step timing records the passes (may be null)
+};
+
 template <class real>
 struct RowsLaunch {
-  ftcg_plan p;
+  const FftCtx* c;
   const void* in;
   int64_t in_row_stride;
   void* out;
@@ -472,7 +484,7 @@ struct RowsLaunch {
   template <int RB, int RC, int MAXQ, int PPT>
   void operator()() const {
     using cx = typename CxF<real>::t;
-    const int L = (int)p->G;
+    const int L = (int)c->G;
     int log2L = 0;
     while ((1 << log2L) < L) ++log2L;
     const size_t lds = ((size_t)RC * padded_len(L) + 64 + std::max(1, L >> 6)) * sizeof(cx);
@@ -482,45 +494,56 @@ struct RowsLaunch {
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
       attr_done = true;
     }
-    const int ncrop = (int)p->n;
-    const int crop_off = (int)((p->G - p->n) / 2);
+    const int ncrop = (int)c->n;
+    const int crop_off = (int)((c->G - c->n) / 2);
     hipLaunchKernelGGL((k_fft_rows<real, RB, RC, MAXQ, PPT>), dim3((unsigned)(rows / RB)), dim3(f.nts * RC), lds,
-                       p->stream, static_cast<const cx*>(in), in_row_stride, static_cast<cx*>(out), out_stride_q, L,
-                       log2L, ncrop, crop_off, rows, pre_sign, dq, drow, p->twiddle.as<cx>(), log2L);
+                       c->stream, static_cast<const cx*>(in), in_row_stride, static_cast<cx*>(out), out_stride_q, L,
+                       log2L, ncrop, crop_off, rows, pre_sign, dq, drow, static_cast<const cx*>(c->tw), log2L);
     FTCG_HIP(hipGetLastError());
   }
 };
 
 template <class real>
-static void launch_rows(ftcg_plan p, const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q,
+static void launch_rows(const FftCtx& c, const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q,
                         int rows, int pre_sign, const double* dq, const double* drow) {
-  const FftShape f = fft_shape(p->G, p->n, rows, (int)sizeof(typename CxF<real>::t));
-  dispatch_shape(f, RowsLaunch<real>{p, in, in_row_stride, out, out_stride_q, rows, pre_sign, f, dq, drow});
+  const FftShape f = fft_shape(c.G, c.n, rows, (int)sizeof(typename CxF<real>::t));
+  dispatch_shape(f, RowsLaunch<real>{&c, in, in_row_stride, out, out_stride_q, rows, pre_sign, f, dq, drow});
 }
 
 template <class real>
-static void grid_to_image_t(ftcg_plan p, const void* grid, void* image) {
-  const double* d = p->deapod.as<double>();
-  const int64_t G = p->G, n = p->n;
-  if (p->dim == 1) {
-    timing_begin(p, STEP_FFT2);
-    launch_rows<real>(p, grid, G, image, 1, 1, 1, d, nullptr);
-    timing_end(p, STEP_FFT2);
+static void grid_to_image_t(const FftCtx& c, const void* grid, void* image) {
+  const double* d = c.deapod;
+  const int64_t G = c.G, n = c.n;
+  ftcg_plan tp = c.timed;
+  if (c.dim == 1) {
+    if (tp) timing_begin(tp, STEP_FFT2);
+    launch_rows<real>(c, grid, G, image, 1, 1, 1, d, nullptr);
+    if (tp) timing_end(tp, STEP_FFT2);
     return;
   }
-  timing_begin(p, STEP_FFT1);
-  launch_rows<real>(p, grid, G, p->fft_tmp.p, G, (int)G, 1, nullptr, nullptr);
-  timing_end(p, STEP_FFT1);
-  timing_begin(p, STEP_FFT2);
-  launch_rows<real>(p, p->fft_tmp.p, G, image, n, (int)n, 0, d, d);
-  timing_end(p, STEP_FFT2);
+  if (tp) timing_begin(tp, STEP_FFT1);
+  launch_rows<real>(c, grid, G, c.tmp, G, (int)G, 1, nullptr, nullptr);
+  if (tp) timing_end(tp, STEP_FFT1);
+  if (tp) timing_begin(tp, STEP_FFT2);
+  launch_rows<real>(c, c.tmp, G, image, n, (int)n, 0, d, d);
+  if (tp) timing_end(tp, STEP_FFT2);
+}
+
+void grid_to_image_raw(int dim, int64_t n, int64_t G, bool f64, hipStream_t stream, const void* tw,
+                       const double* deapod, void* tmp, const void* grid, void* image) {
+  const FftCtx c{dim, n, G, stream, tw, deapod, tmp, nullptr};
+  if (f64)
+    grid_to_image_t<double>(c, grid, image);
+  else
+    grid_to_image_t<float>(c, grid, image);
 }
 
 void grid_to_image(ftcg_plan p, const void* grid, void* image) {
+  const FftCtx c{p->dim, p->n, p->G, p->stream, p->twiddle.p, p->deapod.as<double>(), p->fft_tmp.p, p};
   if (p->dtype == FTCG_F64)
-    grid_to_image_t<double>(p, grid, image);
+    grid_to_image_t<double>(c, grid, image);
   else
-    grid_to_image_t<float>(p, grid, image);
+    grid_to_image_t<float>(c, grid, image);
 }
 
 // deapodization factors 1 / Phi(x_p / sigma), Phi(t) = sqrt(pi/beta) exp(-pi^2 t^2 / beta), float64
@@ -557,10 +580,11 @@ void compute_twiddles(void* tw, int64_t L, bool f64, hipStream_t s) {
   FTCG_HIP(hipGetLastError());
 }
 
-void compute_deapod(ftcg_plan p) {
-  hipLaunchKernelGGL(k_deapod, dim3((unsigned)((p->n + 255) / 256)), dim3(256), 0, p->stream,
-                     p->deapod.as<double>(), p->n, p->sigma, p->beta);
+void compute_deapod_raw(double* d, int64_t n, double sigma, double beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_deapod, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d, n, sigma, beta);
   FTCG_HIP(hipGetLastError());
 }
+
+void compute_deapod(ftcg_plan p) { compute_deapod_raw(p->deapod.as<double>(), p->n, p->sigma, p->beta, p->stream); }
 
 }  // namespace ftcg

@@ -94,6 +94,21 @@ constexpr double WPI = 3.141592653589793238462643383279502884;
 template <int DIM>
 constexpr double wscale() { return DIM == 1 ? WPI * WPI : WPI * WPI * WPI * WPI; }
 
+// Determinism of the frame-weight sums. Every term (pi^DIM T_in)^2 <= pi^4
+// that enters a sum is rounded to a multiple of 2^-36 (one fused
+// multiply-add against 1.5 * 2^16, whose neighbours are 2^-36 apart, then the
+// exact subtraction of that constant), and so is the self term. Sums of such
+// multiples are exact while they stay below 2^17 (sum T^2 below about 1300 in
+// 2D and 13000 in 1D, far above any raster's density), so the order in which
+// lanes, LDS atomics and global atomics add them does not change a bit: the
+// weights are bitwise reproducible although the kernels add with atomics.
+// The rounding moves each term by at most 2^-37 absolutely, about 1e-13 of
+// the sum, which always holds the self term pi^DIM.
+constexpr double WQ_MAGIC = 98304.0;   // 1.5 * 2^16
+__device__ inline double wq_square(double q) { return fma(q, q, WQ_MAGIC) - WQ_MAGIC; }
+template <int DIM>
+constexpr double wself() { return (wscale<DIM>() + WQ_MAGIC) - WQ_MAGIC; }
+
 // the input check reduced on the device: bounding box, the neighbour-bin
 // geometry derived from it, and whether the points are rejected
 struct CheckOut {
@@ -111,7 +126,21 @@ struct WSample {
 };
 
 // tile accumulation of float32 plans
-enum Accum { ACCUM_FIXED = 0, ACCUM_F64 = 1, ACCUM_MFMA = 2 };
+enum Accum { ACCUM_FIXED = 0, ACCUM_F64 = 1 };
+
+// One fixed-point tap of the float32 spreading kernels: the scaled
+// components rounded to the nearest integer (v_cvt_rpi_i32_f32 computes
+// floor(x + 1/2); truncation toward zero would bias every tap by half a
+// quantum against its sign, which adds up over the thousands of taps a cell
+// of a dense tile receives) and packed as im * 2^32 + re in two's
+// complement, so that one 64-bit integer add accumulates both exactly.
+__device__ inline unsigned long long fx_pack(float pr, float pi) {
+  int ir, ii;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(ir) : "v"(pr));
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(ii) : "v"(pi));
+  const unsigned hi = (unsigned)ii + (unsigned)(ir >> 31);
+  return ((unsigned long long)hi << 32) | (unsigned)ir;
+}
 
 enum Step {
   STEP_BIN = 0,      // input check + tile binning of spread records
@@ -122,7 +151,11 @@ enum Step {
   STEP_WBIN = 5,     // neighbour binning for the weight sum
   STEP_LEARNED = 6,  // fused 16-NN + MLP inference
   STEP_AUDIT = 7,    // audit of learned weights against plain ones
-  N_STEPS = 8
+  STEP_WFINISH = 8,  // weights from the sums of the symmetric kernel (and their preset)
+  STEP_BAND_GRAM = 9,    // banded C: the band of T^2
+  STEP_BAND_SOLVE = 10,  // banded C: per-column normal equations
+  STEP_BAND_APPLY = 11,  // c = C fhat ahead of the spread
+  N_STEPS = 16       // entries of the timing arrays (steps 12..15 unused)
 };
 
 // per-step HIP event pairs recorded on the plan's stream; resolved (and
@@ -248,6 +281,14 @@ struct ftcg_plan_s {
   bool have_wbins = false;
   bool weights_only = false;  // internal plans that only compute weights (no tile binning)
 
+  // banded coefficient matrix C (FTCG_W_BAND)
+  int band_r = 1;             // band half-width r: 2r - 1 entries per column
+  int band_bad = 0;           // columns whose normal equations broke down (last set_points)
+  ftcg::DevBuf band_P;        // m x (2r-1): pi^(2 dim) (T^2)_{a, a+e}
+  ftcg::DevBuf band_col;      // m x (2r-1): C[n - r + 1 + p, n] (column form)
+  ftcg::DevBuf band_row;      // m x (2r-1): C[i, i + e - r + 1] (row form, for the apply)
+  ftcg::DevBuf band_c;        // m complex: C fhat of the last execute
+
   // learned weights
   struct ftcg_mlp_s* mlp = nullptr;
   double audit_threshold = 1e-4;
@@ -304,9 +345,15 @@ void finish_deferred_weights(ftcg_plan p);          // no-op unless p->weights_d
 // plain weights of the samples idx[0..n) (caller indices) into out[0..n)
 void plain_weights_at(ftcg_plan p, const double* k, const int32_t* idx, int64_t n, double* out);
 void fill_ones(double* a, int64_t m, hipStream_t s);
+void run_band_weights(ftcg_plan p);                 // banded C from the neighbour bins (FTCG_W_BAND)
+void band_apply(ftcg_plan p, const void* fhat);     // p->band_c = C fhat
 void spread(ftcg_plan p, const void* fhat, void* grid);
 void grid_to_image(ftcg_plan p, const void* grid, void* image);
 void compute_deapod(ftcg_plan p);
+void compute_deapod_raw(double* d, int64_t n, double sigma, double beta, hipStream_t s);
+// the transform of grid_to_image with explicit sizes, tables and intermediate
+void grid_to_image_raw(int dim, int64_t n, int64_t G, bool f64, hipStream_t stream, const void* tw,
+                       const double* deapod, void* tmp, const void* grid, void* image);
 // two-level twiddle tables of the L-th roots of unity (float2, or double2 when f64)
 int64_t twiddle_entries(int64_t L);
 void compute_twiddles(void* tw, int64_t L, bool f64, hipStream_t s);

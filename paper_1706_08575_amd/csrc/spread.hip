@@ -10,17 +10,17 @@
 // Lane layout (2D): a wavefront takes 64 / (2W) records at a time (5 for
 // W = 6); within a record, lane i owns footprint column i and walks the 2W
 // rows. The row kernel values follow the recursion
-//   e^{-beta (d+1)^2} = e^{-beta d^2} * q,  q_{next} = q * e^{-2 beta},
-// so each tap costs three multiplies and two LDS float atomics.
+//   e^{-beta (d+1)^2} = e^{-beta d^2} * q,  q_{next} = q * e^{-2 beta}.
 //
-// The tile accumulates in float64 LDS words with ds_add_f64 for both value
-// precisions: on gfx950 the float32 LDS atomic add retires about 0.33 lanes
-// per clock per CU, the float64 one about 7.6 (measured), so float64
-// accumulation is both the faster and the more accurate choice. Tap values
-// are formed in the plan's precision and widened before the add.
-//
-// With lds_copies > 1, wave w accumulates into partial tile w % copies and the
-// partial tiles are combined at the flush with compensated (TwoSum) addition.
+// Two accumulations:
+//   * float32 plans (k_spread2d_fx, the default): exact fixed-point integers,
+//     one 64-bit LDS integer add per complex tap (see the block comment of
+//     that kernel); on gfx950 the float32 LDS atomic add retires about 0.33
+//     lanes per clock per CU and the 64-bit integer one about 9.9 (measured);
+//   * float64 plans, and float32 plans that ask for it (k_spread2d,
+//     k_spread1d): float64 LDS words with ds_add_f64; with lds_copies > 1
+//     wave w accumulates into partial tile w % copies and the partial tiles
+//     are combined at the flush with compensated (TwoSum) addition.
 #include <type_traits>
 
 #include "ftcg_internal.h"
@@ -143,14 +143,15 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d(const Rec<real>* __re
 // Each tap value x (complex) is scaled by s = (2^31 - 2^24) / B_t, where B_t >=
 // sum over the tile's records of max(|Re c_r|, |Im c_r|) bounds every cell of
 // the tile (kernel values never exceed 1; B_t is formed from order-independent
-// reductions, so it is the same for any record order), truncated to int32 per
-// component,
-// and both components are added with ONE 64-bit LDS integer atomic: the pair
-// (re, im) is packed as im * 2^32 + re in two's complement, and integer
-// addition of packed pairs adds both components exactly as long as neither
-// sum leaves int32, which the bound guarantees. The accumulation is therefore
-// exact and independent of record order (bitwise reproducible), and its only
-// error is the truncation of each tap to 2^-31 B_t.
+// reductions, so it is the same for any record order), rounded to the nearest
+// int32 per component (fx_pack), and both components are added with ONE
+// 64-bit LDS integer atomic: the pair (re, im) is packed as im * 2^32 + re in
+// two's complement, and integer addition of packed pairs adds both components
+// exactly as long as neither sum leaves int32, which the bound guarantees (its
+// 2^24 quanta of headroom also cover the half quantum each rounding may add).
+// The accumulation is therefore exact and independent of record order
+// (bitwise reproducible), and its only error is the rounding of each tap to
+// the quantum 2^-31 B_t: unbiased, at most half a quantum per tap.
 //
 // The LDS tile carries 2W - 1 halo rows above and below, so the 2W rows of a
 // record's footprint never need a bounds check (halo rows are dropped at the
@@ -283,10 +284,7 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
     unsigned long long* dst = acc + (c0 - W + 1 + PAD) * TP + col;
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-      const int ir = (int)pr, ii = (int)pi;   // truncation toward zero
-      const unsigned hi = (unsigned)ii + (unsigned)(ir >> 31);
-      const unsigned long long packed = ((unsigned long long)hi << 32) | (unsigned)ir;
-      __hip_atomic_fetch_add(dst + j * TP, packed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(dst + j * TP, fx_pack(pr, pi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       pr *= q;
       pi *= q;
       q *= e2b;
@@ -333,163 +331,6 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
     o.y = (float)im * unscale;
     out[(int64_t)row * G + col] = o;
   }
-}
-
-// ---------------------------------------------------------------------------
-// float32 plans, matrix-core tile accumulation (FTCG_ACCUM_MFMA, tile 64)
-//
-// A 16 x 16 block of the tile is a sum of rank-one terms over the records r
-// that reach it: H[rb + i][cb + j] = sum_r (c_r a_r(i)) b_r(j), with the row
-// taps a_r(i) = exp(-beta (rb + i - u_r0)^2), the column taps
-// b_r(j) = exp(-beta (cb + j - u_r1)^2) and c_r = alpha_r fhat_r (complex).
-// Four records at a time form the 16 x 4 and 4 x 16 operands of
-// v_mfma_f32_16x16x4_f32 (float32 products, float32 accumulation), one
-// product for the real and one for the imaginary part; lane l supplies row
-// (column) l % 16 of record l / 16. Each record keeps the kernel's 2W taps per
-// axis, cells floor(u) - W + 1 .. floor(u) + W, as the LDS-atomic paths do.
-//
-// Workgroup = one 64 x 64 tile, 4 wavefronts; wavefront w owns block column
-// cb = 16 w and its four blocks. The tile's records pass through LDS in chunks
-// of SPM_NR; staging a chunk forms every record's 2W row and 2W column taps
-// once (exp recurrence, three multiplies per tap) next to its value c. Each
-// wavefront then lists (ballot compaction) the records that reach its column
-// and, per block, those that reach the block's rows; a list entry carries the
-// record and its tile-local cells, so the product loop reads the entry, then
-// the two taps (or a zero word outside the footprint) and c. The blocks stay
-// in accumulator registers across chunks and are stored once, 16 consecutive
-// cells per row segment.
-// ---------------------------------------------------------------------------
-
-constexpr int SPM_NR = 256;   // records per LDS chunk (one per thread)
-
-__device__ inline unsigned lanes_below(unsigned long long mask) {
-  return (unsigned)__popcll(mask & ((1ull << __lane_id()) - 1ull));
-}
-
-template <int W>
-__global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_mfma(const Rec<float>* __restrict__ recs,
-                                                                const float* __restrict__ alpha_s,
-                                                                const int32_t* __restrict__ tile_off,
-                                                                const float2* __restrict__ fhat,
-                                                                float2* __restrict__ grid, int64_t G, int nt,
-                                                                float beta) {
-  static_assert(SPM_NR == SPREAD_BLOCK, "one staged record per thread");
-  constexpr int T = 64;
-  constexpr int L = 2 * W;
-  constexpr int STRIDE = 2 * L + 2;          // row taps, column taps, Re c, Im c
-  constexpr int ZERO = SPM_NR * STRIDE;      // a word that holds 0
-  __shared__ float stap[SPM_NR * STRIDE + 1];
-  __shared__ int32_t scell[SPM_NR];          // tile-local cells, c0 | c1 << 16
-  __shared__ uint32_t clist[4][SPM_NR];      // per wavefront: records reaching its block column
-  __shared__ uint32_t blist[4][SPM_NR];      // per wavefront: records reaching the current block
-
-  const int tile = blockIdx.x;
-  const int t0 = tile / nt, t1 = tile - (tile / nt) * nt;
-  const int beg = tile_off[tile], end = tile_off[tile + 1];
-  float2* out = grid + (int64_t)t0 * T * G + (int64_t)t1 * T;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int cb = 16 * wave;
-  const int li = lane & 15, lk = lane >> 4;
-  const float e2b = __expf(-2.f * beta);
-  if (tid == 0) stap[ZERO] = 0.f;
-
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  f4 acc_re[4], acc_im[4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    acc_re[b] = f4{0.f, 0.f, 0.f, 0.f};
-    acc_im[b] = f4{0.f, 0.f, 0.f, 0.f};
-  }
-
-  for (int q0 = beg; q0 < end; q0 += SPM_NR) {
-    const int n = min(SPM_NR, end - q0);
-    __syncthreads();  // the previous chunk has been consumed
-    if (tid < n) {
-      const Rec<float> rec = recs[q0 + tid];
-      const float a = alpha_s[q0 + tid];
-      const float2 v = fhat[rec.src];
-      float* t = stap + tid * STRIDE;
-      const float d0 = (float)(1 - W) - rec.f0, d1 = (float)(1 - W) - rec.f1;
-      float w0 = __expf(-beta * d0 * d0), p0 = __expf(-beta * (2.f * d0 + 1.f));
-      float w1 = __expf(-beta * d1 * d1), p1 = __expf(-beta * (2.f * d1 + 1.f));
-#pragma unroll
-      for (int j = 0; j < L; ++j) {
-        t[j] = w0;
-        t[L + j] = w1;
-        w0 *= p0;
-        p0 *= e2b;
-        w1 *= p1;
-        p1 *= e2b;
-      }
-      t[2 * L] = v.x * a;
-      t[2 * L + 1] = v.y * a;
-      scell[tid] = rec.c01;
-    }
-    __syncthreads();
-    // records whose 2W columns c1 - W + 1 .. c1 + W meet cb .. cb + 15
-    int ncol = 0;
-    for (int base = 0; base < n; base += 64) {
-      const int r = base + lane;
-      bool hit = false;
-      uint32_t e = 0;
-      if (r < n) {
-        const int cell = scell[r];
-        const int c0 = (int)(int16_t)(cell & 0xffff), c1 = cell >> 16;
-        hit = c1 + W >= cb && c1 - W + 1 <= cb + 15;
-        // entry: record | (c0 + 128) << 16 | (c1 + 128) << 24 (cells lie in -W .. T + W)
-        e = (uint32_t)r | ((uint32_t)(c0 + 128) << 16) | ((uint32_t)(c1 + 128) << 24);
-      }
-      const unsigned long long mk = __ballot(hit);
-      if (hit) clist[wave][ncol + lanes_below(mk)] = e;
-      ncol += __popcll(mk);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
-      const int rb = 16 * bi;
-      int nb = 0;
-      for (int base = 0; base < ncol; base += 64) {
-        const int q = base + lane;
-        bool hit = false;
-        uint32_t e = 0;
-        if (q < ncol) {
-          e = clist[wave][q];
-          const int c0 = (int)((e >> 16) & 0xff) - 128;
-          hit = c0 + W >= rb && c0 - W + 1 <= rb + 15;
-        }
-        const unsigned long long mk = __ballot(hit);
-        if (hit) blist[wave][nb + lanes_below(mk)] = e;
-        nb += __popcll(mk);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      // tap index of row rb + li (column cb + li) in a record with cell c: rb + li - c + W - 1
-      const int ri = rb + li + W - 1 + 128, ci = cb + li + W - 1 + 128;
-      for (int s0 = 0; s0 < nb; s0 += 4) {
-        const int k = s0 + lk;
-        int ia = ZERO, ib = ZERO, ire = ZERO, iim = ZERO;   // ZERO: past the list, or off the footprint
-        if (k < nb) {
-          const uint32_t e = blist[wave][k];
-          const int r = (int)(e & 0xffff);
-          const int ja = ri - (int)((e >> 16) & 0xff), jb = ci - (int)(e >> 24);
-          ia = (unsigned)ja < (unsigned)L ? r * STRIDE + ja : ZERO;
-          ib = (unsigned)jb < (unsigned)L ? r * STRIDE + L + jb : ZERO;
-          ire = r * STRIDE + 2 * L;
-          iim = ire + 1;
-        }
-        const float av = stap[ia], bv = stap[ib], cre = stap[ire], cim = stap[iim];
-        acc_re[bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av * cre, bv, acc_re[bi], 0, 0, 0);
-        acc_im[bi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av * cim, bv, acc_im[bi], 0, 0, 0);
-      }
-    }
-  }
-  // block (bi, wave): lane l holds rows 4 (l / 16) + e, column l % 16
-#pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int row = 16 * bi + 4 * lk + e;
-      out[(int64_t)row * G + cb + li] = make_float2(acc_re[bi][e], acc_im[bi][e]);
-    }
 }
 
 // 1D: one thread per record walks its 2W taps
@@ -578,15 +419,6 @@ static void launch_spread_w(ftcg_plan p, const void* fhat, void* grid) {
     return;
   }
   finish_deferred_weights(p);          // the other kernels read the records' weights
-  if (std::is_same<real, float>::value && p->dim == 2 && p->accum == ACCUM_MFMA) {
-    if (T != 64) throw StatusError{FTCG_EUNSUPPORTED};
-    hipLaunchKernelGGL((k_spread2d_mfma<W>), dim3((unsigned)p->ntiles), dim3(SPREAD_BLOCK), 0, p->stream,
-                       p->recs.as<Rec<float>>(), p->alpha_s.as<float>(), p->tile_off.as<int32_t>(),
-                       static_cast<const float2*>(fhat), static_cast<float2*>(grid), p->G, (int)p->nt,
-                       (float)p->beta);
-    FTCG_HIP(hipGetLastError());
-    return;
-  }
   const real beta = (real)p->beta;
   const int copies = p->lds_copies;
   if (p->dim == 2) {

@@ -107,12 +107,11 @@ __device__ inline double pair_term(const WSample<DIM>& o, const double* x, const
   return __hiloint2double(hi, __double2loint(q));
 }
 
-// acc + (pi^DIM T_in)^2, the square fused into the sum
+// acc + (pi^DIM T_in)^2, the square rounded to the sums' quantum (wq_square)
 template <int DIM>
 __device__ inline double pair_add(double acc, const WSample<DIM>& o, const double* x, const double* sn,
                                   const double* cs, double R) {
-  const double q = pair_term<DIM>(o, x, sn, cs, R);
-  return fma(q, q, acc);
+  return acc + wq_square(pair_term<DIM>(o, x, sn, cs, R));
 }
 
 // a candidate record; 2D records (48 bytes) sit in 16-byte aligned arrays
@@ -309,7 +308,7 @@ __device__ inline void sym_pair(double (&acc)[WT], double* cacc, int p, int i, c
   for (int u = 0; u < WT; ++u) {
     const double q = pair_term<2>(o, x[u], sn[u], cs[u], R);
     // (one sample per lane: its range already starts after first[0])
-    const double q2 = (WT == 1 || i > first[u]) ? q * q : 0.0;
+    const double q2 = (WT == 1 || i > first[u]) ? wq_square(q) : 0.0;
     acc[u] += q2;
     csum += q2;
   }
@@ -789,7 +788,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_
           ss[rs + q] = smp;
           sidx[rs + q] = r[u].j;
           if (inv) inv[r[u].j] = rs + q;
-          if (sums) sums[rs + q] = wscale<2>();   // the self term
+          if (sums) sums[rs + q] = wself<2>();   // the self term
         }
       }
     }
@@ -806,7 +805,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_sort(WBinGeom g, const int32_
     ss[pos] = smp;
     sidx[pos] = r.j;
     if (inv) inv[r.j] = pos;
-    if (sums) sums[pos] = wscale<2>();
+    if (sums) sums[pos] = wself<2>();
   }
 }
 
@@ -845,7 +844,7 @@ void sort_weight_rows(ftcg_plan p) {
   const WBinGeom& g = p->wgeom;
   // the inverse map serves the learned features, the audit and the
   // record-order weights written by the finish of the weight sum
-  const bool need_inv = p->wmode == FTCG_W_LEARNED || p->weights_only || p->finish_recs;
+  const bool need_inv = p->wmode == FTCG_W_LEARNED || p->wmode == FTCG_W_BAND || p->weights_only || p->finish_recs;
   // the symmetric weight sum starts from the self terms, preset here
   p->ws_sum.ensure(sizeof(double) * p->m);
   hipLaunchKernelGGL(k_wrow_sort, dim3((unsigned)g.nb[0]), dim3(WB_BLOCK), 0, p->stream, g,
@@ -903,23 +902,31 @@ static void launch_weights_sym(ftcg_plan p) {
   const int64_t m = p->m;
   double* wsum = p->ws_sum.as<double>();
   if (!p->ws_sum_fresh) {   // sums already used: start again from the self terms
+    timing_begin(p, STEP_WFINISH);
     hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((m + WB_BLOCK - 1) / WB_BLOCK)), dim3(WB_BLOCK), 0, p->stream,
-                       wsum, m, wscale<2>());
+                       wsum, m, wself<2>());
+    timing_end(p, STEP_WFINISH);
   }
   p->ws_sum_fresh = false;
   const int64_t runs = (m * S + WB_BLOCK * WT - 1) / (WB_BLOCK * WT);
   const int cx = (int)std::max<int64_t>(1, (2 * runs + g.nb[0] - 1) / g.nb[0]);
   const int64_t nb = (int64_t)cx * g.nb[0];
   const int chunk = cx * std::max(1, g.nb[0] / 64);
+  // the weight step times this kernel alone (its launch is what the
+  // roofline of the weight sum is measured on)
+  timing_begin(p, STEP_WEIGHTS);
   hipLaunchKernelGGL((k_frame_weights_sym<WT, S>), dim3((unsigned)nb), dim3(WB_BLOCK), 0, p->stream,
                      p->ws_k.as<WSample<2>>(), p->wb_off.as<int32_t>(), g, cx, chunk, wsum);
+  timing_end(p, STEP_WEIGHTS);
   if (p->finish_recs) {   // finished on demand (finish_deferred_weights) or inside the spread
     p->weights_deferred = true;
     p->finish_recs = false;
     return;
   }
+  timing_begin(p, STEP_WFINISH);
   hipLaunchKernelGGL(k_weights_from_sums, dim3((unsigned)((m + WB_BLOCK - 1) / WB_BLOCK)), dim3(WB_BLOCK), 0,
                      p->stream, wsum, p->ws_idx.as<int32_t>(), m, p->alpha.as<double>());
+  timing_end(p, STEP_WFINISH);
 }
 
 template <int WT>
@@ -941,6 +948,7 @@ static void launch_weights_1d(ftcg_plan p) {
 
 void finish_deferred_weights(ftcg_plan p) {
   if (!p->weights_deferred) return;
+  timing_begin(p, STEP_WFINISH);
   const int64_t m = p->m;
   const double* wsum = p->ws_sum.as<double>();
   const unsigned fb = (unsigned)std::min<int64_t>(2048, (2 * m + WB_BLOCK - 1) / WB_BLOCK);
@@ -954,6 +962,7 @@ void finish_deferred_weights(ftcg_plan p) {
                        p->ws_idx.as<int32_t>(), p->ws_inv.as<int32_t>(), m, p->alpha.as<double>(),
                        p->recs.as<Rec<float>>(), nrec, p->alpha_s.as<float>());
   FTCG_HIP(hipGetLastError());
+  timing_end(p, STEP_WFINISH);
   p->weights_deferred = false;
 }
 
@@ -966,7 +975,6 @@ constexpr bool WEIGHT_SYMMETRIC = true;
 constexpr int SYM_MAX_WT = 2;   // samples per lane the symmetric kernel is built for
 
 void run_plain_weights(ftcg_plan p) {
-  timing_begin(p, STEP_WEIGHTS);
   const int wt = p->w_samples ? p->w_samples : (p->dim == 2 && p->m >= (int64_t(1) << 20) ? 2 : 1);
   if (p->dim == 2) {
     // lanes per sample group: the plan's tuning, else 4 below 2^21 samples
@@ -988,15 +996,16 @@ void run_plain_weights(ftcg_plan p) {
         default: launch_weights_sym<2, 4>(p); break;
       }
       FTCG_HIP(hipGetLastError());
-      timing_end(p, STEP_WEIGHTS);
       return;
     }
+    timing_begin(p, STEP_WEIGHTS);
     switch (wt) {
       case 1: launch_weights_rows_s<1>(p, S); break;
       case 2: launch_weights_rows_s<2>(p, S); break;
       default: launch_weights_rows_s<4>(p, S); break;
     }
   } else {
+    timing_begin(p, STEP_WEIGHTS);
     switch (wt) {
       case 1: launch_weights_1d<1>(p); break;
       case 2: launch_weights_1d<2>(p); break;

@@ -40,7 +40,7 @@ class Plan:
         self.n, self.dim, self.W, self.sigma, self.R = int(n), int(dim), int(W), float(sigma), float(R)
         self.dtype = {"f32": L.FTCG_F32, "f64": L.FTCG_F64}[dtype]
         self.wmode = {"plain": L.FTCG_W_PLAIN, "learned": L.FTCG_W_LEARNED, "user": L.FTCG_W_USER,
-                      "none": L.FTCG_W_NONE}[weights]
+                      "none": L.FTCG_W_NONE, "band": L.FTCG_W_BAND}[weights]
         self.cdtype = torch.complex64 if self.dtype == L.FTCG_F32 else torch.complex128
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream
@@ -90,6 +90,20 @@ class Plan:
         self.used_fallback = bool(fb.value)
         return out
 
+    def set_band(self, r: int) -> None:
+        """Band half-width r of a weights="band" plan (applies from the next set_points)."""
+        L.check(L.call("ftcg_plan_set_band", self._h, int(r)), "ftcg_plan_set_band")
+        self.band_r = int(r)
+
+    def get_band(self) -> torch.Tensor:
+        """Banded C by columns: (m, 2r - 1) float64, [n, p] = C[n - r + 1 + p, n]."""
+        r = C.c_int(0)
+        nb = 2 * getattr(self, "band_r", 1) - 1
+        out = torch.empty((self.m, nb), dtype=torch.float64, device=self.device)
+        L.check(L.call("ftcg_get_band", self._h, C.c_void_p(_dptr(out, torch.float64, self.m * nb, "band")),
+                       C.byref(r)), "ftcg_get_band")
+        return out
+
     def execute(self, fhat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:
             out = torch.empty((self.n,) * self.dim, dtype=self.cdtype, device=self.device)
@@ -122,11 +136,10 @@ class Plan:
 
     def set_tuning(self, tile: int = 0, accum: str | None = None, lds_copies: int = 1) -> None:
         """tile: 0 (automatic) or 16/32/64/128; accum: "fixed" (float32 plans'
-        default), "f64" or "mfma" (2D float32, tile 64); lds_copies: partial
-        tiles for "f64"."""
+        default) or "f64"; lds_copies: partial tiles for "f64"."""
         if accum is None:
             accum = "fixed" if self.dtype == L.FTCG_F32 else "f64"
-        a = {"fixed": L.FTCG_ACCUM_FIXED, "f64": L.FTCG_ACCUM_F64, "mfma": L.FTCG_ACCUM_MFMA}[accum]
+        a = {"fixed": L.FTCG_ACCUM_FIXED, "f64": L.FTCG_ACCUM_F64}[accum]
         L.check(L.call("ftcg_plan_set_tuning", self._h, int(tile), a, int(lds_copies)), "ftcg_plan_set_tuning")
 
     def set_weight_tuning(self, samples_per_lane: int = 0, lanes_per_group: int = 0) -> None:
@@ -152,7 +165,7 @@ class Plan:
         L.check(L.call("ftcg_plan_enable_timing", self._h, 1 if on else 0), "ftcg_plan_enable_timing")
 
     def timing(self) -> dict:
-        ms = (C.c_double * 8)()
-        cnt = (C.c_int64 * 8)()
+        ms = (C.c_double * L.TIMING_STEPS)()
+        cnt = (C.c_int64 * L.TIMING_STEPS)()
         L.check(L.call("ftcg_plan_timing", self._h, ms, cnt), "ftcg_plan_timing")
-        return {L.STEP_NAMES[i]: (ms[i], cnt[i]) for i in range(8) if cnt[i]}
+        return {L.STEP_NAMES[i]: (ms[i], cnt[i]) for i in range(L.TIMING_STEPS) if cnt[i]}
