@@ -14,5 +14,6 @@ of arXiv:1706.08575).
 from .ftcg_ref import (  # noqa: F401
     kernel_beta, grid_size, pixel_coords, nudft, nudft_at, frame_weights,
     frame_weights_at, spread, spread_window, grid_to_image, deapod_factors, ftcg_image, rel_l2,
+    nudft_forward, image_to_grid, interpolate, forward,
 )
 from .band_ref import band_columns, band_dense, band_apply  # noqa: F401,E402

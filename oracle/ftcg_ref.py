@@ -266,3 +266,77 @@ def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:
     a = np.asarray(a, dtype=np.complex128)
     ref = np.asarray(ref, dtype=np.complex128)
     return float(np.linalg.norm((a - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+# ----------------------------------------------------------------------------
+# the forward (type-2) transform: uniform image -> values at the raster, the
+# adjoint of the reconstruction above (Omega^T of eq:cgmatrix after the
+# forward DFT of the deapodized, zero-padded image)
+# ----------------------------------------------------------------------------
+
+def nudft_forward(k: np.ndarray, image: np.ndarray, chunk: int = 4096) -> np.ndarray:
+    """fhat_j = sum_p I[p] exp(-2 pi i k_j . x_p): the analysis sum at the raster
+    (the data model fhat(lambda) = <f, phi_lambda> of Sec. III-B sampled on
+    the pixel grid), direct, in chunks of samples."""
+    k = np.asarray(k, dtype=np.float64)
+    image = np.asarray(image, dtype=np.complex128)
+    d = k.shape[1]
+    n = image.shape[0]
+    x = pixel_coords(n)
+    out = np.zeros(k.shape[0], dtype=np.complex128)
+    for b in range(0, k.shape[0], chunk):
+        e0 = np.exp(-2j * np.pi * np.outer(k[b:b + chunk, 0], x))
+        if d == 1:
+            out[b:b + chunk] = e0 @ image
+        else:
+            e1 = np.exp(-2j * np.pi * np.outer(k[b:b + chunk, 1], x))
+            out[b:b + chunk] = np.einsum("jp,pq,jq->j", e0, image, e1)
+    return out
+
+
+def image_to_grid(image: np.ndarray, n: int, sigma: float = 2.0, W: int = 6, workers: int = 1) -> np.ndarray:
+    """Adjoint of grid_to_image: multiply by the deapodization factors,
+    zero-pad to the centred n^d window of the G^d grid, then
+    H[g] = sum_q J[q] exp(-2 pi i (g - G/2).(q - G/2) / G) (an unnormalised
+    forward DFT, scipy.fft in float64)."""
+    image = np.asarray(image, dtype=np.complex128)
+    d = image.ndim
+    G = grid_size(n, sigma)
+    f = deapod_factors(n, sigma, W)
+    o = (G - n) // 2
+    J = np.zeros((G,) * d, dtype=np.complex128)
+    if d == 1:
+        J[o:o + n] = image * f
+    else:
+        J[o:o + n, o:o + n] = image * f[:, None] * f[None, :]
+    axes = tuple(range(d))
+    return scipy.fft.fftshift(scipy.fft.fftn(scipy.fft.ifftshift(J, axes=axes), axes=axes, workers=workers),
+                              axes=axes)
+
+
+def interpolate(k: np.ndarray, H: np.ndarray, sigma: float = 2.0, W: int = 6, chunk: int = 1 << 14) -> np.ndarray:
+    """fhat_j = sum over the taps g of sample j of H[g mod G] prod_a exp(-beta (g_a - u_ja)^2),
+    the same taps as spread() (Omega^T)."""
+    k = np.asarray(k, dtype=np.float64)
+    d = k.shape[1]
+    G = H.shape[0]
+    beta = kernel_beta(sigma, W)
+    Hf = H.reshape(-1)
+    out = np.zeros(k.shape[0], dtype=np.complex128)
+    for b in range(0, k.shape[0], chunk):
+        u = sigma * k[b:b + chunk] + G / 2
+        i0, w0 = _axis_taps(u[:, 0], W, beta, G)
+        if d == 1:
+            out[b:b + chunk] = np.sum(Hf[i0] * w0, axis=1)
+        else:
+            i1, w1 = _axis_taps(u[:, 1], W, beta, G)
+            flat = i0[:, :, None] * G + i1[:, None, :]
+            out[b:b + chunk] = np.sum(Hf[flat] * (w0[:, :, None] * w1[:, None, :]), axis=(1, 2))
+    return out
+
+
+def forward(k: np.ndarray, image: np.ndarray, n: int, sigma: float = 2.0, W: int = 6,
+            workers: int = 1) -> np.ndarray:
+    """The type-2 gridding transform: interpolate(image_to_grid(image)),
+    approximating nudft_forward to the kernel error."""
+    return interpolate(k, image_to_grid(image, n, sigma, W, workers=workers), sigma, W)
