@@ -17,3 +17,4 @@ from .ftcg_ref import (  # noqa: F401
     nudft_forward, image_to_grid, interpolate, forward,
 )
 from .band_ref import band_columns, band_dense, band_apply  # noqa: F401,E402
+from .density_ref import pipe_menon_weights  # noqa: F401,E402
