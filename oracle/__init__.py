@@ -18,3 +18,4 @@ from .ftcg_ref import (  # noqa: F401
 )
 from .band_ref import band_columns, band_dense, band_apply  # noqa: F401,E402
 from .density_ref import pipe_menon_weights  # noqa: F401,E402
+from .frame_ref import window, g_integral, frame_matrix, frame_coefficients, frame_image  # noqa: F401,E402
