@@ -68,8 +68,10 @@ typedef enum {
   FTCG_W_LEARNED = 1,     /* weights predicted by the plan's MLP, audited against FTCG_W_PLAIN */
   FTCG_W_USER = 2,        /* caller supplies alpha with ftcg_set_weights */
   FTCG_W_NONE = 3,        /* alpha_j = 1 */
-  FTCG_W_BAND = 4         /* the (2r-1)-banded FTCG coefficient matrix C of eq:ftcg / eq:cr,
+  FTCG_W_BAND = 4,        /* the (2r-1)-banded FTCG coefficient matrix C of eq:ftcg / eq:cr,
                              computed on the GPU in float64 (ftcg_plan_set_band) */
+  FTCG_W_DENSITY = 5      /* iterative density compensation, the iterative quadrature weights
+                             cited in Sec. III-A (ftcg_plan_set_density_iterations) */
 } ftcg_wmode;
 
 /* Human-readable name of a status code (static storage). */
@@ -136,6 +138,54 @@ ftcg_status ftcg_get_weights(ftcg_plan plan, double* alpha_dev, int* used_fallba
  * FTCG_ESTATE before ftcg_set_points (and, for FTCG_W_USER, the weights);
  * FTCG_EINVAL for NULL pointers. Enqueues only (no host synchronisation). */
 ftcg_status ftcg_execute(ftcg_plan plan, const void* fhat_dev, void* image_dev);
+
+/* Forward (type-2) transform at the plan's raster: the adjoint of the
+ * reconstruction with unit weights (Omega^T of eq:cgmatrix after the forward
+ * DFT), fhat_j ~ sum_p I[p] exp(-2 pi i k_j . x_p), the analysis sum that
+ * gives the data of Sec. III-A / eq:twoddataframe from an image on the pixel
+ * grid. Steps: multiply by the deapodization factors, zero-pad to the
+ * G^dim grid, forward FFT, interpolate with the spreading taps.
+ *   image_dev : device, n^dim complex values (dtype), row-major, read only.
+ *   fhat_dev  : device, m complex values (caller sample order), written
+ *               entirely.
+ * Uses the plan's grid and FFT workspace (an execute's grid is overwritten).
+ * FTCG_ESTATE before ftcg_set_points; FTCG_EUNSUPPORTED for float64 plans
+ * with tile 128 in 2D. Enqueues only. */
+ftcg_status ftcg_forward(ftcg_plan plan, const void* image_dev, void* fhat_dev);
+
+/* Dense frame approximation A_fr (Sec. III-B eq:binv, eq:afr, eq:afrm; 2D
+ * Sec. IV eq:twodframe, eq:twodframeB), the accuracy reference of small
+ * rasters that FTCG approximates with a banded C:
+ *   zeta_n = e^{2 pi i n . x} / w(x), modes n_a in -n/2 .. n/2 - 1, w the
+ *   plan's window Phi(x / sigma) per axis; Psi_{j,n} = <phi_j, zeta_n> =
+ *   prod_a g(k_ja - n_a), g(t) = int_{-1/2}^{1/2} cos(2 pi t x) / w(x) dx
+ *   (Gauss-Legendre, 4n + 64 nodes); beta = Psi^dagger fhat by a Householder
+ *   QR in float64 (least squares when m >= n^dim, minimum norm otherwise);
+ *   image[p] = sum_n beta_n e^{2 pi i n . x_p} / w(x_p).
+ *   m, k_dev : the raster (device float64, m x dim); independent of set_points.
+ *   fhat_dev : device complex128, m values.
+ *   image_dev: device complex128, n^dim values, row-major, written entirely.
+ * Float64 plans with n a power of two only; n^dim <= 4096 modes, n <= 1024,
+ * min(m, n^dim) <= 4096 and m n^dim <= 2^27 (FTCG_EUNSUPPORTED otherwise).
+ * FTCG_EINVAL when Psi is rank deficient (a pivot of R below 1e-14 of the
+ * largest). Synchronises the stream (reads that check). */
+ftcg_status ftcg_frame_approx(ftcg_plan plan, int64_t m, const double* k_dev, const void* fhat_dev,
+                              void* image_dev);
+
+/* Iterative density compensation (FTCG_W_DENSITY plans): the iterative
+ * quadrature weights the paper cites in Sec. III-A, a comparator to the
+ * frame weights of eq:difopt. From w = 1, each iteration spreads w with the
+ * path's kernel and interpolates it back at the samples with the same taps
+ * (d = Omega^T Omega w, Omega of eq:cgmatrix), then sets w <- w / d; the
+ * weights are kept in float64, spread and interpolated in the plan's
+ * precision. alpha = w (pi / (sigma beta))^dim, at which a uniform lattice of
+ * spacing h (cycles per FOV) gets h^dim, as the frame weights do; samples
+ * outside the k-box wrap onto the periodic grid and count there.
+ *   ftcg_plan_set_density_iterations : iters in 1..1000 (default 20), from the
+ *                        next ftcg_set_points; FTCG_ESTATE for other modes.
+ * The weights are read with ftcg_get_weights; execute uses them as the
+ * diagonal D. */
+ftcg_status ftcg_plan_set_density_iterations(ftcg_plan plan, int iters);
 
 /* Banded FTCG coefficient matrix (FTCG_W_BAND plans; Sec. III-C eq:ftcg,
  * eq:cr, eq:dif3; 2D Sec. IV eq:twodftcg): tau = Omega C fhat with C the
@@ -221,7 +271,9 @@ ftcg_status ftcg_plan_set_weight_tuning(ftcg_plan plan, int samples_per_lane, in
  *  2 spread, 3 fft pass 1, 4 fft pass 2 + deapodize + crop, 5 neighbour binning
  *  for weights, 6 learned-weight inference, 7 learned-weight audit,
  *  8 weights from the sums (and the sums' preset), 9 banded C: band of T^2,
- *  10 banded C: normal equations, 11 banded C: c = C fhat},
+ *  10 banded C: normal equations, 11 banded C: c = C fhat,
+ *  12 forward transform: FFT passes, 13 forward transform: interpolation,
+ *  14 iterative density compensation, 15 dense frame approximation},
  * the summed milliseconds ms[s] and the number of timed intervals count[s]
  * (host arrays of FTCG_TIMING_STEPS entries; unused entries are 0), then
  * resets the sums. A step can be timed in several intervals per call (step 0:

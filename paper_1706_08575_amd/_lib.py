@@ -15,11 +15,11 @@ LIB_PATH = os.path.join(HERE, "libftcg.so")
 
 FTCG_OK, FTCG_EINVAL, FTCG_ENOMEM, FTCG_EHIP, FTCG_ESTATE, FTCG_EUNSUPPORTED = range(6)
 FTCG_F64, FTCG_F32 = 0, 1
-FTCG_W_PLAIN, FTCG_W_LEARNED, FTCG_W_USER, FTCG_W_NONE, FTCG_W_BAND = range(5)
+FTCG_W_PLAIN, FTCG_W_LEARNED, FTCG_W_USER, FTCG_W_NONE, FTCG_W_BAND, FTCG_W_DENSITY = range(6)
 FTCG_ACCUM_FIXED, FTCG_ACCUM_F64 = 0, 1
 
 STEP_NAMES = ("bin", "weights", "spread", "fft1", "fft2_deapod", "weight_bin", "learned", "audit",
-              "weight_finish", "band_gram", "band_solve", "band_apply", "step12", "step13", "step14", "step15")
+              "weight_finish", "band_gram", "band_solve", "band_apply", "forward_fft", "forward_interp", "density", "frame_approx")
 TIMING_STEPS = 16
 
 
@@ -43,7 +43,10 @@ _SIGS = [
     ("ftcg_execute", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ftcg_spread_only", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ftcg_grid_to_image", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ftcg_forward", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ftcg_frame_approx", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ftcg_plan_set_band", C.c_int, [C.c_void_p, C.c_int]),
+    ("ftcg_plan_set_density_iterations", C.c_int, [C.c_void_p, C.c_int]),
     ("ftcg_get_band", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]),
     ("ftcg_plan_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int)]),

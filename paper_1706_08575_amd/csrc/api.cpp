@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "ftcg_internal.h"
@@ -136,7 +137,7 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
   if (half_width < 2 || half_width > 8) return FTCG_EINVAL;
   if (!(oversampling >= 1.25 && oversampling <= 4.0)) return FTCG_EINVAL;
   if (dtype != FTCG_F32 && dtype != FTCG_F64) return FTCG_EINVAL;
-  if (wmode < FTCG_W_PLAIN || wmode > FTCG_W_BAND) return FTCG_EINVAL;
+  if (wmode < FTCG_W_PLAIN || wmode > FTCG_W_DENSITY) return FTCG_EINVAL;
   if (!(weight_radius > 0.0 && weight_radius <= 64.0)) return FTCG_EINVAL;
   const double g = oversampling * (double)n0;
   if (fabs(g - nearbyint(g)) > 1e-9) return FTCG_EINVAL;
@@ -192,7 +193,7 @@ ftcg_status ftcg_plan_create(ftcg_plan* out, int dim, const int64_t* n, int half
 ftcg_status ftcg_plan_destroy(ftcg_plan p) {
   if (!p) return FTCG_EINVAL;
   (void)hipStreamSynchronize(p->stream);
-  DevBuf* bufs[] = {&p->band_P, &p->band_col, &p->band_row, &p->band_c, &p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp, &p->tile_scan_tmp, &p->check_part, &p->geo,
+  DevBuf* bufs[] = {&p->fa_gl, &p->fa_G, &p->fa_A, &p->fa_diag, &p->fa_beta, &p->fa_tw, &p->fa_tmp, &p->den_val, &p->den_d, &p->band_P, &p->band_col, &p->band_row, &p->band_c, &p->alpha,  &p->recs,  &p->alpha_s, &p->tile_cnt, &p->tile_off, &p->scan_tmp, &p->tile_scan_tmp, &p->check_part, &p->geo,
                     &p->flags,  &p->wb_cnt, &p->wb_off, &p->wb_rowoff, &p->wb_rowbuf, &p->ws_k,   &p->ws_idx,   &p->wb_of, &p->ws_inv, &p->ws_sum, &p->audit_buf,
                     &p->grid,   &p->fft_tmp, &p->deapod, &p->twiddle, &p->tile_order};
   for (DevBuf* b : bufs) b->release();
@@ -336,6 +337,16 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
         timing_end(p, STEP_BIN);
       }
     }
+    // 5) iterative density compensation: spreads and interpolates through
+    //    the records just written (weight 1), then gives them its weights
+    if (p->wmode == FTCG_W_DENSITY) {
+      if (!tiles) throw StatusError{FTCG_EUNSUPPORTED};
+      run_density_weights(p);
+      p->have_weights = true;
+      timing_begin(p, STEP_BIN);
+      refill_alpha_dev(p);
+      timing_end(p, STEP_BIN);
+    }
     p->finish_recs = false;
     p->nrec = -1;  // on the device (tile_off[ntiles]); read only when asked for
     p->have_points = true;
@@ -400,11 +411,38 @@ ftcg_status ftcg_execute(ftcg_plan p, const void* fhat_dev, void* image_dev) {
   });
 }
 
+ftcg_status ftcg_forward(ftcg_plan p, const void* image_dev, void* fhat_dev) {
+  if (!p || !image_dev || !fhat_dev) return FTCG_EINVAL;
+  if (!p->have_points || p->weights_only) return FTCG_ESTATE;
+  return guarded([&] { forward_transform(p, image_dev, fhat_dev); });
+}
+
+ftcg_status ftcg_frame_approx(ftcg_plan p, int64_t m, const double* k_dev, const void* fhat_dev, void* image_dev) {
+  if (!p || !k_dev || !fhat_dev || !image_dev) return FTCG_EINVAL;
+  if (m < 1) return FTCG_EINVAL;
+  if (p->dtype != FTCG_F64 || (p->n & (p->n - 1)) != 0) return FTCG_EUNSUPPORTED;
+  int64_t modes = p->n;
+  if (p->dim == 2) modes *= p->n;
+  if (p->n > 1024 || modes > 4096 || std::min<int64_t>(m, modes) > 4096 || m * modes > (int64_t(1) << 27))
+    return FTCG_EUNSUPPORTED;
+  return guarded([&] { frame_approx(p, m, k_dev, fhat_dev, image_dev); });
+}
+
 ftcg_status ftcg_plan_set_band(ftcg_plan p, int r) {
   if (!p) return FTCG_EINVAL;
   if (p->wmode != FTCG_W_BAND) return FTCG_ESTATE;
   if (r < 1 || r > 16) return FTCG_EINVAL;
   p->band_r = r;
+  p->have_points = false;
+  p->have_weights = false;
+  return FTCG_OK;
+}
+
+ftcg_status ftcg_plan_set_density_iterations(ftcg_plan p, int iters) {
+  if (!p) return FTCG_EINVAL;
+  if (p->wmode != FTCG_W_DENSITY) return FTCG_ESTATE;
+  if (iters < 1 || iters > 1000) return FTCG_EINVAL;
+  p->den_iters = iters;
   p->have_points = false;
   p->have_weights = false;
   return FTCG_OK;

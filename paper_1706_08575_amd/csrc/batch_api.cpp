@@ -146,7 +146,9 @@ ftcg_status ftcg_batch_create(ftcg_batch_s** out, int n_items, const int64_t* n,
   if (!out || !n) return FTCG_EINVAL;
   *out = nullptr;
   if (n_items < 1 || n_items > 4096) return FTCG_EINVAL;
-  if (wmode == FTCG_W_BAND) return FTCG_EUNSUPPORTED;   // batches apply diagonal weights only
+  // batches take diagonal weights computed per item by the frame-weight sum
+  // or the network, or given by the caller
+  if (wmode == FTCG_W_BAND || wmode == FTCG_W_DENSITY) return FTCG_EUNSUPPORTED;
   ftcg_batch_s* b = new (std::nothrow) ftcg_batch_s();
   if (!b) return FTCG_ENOMEM;
   b->stream = static_cast<hipStream_t>(hip_stream);

@@ -588,3 +588,136 @@ void compute_deapod_raw(double* d, int64_t n, double sigma, double beta, hipStre
 void compute_deapod(ftcg_plan p) { compute_deapod_raw(p->deapod.as<double>(), p->n, p->sigma, p->beta, p->stream); }
 
 }  // namespace ftcg
+
+namespace ftcg {
+
+// ---------------------------------------------------------------------------
+// Forward transform passes (the adjoint of the passes above), for the
+// type-2 transform: H[g] = sum_q J[q] e^{-2 pi i (g - G/2)(q - G/2)/G} over
+// the centred window J[q] = image[q - (G - n)/2] (zero elsewhere). As above,
+// with G divisible by 4 this is (-1)^g sum_q (-1)^q J[q] e^{-2 pi i g q / G},
+// and the forward DFT is the conjugate of the inverse DFT of the conjugate,
+// so each row runs through the same in-LDS inverse FFT: load the n values of
+// a row at offset crop_off, times dq[p] drow[row] (-1)^q, conjugated, into
+// a zero row of length L; transform; conjugate and multiply by (-1)^g; keep
+// all L outputs in registers and store them transposed, RB rows at a time as
+// RB-element segments: out[g * out_stride_q + row].
+// ---------------------------------------------------------------------------
+template <class real, int PPT, int RB>
+__global__ void k_fft_rows_fwd(const typename CxF<real>::t* __restrict__ in, int64_t in_row_stride,
+                               typename CxF<real>::t* __restrict__ out, int64_t out_stride_q, int L, int log2L,
+                               int n, int crop_off, const double* __restrict__ dq, const double* __restrict__ drow,
+                               const typename CxF<real>::t* __restrict__ tw, int log2T) {
+  using cx = typename CxF<real>::t;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx* buf = reinterpret_cast<cx*>(smem_raw);
+  cx* tw_lo = buf + padded_len(L);
+  cx* tw_hi = tw_lo + 64;
+  const int ntw = 64 + max(1, (1 << log2T) >> 6);
+  for (int i = threadIdx.x; i < ntw; i += blockDim.x) tw_lo[i] = tw[i];
+  const int nts = blockDim.x, t = threadIdx.x;
+  const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * RB;
+  cx outv[RB][PPT];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    const int row = r0 + j;
+    const double fr = drow ? drow[row] : 1.0;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int g = t + u * nts;
+      if (g < L) {
+        cx v;
+        v.x = (real)0;
+        v.y = (real)0;
+        const int p = g - crop_off;
+        if (p >= 0 && p < n) {
+          v = in[(int64_t)row * in_row_stride + p];
+          double f = (g & 1) ? -fr : fr;
+          if (dq) f *= dq[p];
+          const real fs = (real)f;
+          v.x *= fs;
+          v.y *= -fs;   // conjugate
+        }
+        buf[lp(g)] = v;
+      }
+    }
+    __syncthreads();
+    lds_ifft<real, PPT>(buf, L, log2L, t, nts, tw_lo, tw_hi, log2T);
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int g = t + u * nts;
+      if (g < L) {
+        cx v = buf[lp(g)];
+        const real s = (g & 1) ? (real)-1 : (real)1;
+        v.x *= s;
+        v.y *= -s;      // conjugate
+        outv[j][u] = v;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int g = t + u * nts;
+    if (g < L) {
+      cx* d = out + (int64_t)g * out_stride_q + r0;
+#pragma unroll
+      for (int j = 0; j < RB; ++j) d[j] = outv[j][u];
+    }
+  }
+}
+
+template <class real, int PPT, int RB>
+static void launch_fwd_rows(const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q, int64_t L,
+                            int64_t n, int rows, const double* dq, const double* drow, const void* tw,
+                            hipStream_t s) {
+  using cx = typename CxF<real>::t;
+  int log2L = 0;
+  while ((int64_t(1) << log2L) < L) ++log2L;
+  const int nts = (int)std::max<int64_t>(64, L / PPT);
+  const size_t lds = ((size_t)padded_len((int)L) + 64 + std::max<int64_t>(1, L >> 6)) * sizeof(cx);
+  static bool attr_done = false;
+  if (!attr_done) {
+    FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows_fwd<real, PPT, RB>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_done = true;
+  }
+  hipLaunchKernelGGL((k_fft_rows_fwd<real, PPT, RB>), dim3((unsigned)(rows / RB)), dim3(nts), lds, s,
+                     static_cast<const cx*>(in), in_row_stride, static_cast<cx*>(out), out_stride_q, (int)L, log2L,
+                     (int)n, (int)((L - n) / 2), dq, drow, static_cast<const cx*>(tw), log2L);
+  FTCG_HIP(hipGetLastError());
+}
+
+// RB rows per workgroup: 4 (32-byte float2 segments) while the outputs
+// kept in registers (RB x PPT complex per thread) leave room at the
+// workgroup sizes of long rows (1024 threads: 128 VGPRs per lane), else 2
+template <class real, int PPT>
+static void fwd_rows_rb(const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q, int64_t L,
+                        int64_t n, int rows, const double* dq, const double* drow, const void* tw, hipStream_t s) {
+  const bool four = sizeof(real) == 4 && PPT == 8 && L <= 4096;
+  if (four && rows % 4 == 0)
+    launch_fwd_rows<real, PPT, 4>(in, in_row_stride, out, out_stride_q, L, n, rows, dq, drow, tw, s);
+  else if (rows % 2 == 0)
+    launch_fwd_rows<real, PPT, 2>(in, in_row_stride, out, out_stride_q, L, n, rows, dq, drow, tw, s);
+  else
+    launch_fwd_rows<real, PPT, 1>(in, in_row_stride, out, out_stride_q, L, n, rows, dq, drow, tw, s);
+}
+
+// rows of length n (stride in_row_stride) -> zero-padded length-G forward
+// DFTs with the centred sign convention, written transposed
+void fft_rows_forward(bool f64, const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q, int64_t G,
+                      int64_t n, int rows, const double* dq, const double* drow, const void* tw, hipStream_t s) {
+  if (f64) {
+    if (G <= 8192)
+      fwd_rows_rb<double, 8>(in, in_row_stride, out, out_stride_q, G, n, rows, dq, drow, tw, s);
+    else
+      throw StatusError{FTCG_EUNSUPPORTED};
+  } else {
+    if (G <= 8192)
+      fwd_rows_rb<float, 8>(in, in_row_stride, out, out_stride_q, G, n, rows, dq, drow, tw, s);
+    else
+      fwd_rows_rb<float, 16>(in, in_row_stride, out, out_stride_q, G, n, rows, dq, drow, tw, s);
+  }
+}
+
+}  // namespace ftcg

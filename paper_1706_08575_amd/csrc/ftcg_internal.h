@@ -155,7 +155,11 @@ enum Step {
   STEP_BAND_GRAM = 9,    // banded C: the band of T^2
   STEP_BAND_SOLVE = 10,  // banded C: per-column normal equations
   STEP_BAND_APPLY = 11,  // c = C fhat ahead of the spread
-  N_STEPS = 16       // entries of the timing arrays (steps 12..15 unused)
+  STEP_FWD_FFT = 12,     // forward transform: deapodize, pad, forward FFT passes
+  STEP_FWD_INTERP = 13,  // forward transform: interpolation at the raster
+  STEP_DENSITY = 14,     // iterative density compensation (all iterations)
+  STEP_FRAME = 15,       // dense frame approximation (matrix, QR, solve, image)
+  N_STEPS = 16       // entries of the timing arrays
 };
 
 // per-step HIP event pairs recorded on the plan's stream; resolved (and
@@ -289,6 +293,14 @@ struct ftcg_plan_s {
   ftcg::DevBuf band_row;      // m x (2r-1): C[i, i + e - r + 1] (row form, for the apply)
   ftcg::DevBuf band_c;        // m complex: C fhat of the last execute
 
+  // iterative density compensation (FTCG_W_DENSITY)
+  int den_iters = 20;
+  ftcg::DevBuf den_val;       // m complex: the weights as spread values
+  ftcg::DevBuf den_d;         // m complex: Omega^T Omega w
+
+  // dense frame approximation (ftcg_frame_approx)
+  ftcg::DevBuf fa_gl, fa_G, fa_A, fa_diag, fa_beta, fa_tw, fa_tmp;
+
   // learned weights
   struct ftcg_mlp_s* mlp = nullptr;
   double audit_threshold = 1e-4;
@@ -347,6 +359,14 @@ void plain_weights_at(ftcg_plan p, const double* k, const int32_t* idx, int64_t 
 void fill_ones(double* a, int64_t m, hipStream_t s);
 void run_band_weights(ftcg_plan p);                 // banded C from the neighbour bins (FTCG_W_BAND)
 void band_apply(ftcg_plan p, const void* fhat);     // p->band_c = C fhat
+// rows of length n -> zero-padded forward DFTs of length G, centred signs, transposed store
+void fft_rows_forward(bool f64, const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q, int64_t G,
+                      int64_t n, int rows, const double* dq, const double* drow, const void* tw, hipStream_t s);
+void forward_transform(ftcg_plan p, const void* image, void* fhat);   // type-2 transform at the plan's raster
+void interpolate_grid(ftcg_plan p, void* out);      // out_j = taps of sample j applied to p->grid
+void run_density_weights(ftcg_plan p);              // iterative density compensation into p->alpha
+// dense frame approximation of the raster k (m samples) into image (float64 plans)
+void frame_approx(ftcg_plan p, int64_t m, const double* k, const void* fhat, void* image);
 void spread(ftcg_plan p, const void* fhat, void* grid);
 void grid_to_image(ftcg_plan p, const void* grid, void* image);
 void compute_deapod(ftcg_plan p);

@@ -40,7 +40,7 @@ class Plan:
         self.n, self.dim, self.W, self.sigma, self.R = int(n), int(dim), int(W), float(sigma), float(R)
         self.dtype = {"f32": L.FTCG_F32, "f64": L.FTCG_F64}[dtype]
         self.wmode = {"plain": L.FTCG_W_PLAIN, "learned": L.FTCG_W_LEARNED, "user": L.FTCG_W_USER,
-                      "none": L.FTCG_W_NONE, "band": L.FTCG_W_BAND}[weights]
+                      "none": L.FTCG_W_NONE, "band": L.FTCG_W_BAND, "density": L.FTCG_W_DENSITY}[weights]
         self.cdtype = torch.complex64 if self.dtype == L.FTCG_F32 else torch.complex128
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream
@@ -89,6 +89,29 @@ class Plan:
                        C.byref(fb)), "ftcg_get_weights")
         self.used_fallback = bool(fb.value)
         return out
+
+    def forward(self, image: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Type-2 transform of an n^dim image at the plan's raster (m values)."""
+        if out is None:
+            out = torch.empty(self.m, dtype=self.cdtype, device=self.device)
+        L.check(L.call("ftcg_forward", self._h, C.c_void_p(_dptr(image, self.cdtype, self.n ** self.dim, "image")),
+                       C.c_void_p(_dptr(out, self.cdtype, self.m, "fhat"))), "ftcg_forward")
+        return out
+
+    def frame_approx(self, k: torch.Tensor, fhat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Dense frame approximation of raster k (m x dim float64) with values
+        fhat (complex128) on this float64 plan's n^dim pixels."""
+        m = int(k.shape[0])
+        if out is None:
+            out = torch.empty((self.n,) * self.dim, dtype=torch.complex128, device=self.device)
+        L.check(L.call("ftcg_frame_approx", self._h, m, C.c_void_p(_dptr(k, torch.float64, m * self.dim, "k")),
+                       C.c_void_p(_dptr(fhat, torch.complex128, m, "fhat")),
+                       C.c_void_p(_dptr(out, torch.complex128, self.n ** self.dim, "image"))), "ftcg_frame_approx")
+        return out
+
+    def set_density_iterations(self, iters: int) -> None:
+        """Iterations of a weights="density" plan (applies from the next set_points)."""
+        L.check(L.call("ftcg_plan_set_density_iterations", self._h, int(iters)), "ftcg_plan_set_density_iterations")
 
     def set_band(self, r: int) -> None:
         """Band half-width r of a weights="band" plan (applies from the next set_points)."""

@@ -262,3 +262,33 @@ def mlp_init(seed: int = SEED_BASE + 40) -> dict:
             v = 0.1 * v
         out[name] = v.astype(np.float32)
     return out
+
+
+# ----------------------------------------------------------------------------
+# the 2D experiments of Sec. V: noisy grid raster, test function
+# ----------------------------------------------------------------------------
+
+def noisy_grid(seed: int, side: int) -> np.ndarray:
+    """Noisy grid raster of Sec. V-A: lambda = (n1, n2) + U(-1/4, 1/4)^2 for
+    n_a = -side/2 .. side/2 - 1, raster order n1-major. Draw order: jitter
+    (side^2 x 2)."""
+    rng = np.random.default_rng(seed)
+    g = np.arange(side) - side // 2
+    base = np.stack(np.meshgrid(g, g, indexing="ij"), axis=-1).reshape(-1, 2).astype(np.float64)
+    return base + rng.uniform(-0.25, 0.25, size=base.shape)
+
+
+def sine_test_function(x: np.ndarray) -> np.ndarray:
+    """f(x) = sin(4 pi x1) sin(2 pi x2) (the test function of Sec. V), x (..., 2)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.sin(4 * np.pi * x[..., 0]) * np.sin(2 * np.pi * x[..., 1])
+
+
+def sine_test_fourier(k: np.ndarray) -> np.ndarray:
+    """Exact fhat(k) = int over [-1/2, 1/2)^2 of f(x) e^{-2 pi i k.x} dx for the
+    test function: per axis int sin(2 pi c x) e^{-2 pi i k x} dx =
+    (sinc(k - c) - sinc(k + c)) / (2i), c = 2 and 1."""
+    k = np.asarray(k, dtype=np.float64)
+    f0 = (np.sinc(k[:, 0] - 2.0) - np.sinc(k[:, 0] + 2.0)) / 2j
+    f1 = (np.sinc(k[:, 1] - 1.0) - np.sinc(k[:, 1] + 1.0)) / 2j
+    return f0 * f1
