@@ -221,6 +221,27 @@ ftcg_status ftcg_get_band(ftcg_plan plan, double* c_dev, int* r_host);
 ftcg_status ftcg_spread_only(ftcg_plan plan, const void* fhat_dev, void* grid_dev);
 ftcg_status ftcg_grid_to_image(ftcg_plan plan, const void* grid_dev, void* image_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * transform of ftcg_grid_to_image (inverse FFT, deapodization, crop) with no
+ * plan and no allocation. Its workspace (the n x G intermediate, the twiddle
+ * tables and the deapodization factors) is a static 36 MiB device array that
+ * each GPU the library runs on holds until the process ends.
+ *   dim, n, half_width, oversampling, dtype : as ftcg_plan_create (the grid is
+ *                   G = oversampling * n per axis).
+ *   grid_dev  : device, G^dim complex values (dtype), row-major, read only.
+ *   image_dev : device, n^dim complex values, written entirely.
+ *   hip_stream: stream to enqueue on (NULL = the default stream).
+ * FTCG_EUNSUPPORTED when the workspace exceeds the array: in 2D,
+ * n * G * (8 for FTCG_F32, 16 for FTCG_F64) bytes plus the tables must fit
+ * 36 MiB (float32: n <= 1024 at oversampling 2; float64: n <= 1024 with
+ * 32 MiB). Results equal ftcg_grid_to_image's bit for bit. Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU race.
+ * Enqueues only. */
+ftcg_status ftcg_grid_to_image_noalloc(int dim, int64_t n, int half_width, double oversampling,
+                                       ftcg_dtype dtype, const void* grid_dev, void* image_dev,
+                                       void* hip_stream);
+
 /* Plan properties: G per axis, number of spread records after halo
  * duplication, number of tiles, tile edge. Any output pointer may be NULL. */
 ftcg_status ftcg_plan_info(ftcg_plan plan, int64_t* grid_size, int64_t* n_records,

@@ -48,6 +48,8 @@ _SIGS = [
     ("ftcg_plan_set_band", C.c_int, [C.c_void_p, C.c_int]),
     ("ftcg_plan_set_density_iterations", C.c_int, [C.c_void_p, C.c_int]),
     ("ftcg_get_band", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]),
+    ("ftcg_grid_to_image_noalloc", C.c_int, [C.c_int, C.c_int64, C.c_int, C.c_double, C.c_int, C.c_void_p,
+                                             C.c_void_p, C.c_void_p]),
     ("ftcg_plan_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int)]),
     ("ftcg_plan_set_tuning", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
