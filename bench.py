@@ -333,6 +333,189 @@ def bench_learned(steps: int, warmup: int) -> dict:
     return res
 
 
+def _timed_steps(P, step, steps, warmup):
+    """Mean seconds of `step` over `steps` calls after `warmup`, then the same
+    steps with the library's HIP events (ms per step in each stage)."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    P.enable_timing(True)
+    P.timing()
+    for _ in range(steps):
+        step()
+    st = {s_: ms / steps for s_, (ms, c) in P.timing().items()}
+    P.enable_timing(False)
+    return sec, st
+
+
+def bench_band(steps: int, warmup: int, r: int = 8) -> dict:
+    """Banded FTCG (Sec. III-C eq:ftcg, eq:cr) on the 512^2 SAS workload with the
+    paper's band of 15 (r = 8): a step = set_points (neighbour bins, band of
+    T^2, per-column normal equations) + execute (c = C fhat, spread, FFT).
+    Parity: 32 seeded columns of C against the oracle's lstsq, and the image
+    against the oracle fed the GPU's C."""
+    import torch
+    import oracle as O
+    from paper_1706_08575_amd import synth as S
+    from paper_1706_08575_amd.ftcg import Plan
+    k, f, _ = S.workload_2d_plain()
+    n, m = 512, len(f)
+    kd = torch.from_numpy(k).cuda()
+    fd = torch.from_numpy(f).to(torch.complex64).cuda()
+    with Plan(n, dim=2, weights="band") as P:
+        P.set_band(r)
+        out = torch.empty((n, n), dtype=torch.complex64, device="cuda")
+
+        def step():
+            P.set_points(kd)
+            P.execute(fd, out)
+
+        sec, st = _timed_steps(P, step, steps, warmup)
+        B = P.get_band().cpu().numpy()
+        img = out.cpu().numpy()
+    cols = np.random.default_rng(8).choice(m, 32, replace=False)
+    Bref = O.band_columns(k, r, 8.0, cols=cols)
+    cerr = float(np.max(np.abs(B[cols] - Bref)) / np.max(np.abs(Bref)))
+    ref = O.ftcg_image(k, O.band_apply(B, f, r), np.ones(m), n, workers=os.cpu_count() or 1)
+    pairs = count_box_pairs(k, 8.0)
+    gram_ms = st.get("band_gram", float("nan"))
+    ach = pairs * (2 * r - 1) * FLOPS_PER_PAIR[2] / (gram_ms * 1e-3) / 1e12
+    return {"workload": "sas512_band_r8", "samples": m, "r": r, "ms_per_step": sec * 1e3, "images_per_s": 1 / sec,
+            "msamples_per_s": m / sec / 1e6, "stage_ms": st, "rel_l2_vs_oracle_same_C": O.rel_l2(img, ref),
+            "C_max_rel_err_32_columns": cerr,
+            "band_gram_roofline": {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": ach / FP64_PEAK_TFLOPS,
+                                   "work": f"{pairs} ordered in-box pairs x {2 * r - 1} products x "
+                                           f"{FLOPS_PER_PAIR[2]} FP64 flops"}}
+
+
+def bench_forward(steps: int, warmup: int) -> dict:
+    """Forward (type-2) transform on the 4096^2 workload's raster (8.4M samples):
+    a step = deapodize + pad + two forward FFT passes + interpolation. Parity:
+    512 seeded values against the oracle's forward transform."""
+    import torch
+    import oracle as O
+    from paper_1706_08575_amd import synth as S
+    from paper_1706_08575_amd.ftcg import Plan
+    k, _, _ = S.workload_2d_precision()
+    n, m, G = 4096, len(k), 8192
+    rng = np.random.default_rng(40)
+    x = (np.arange(n) - n / 2) / n
+    env = np.exp(-(x[:, None] ** 2 + x[None, :] ** 2) / 0.05)
+    img = (env * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))).astype(np.complex64)
+    with Plan(n, dim=2, weights="none") as P:
+        P.set_points(torch.from_numpy(k).cuda())
+        imd = torch.from_numpy(img).cuda()
+        out = torch.empty(m, dtype=torch.complex64, device="cuda")
+        sec, st = _timed_steps(P, lambda: P.forward(imd, out), steps, warmup)
+        got = out.cpu().numpy()
+        nrec = P.info()["n_records"]
+    idx = rng.choice(m, 512, replace=False)
+    ref = O.interpolate(k[idx], O.image_to_grid(img.astype(np.complex128), n, workers=os.cpu_count() or 1))
+    fft_bytes = (n * n * 8 + G * n * 8) + (G * n * 8 + G * G * 8)
+    interp_bytes = G * G * 8 + m * 8 + nrec * 16
+    fms, ims = st.get("forward_fft", float("nan")), st.get("forward_interp", float("nan"))
+    return {"workload": "sas4096_forward", "samples": m, "ms_per_step": sec * 1e3,
+            "msamples_per_s": m / sec / 1e6, "stage_ms": st,
+            "rel_l2_vs_oracle_512_sampled": O.rel_l2(got[idx], ref),
+            "hbm": {"fft_passes": {"bytes": fft_bytes, "GB/s": fft_bytes / (fms * 1e-3) / 1e9,
+                                   "frac_hbm": fft_bytes / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                    "interp": {"bytes": interp_bytes, "GB/s": interp_bytes / (ims * 1e-3) / 1e9,
+                               "frac_hbm": interp_bytes / (ims * 1e-3) / 1e9 / HBM_PEAK_GBS}}}
+
+
+def bench_density(steps: int, warmup: int, iters: int = 20) -> dict:
+    """Iterative density compensation (the cited iterative quadrature weights)
+    on the 512^2 SAS workload, 20 iterations: a step = set_points (binning +
+    20 x (spread + interpolation)) + execute. Parity against the oracle's
+    iteration on a 128^2 raster (the oracle's cost grows with samples x
+    iterations); the weights are compared with the frame weights."""
+    import torch
+    import oracle as O
+    from paper_1706_08575_amd import synth as S
+    from paper_1706_08575_amd.ftcg import Plan
+    k, f, _ = S.workload_2d_plain()
+    n, m = 512, len(f)
+    kd = torch.from_numpy(k).cuda()
+    fd = torch.from_numpy(f).to(torch.complex64).cuda()
+    with Plan(n, dim=2, weights="density") as P:
+        P.set_density_iterations(iters)
+        out = torch.empty((n, n), dtype=torch.complex64, device="cuda")
+
+        def step():
+            P.set_points(kd)
+            P.execute(fd, out)
+
+        sec, st = _timed_steps(P, step, steps, warmup)
+        a_pm = P.get_weights().cpu().numpy()
+    with Plan(n, dim=2, weights="plain") as Q:
+        Q.set_points(kd)
+        a_fr = Q.get_weights().cpu().numpy()
+    ks, fs, _ = S.make_sas(S.seed_for(1) + 80, n=128, pulses=64, per_pulse=128)
+    with Plan(128, dim=2, weights="density") as P:
+        P.set_density_iterations(iters)
+        P.set_points(torch.from_numpy(ks).cuda())
+        a_s = P.get_weights().cpu().numpy()
+    ref = O.pipe_menon_weights(ks, 128, iters)
+    rel = (a_s - ref) / ref
+    return {"workload": "sas512_density20", "samples": m, "iterations": iters, "ms_per_step": sec * 1e3,
+            "images_per_s": 1 / sec, "stage_ms": st,
+            "parity_128": {"samples": len(ks), "max_rel": float(np.max(np.abs(rel))),
+                           "rms_rel": float(np.sqrt(np.mean(rel ** 2)))},
+            "vs_frame_weights": {"mean_density": float(a_pm.mean()), "mean_frame": float(a_fr.mean()),
+                                 "rel_rms_difference": float(np.sqrt(np.mean(((a_pm - a_fr) / a_fr) ** 2)))}}
+
+
+def bench_frame() -> dict:
+    """Dense frame approximation (Sec. III-B eq:binv, eq:afr) on the noisy-grid
+    raster of Sec. V-A with the test function of Sec. V, timed once per case,
+    against the oracle; beside it the PSNR (peak |f| over the RMS error at the
+    pixels) of the frame approximation, of banded FTCG (r = 8, the paper's band
+    of 15) and of diagonal FTCG on the same data (the paper's comparison; its
+    raster sizes are not given, so its figures are not reproduced)."""
+    import torch
+    import oracle as O
+    from paper_1706_08575_amd import synth as S
+    from paper_1706_08575_amd.ftcg import Plan
+    res = {}
+    for side, n in ((16, 16), (30, 32)):
+        k = S.noisy_grid(S.seed_for(5) + side, side)
+        f = S.sine_test_fourier(k)
+        x = (np.arange(n) - n / 2) / n
+        truth = S.sine_test_function(np.stack(np.meshgrid(x, x, indexing="ij"), -1))
+
+        def psnr(img):
+            return float(20 * np.log10(np.max(np.abs(truth)) / np.sqrt(np.mean(np.abs(img - truth) ** 2))))
+
+        kd = torch.from_numpy(k).cuda()
+        fd = torch.from_numpy(f).cuda()
+        with Plan(n, dim=2, dtype="f64", weights="none") as P:
+            P.frame_approx(kd, fd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            img = P.frame_approx(kd, fd)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            img = img.cpu().numpy()
+        ref = O.frame_image(k, f, n)
+        out = {"samples": len(k), "modes": n * n, "ms": ms, "rel_l2_vs_oracle": O.rel_l2(img, ref),
+               "psnr_db": {"frame": psnr(img)}}
+        for name, w, r in (("ftcg_band_r8", "band", 8), ("ftcg_diagonal", "plain", 1)):
+            with Plan(n, dim=2, dtype="f64", weights=w) as P:
+                if w == "band":
+                    P.set_band(r)
+                P.set_points(kd)
+                out["psnr_db"][name] = psnr(P.execute(fd).cpu().numpy())
+        res[f"noisy_grid_{side}x{side}_modes_{n}x{n}"] = out
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -488,7 +671,11 @@ def main():
     forms = None
     if not args.no_forms:
         forms = {"batched": bench_batched(steps=3, warmup=1),
-                 "learned": bench_learned(steps=max(3, min(args.steps, 10)), warmup=1)}
+                 "learned": bench_learned(steps=max(3, min(args.steps, 10)), warmup=1),
+                 "band": bench_band(steps=5, warmup=2),
+                 "forward": bench_forward(steps=10, warmup=5),
+                 "density": bench_density(steps=5, warmup=2),
+                 "frame_approx": bench_frame()}
 
     res = {
         "metric": METRIC,

@@ -52,7 +52,16 @@ extern "C" {
 
 typedef struct ftcg_plan_s* ftcg_plan;
 
-typedef enum {
+/* The enumerations below have int as their underlying type in C++ as well,
+ * so any int a C caller passes is a value of the type (the entry points
+ * reject the ones outside the listed constants). */
+#ifdef __cplusplus
+#define FTCG_ENUM enum : int
+#else
+#define FTCG_ENUM enum
+#endif
+
+typedef FTCG_ENUM {
   FTCG_OK = 0,
   FTCG_EINVAL = 1,        /* bad argument (sizes, null pointer, non-finite k) */
   FTCG_ENOMEM = 2,        /* device allocation failed */
@@ -61,9 +70,9 @@ typedef enum {
   FTCG_EUNSUPPORTED = 5   /* valid request this build does not implement */
 } ftcg_status;
 
-typedef enum { FTCG_F64 = 0, FTCG_F32 = 1 } ftcg_dtype;
+typedef FTCG_ENUM { FTCG_F64 = 0, FTCG_F32 = 1 } ftcg_dtype;
 
-typedef enum {
+typedef FTCG_ENUM {
   FTCG_W_PLAIN = 0,       /* frame-optimal diagonal weights, computed on the GPU in float64 */
   FTCG_W_LEARNED = 1,     /* weights predicted by the plan's MLP, audited against FTCG_W_PLAIN */
   FTCG_W_USER = 2,        /* caller supplies alpha with ftcg_set_weights */
@@ -258,7 +267,7 @@ ftcg_status ftcg_plan_info(ftcg_plan plan, int64_t* grid_size, int64_t* n_record
  *                      and only mode of float64 plans); lds_copies > 1 gives
  *                      each wavefront its own partial tile, combined at the
  *                      flush with compensated (TwoSum) addition. */
-typedef enum { FTCG_ACCUM_FIXED = 0, FTCG_ACCUM_F64 = 1 } ftcg_accum;
+typedef FTCG_ENUM { FTCG_ACCUM_FIXED = 0, FTCG_ACCUM_F64 = 1 } ftcg_accum;
 
 /* Tuning knobs (take effect at the next ftcg_set_points; the points must be
  * set again):

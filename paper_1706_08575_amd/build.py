@@ -63,3 +63,40 @@ def build(verbose: bool = True) -> str:
 
 if __name__ == "__main__":
     build()
+
+
+def build_abi_check(verbose: bool = False) -> str:
+    """Executable of tests/abi_check.cpp against the library's objects, with the
+    host code of the entry-point files (the .cpp sources: argument checks,
+    status plumbing, plan lifecycle) and the driver built with
+    AddressSanitizer and UndefinedBehaviorSanitizer. Device code is built
+    as usual (the sanitizers apply to the host side only); the .hip objects
+    come from the regular build. Returns the executable's path."""
+    build(verbose=False)
+    san = os.path.join(BUILD, "san")
+    os.makedirs(san, exist_ok=True)
+    host_flags = ["-O1", "-g", "-fno-omit-frame-pointer",
+                  "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+    objs = []
+    srcs = [s for s in sources() if s.endswith(".cpp")] + [os.path.join(ROOT, "tests", "abi_check.cpp")]
+
+    def comp(src):
+        obj = os.path.join(san, os.path.basename(src) + ".o")
+        flags = [f for f in COMMON if f != "-O3"]
+        cmd = [HIPCC, "-x", "hip", *flags, *host_flags, "-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(comp, srcs))
+    objs += [os.path.join(BUILD, os.path.basename(s) + ".o") for s in sources() if s.endswith(".hip")]
+    exe = os.path.join(san, "abi_check")
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-fsanitize=address,undefined", "-fno-gpu-sanitize", "-o", exe, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {exe}")
+    return exe
