@@ -529,6 +529,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and learned forms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--only-forms", default=None,
+                    help="comma-separated forms to run alone (band, forward, density, frame_approx), "
+                         "printing one JSON object of their results (for profiling them)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -541,6 +544,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.only_forms:
+        run = {"band": lambda: bench_band(steps=5, warmup=2), "forward": lambda: bench_forward(steps=10, warmup=5),
+               "density": lambda: bench_density(steps=5, warmup=2), "frame_approx": bench_frame}
+        print(json.dumps({name: run[name]() for name in args.only_forms.split(",")}))
+        return
     if args.workload in ("batch64_sas", "learned1024_sas"):
         if args.workload == "batch64_sas":
             r = bench_batched(steps=args.steps, warmup=args.warmup, tune=args.tile == 0)

@@ -597,15 +597,23 @@ namespace ftcg {
 // the centred window J[q] = image[q - (G - n)/2] (zero elsewhere). As above,
 // with G divisible by 4 this is (-1)^g sum_q (-1)^q J[q] e^{-2 pi i g q / G},
 // and the forward DFT is the conjugate of the inverse DFT of the conjugate,
-// so each row runs through the same in-LDS inverse FFT: load the n values of
-// a row at offset crop_off, times dq[p] drow[row] (-1)^q, conjugated, into
-// a zero row of length L; transform; conjugate and multiply by (-1)^g; keep
-// all L outputs in registers and store them transposed, RB rows at a time as
-// RB-element segments: out[g * out_stride_q + row].
+// so each transform runs through the same in-LDS inverse FFT.
+//
+// These passes write every one of the G outputs of a transform (twice the
+// data they read), so they read strided and write contiguous: a workgroup
+// takes RB consecutive columns of its input (the n positions p of column r at
+// in[p in_stride + r], read as RB-element, 32-byte segments), forms for each
+// column the zero row of length G with the n values at offset (G - n)/2,
+// times dq[p] drow[r] (-1)^q and conjugated, transforms it, and writes its G
+// outputs, conjugated and times (-1)^g, as one contiguous row
+// out[r out_row_stride + g]:
+//   pass A: columns p1 of the image I[p0][p1]   -> T[p1][g0]  (n x G)
+//   pass B: columns g0 of T (positions p1)      -> H[g0][g1]  (G x G), the
+//           grid's own layout.
 // ---------------------------------------------------------------------------
 template <class real, int PPT, int RB>
-__global__ void k_fft_rows_fwd(const typename CxF<real>::t* __restrict__ in, int64_t in_row_stride,
-                               typename CxF<real>::t* __restrict__ out, int64_t out_stride_q, int L, int log2L,
+__global__ void k_fft_cols_fwd(const typename CxF<real>::t* __restrict__ in, int64_t in_stride,
+                               typename CxF<real>::t* __restrict__ out, int64_t out_row_stride, int L, int log2L,
                                int n, int crop_off, const double* __restrict__ dq, const double* __restrict__ drow,
                                const typename CxF<real>::t* __restrict__ tw, int log2T) {
   using cx = typename CxF<real>::t;
@@ -617,59 +625,70 @@ __global__ void k_fft_rows_fwd(const typename CxF<real>::t* __restrict__ in, int
   for (int i = threadIdx.x; i < ntw; i += blockDim.x) tw_lo[i] = tw[i];
   const int nts = blockDim.x, t = threadIdx.x;
   const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * RB;
-  cx outv[RB][PPT];
+  double fc[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) fc[j] = drow ? drow[r0 + j] : 1.0;
+  // this thread's positions of all RB columns, scaled and conjugated: the
+  // first column straight into the LDS row, the others held in registers
+  cx x[PPT][RB > 1 ? RB - 1 : 1];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int g = t + u * nts;
+    const int p = g - crop_off;
+    cx v0;
+    v0.x = (real)0;
+    v0.y = (real)0;
+#pragma unroll
+    for (int j = 1; j < RB; ++j) x[u][j - 1] = v0;
+    if (g < L && p >= 0 && p < n) {
+      const cx* src = in + (int64_t)p * in_stride + r0;
+      double f = (g & 1) ? -1.0 : 1.0;
+      if (dq) f *= dq[p];
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        const cx v = src[j];
+        const real fs = (real)(f * fc[j]);
+        cx w;
+        w.x = v.x * fs;
+        w.y = -v.y * fs;   // conjugate
+        if (j == 0)
+          v0 = w;
+        else
+          x[u][j - 1] = w;
+      }
+    }
+    if (g < L) buf[lp(g)] = v0;
+  }
 #pragma unroll
   for (int j = 0; j < RB; ++j) {
-    const int row = r0 + j;
-    const double fr = drow ? drow[row] : 1.0;
+    if (j > 0) {
 #pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-      const int g = t + u * nts;
-      if (g < L) {
-        cx v;
-        v.x = (real)0;
-        v.y = (real)0;
-        const int p = g - crop_off;
-        if (p >= 0 && p < n) {
-          v = in[(int64_t)row * in_row_stride + p];
-          double f = (g & 1) ? -fr : fr;
-          if (dq) f *= dq[p];
-          const real fs = (real)f;
-          v.x *= fs;
-          v.y *= -fs;   // conjugate
-        }
-        buf[lp(g)] = v;
+      for (int u = 0; u < PPT; ++u) {
+        const int g = t + u * nts;
+        if (g < L) buf[lp(g)] = x[u][j - 1];
       }
     }
     __syncthreads();
     lds_ifft<real, PPT>(buf, L, log2L, t, nts, tw_lo, tw_hi, log2T);
+    cx* dst = out + (int64_t)(r0 + j) * out_row_stride;
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
       const int g = t + u * nts;
       if (g < L) {
         cx v = buf[lp(g)];
-        const real s = (g & 1) ? (real)-1 : (real)1;
-        v.x *= s;
-        v.y *= -s;      // conjugate
-        outv[j][u] = v;
+        const real sg = (g & 1) ? (real)-1 : (real)1;
+        v.x *= sg;
+        v.y *= -sg;     // conjugate
+        dst[g] = v;
       }
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int u = 0; u < PPT; ++u) {
-    const int g = t + u * nts;
-    if (g < L) {
-      cx* d = out + (int64_t)g * out_stride_q + r0;
-#pragma unroll
-      for (int j = 0; j < RB; ++j) d[j] = outv[j][u];
-    }
-  }
 }
 
 template <class real, int PPT, int RB>
-static void launch_fwd_rows(const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q, int64_t L,
-                            int64_t n, int rows, const double* dq, const double* drow, const void* tw,
+static void launch_fwd_cols(const void* in, int64_t in_stride, void* out, int64_t out_row_stride, int64_t L,
+                            int64_t n, int cols, const double* dq, const double* drow, const void* tw,
                             hipStream_t s) {
   using cx = typename CxF<real>::t;
   int log2L = 0;
@@ -678,45 +697,46 @@ static void launch_fwd_rows(const void* in, int64_t in_row_stride, void* out, in
   const size_t lds = ((size_t)padded_len((int)L) + 64 + std::max<int64_t>(1, L >> 6)) * sizeof(cx);
   static bool attr_done = false;
   if (!attr_done) {
-    FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows_fwd<real, PPT, RB>,
+    FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_cols_fwd<real, PPT, RB>,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     attr_done = true;
   }
-  hipLaunchKernelGGL((k_fft_rows_fwd<real, PPT, RB>), dim3((unsigned)(rows / RB)), dim3(nts), lds, s,
-                     static_cast<const cx*>(in), in_row_stride, static_cast<cx*>(out), out_stride_q, (int)L, log2L,
+  hipLaunchKernelGGL((k_fft_cols_fwd<real, PPT, RB>), dim3((unsigned)(cols / RB)), dim3(nts), lds, s,
+                     static_cast<const cx*>(in), in_stride, static_cast<cx*>(out), out_row_stride, (int)L, log2L,
                      (int)n, (int)((L - n) / 2), dq, drow, static_cast<const cx*>(tw), log2L);
   FTCG_HIP(hipGetLastError());
 }
 
-// RB rows per workgroup: 4 (32-byte float2 segments) while the outputs
-// kept in registers (RB x PPT complex per thread) leave room at the
-// workgroup sizes of long rows (1024 threads: 128 VGPRs per lane), else 2
+// RB columns per workgroup: 4 in float32 (32-byte read segments; the inputs
+// of the other three columns held in registers bring the kernel to the 128
+// VGPRs per lane of 1024-thread workgroups, with 2 spilled), else 1 (two
+// float64 columns spill 20 VGPRs; float32 rows of 16384 points take 16
+// points per thread)
 template <class real, int PPT>
-static void fwd_rows_rb(const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q, int64_t L,
-                        int64_t n, int rows, const double* dq, const double* drow, const void* tw, hipStream_t s) {
-  const bool four = sizeof(real) == 4 && PPT == 8 && L <= 4096;
-  if (four && rows % 4 == 0)
-    launch_fwd_rows<real, PPT, 4>(in, in_row_stride, out, out_stride_q, L, n, rows, dq, drow, tw, s);
-  else if (rows % 2 == 0)
-    launch_fwd_rows<real, PPT, 2>(in, in_row_stride, out, out_stride_q, L, n, rows, dq, drow, tw, s);
+static void fwd_cols_rb(const void* in, int64_t in_stride, void* out, int64_t out_row_stride, int64_t L, int64_t n,
+                        int cols, const double* dq, const double* drow, const void* tw, hipStream_t s) {
+  constexpr int RB = (PPT == 8 && sizeof(real) == 4) ? 4 : 1;
+  if (cols % RB == 0)
+    launch_fwd_cols<real, PPT, RB>(in, in_stride, out, out_row_stride, L, n, cols, dq, drow, tw, s);
   else
-    launch_fwd_rows<real, PPT, 1>(in, in_row_stride, out, out_stride_q, L, n, rows, dq, drow, tw, s);
+    launch_fwd_cols<real, PPT, 1>(in, in_stride, out, out_row_stride, L, n, cols, dq, drow, tw, s);
 }
 
-// rows of length n (stride in_row_stride) -> zero-padded length-G forward
-// DFTs with the centred sign convention, written transposed
-void fft_rows_forward(bool f64, const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q, int64_t G,
-                      int64_t n, int rows, const double* dq, const double* drow, const void* tw, hipStream_t s) {
+// columns of n positions (column r at in[p in_stride + r]) -> zero-padded
+// length-G forward DFTs with the centred sign convention, one contiguous row
+// of out per column
+void fft_cols_forward(bool f64, const void* in, int64_t in_stride, void* out, int64_t out_row_stride, int64_t G,
+                      int64_t n, int cols, const double* dq, const double* drow, const void* tw, hipStream_t s) {
   if (f64) {
     if (G <= 8192)
-      fwd_rows_rb<double, 8>(in, in_row_stride, out, out_stride_q, G, n, rows, dq, drow, tw, s);
+      fwd_cols_rb<double, 8>(in, in_stride, out, out_row_stride, G, n, cols, dq, drow, tw, s);
     else
       throw StatusError{FTCG_EUNSUPPORTED};
   } else {
     if (G <= 8192)
-      fwd_rows_rb<float, 8>(in, in_row_stride, out, out_stride_q, G, n, rows, dq, drow, tw, s);
+      fwd_cols_rb<float, 8>(in, in_stride, out, out_row_stride, G, n, cols, dq, drow, tw, s);
     else
-      fwd_rows_rb<float, 16>(in, in_row_stride, out, out_stride_q, G, n, rows, dq, drow, tw, s);
+      fwd_cols_rb<float, 16>(in, in_stride, out, out_row_stride, G, n, cols, dq, drow, tw, s);
   }
 }
 

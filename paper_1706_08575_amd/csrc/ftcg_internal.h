@@ -359,9 +359,10 @@ void plain_weights_at(ftcg_plan p, const double* k, const int32_t* idx, int64_t 
 void fill_ones(double* a, int64_t m, hipStream_t s);
 void run_band_weights(ftcg_plan p);                 // banded C from the neighbour bins (FTCG_W_BAND)
 void band_apply(ftcg_plan p, const void* fhat);     // p->band_c = C fhat
-// rows of length n -> zero-padded forward DFTs of length G, centred signs, transposed store
-void fft_rows_forward(bool f64, const void* in, int64_t in_row_stride, void* out, int64_t out_stride_q, int64_t G,
-                      int64_t n, int rows, const double* dq, const double* drow, const void* tw, hipStream_t s);
+// columns of n positions (column r at in[p in_stride + r]) -> zero-padded
+// forward DFTs of length G, centred signs, one contiguous output row each
+void fft_cols_forward(bool f64, const void* in, int64_t in_stride, void* out, int64_t out_row_stride, int64_t G,
+                      int64_t n, int cols, const double* dq, const double* drow, const void* tw, hipStream_t s);
 void forward_transform(ftcg_plan p, const void* image, void* fhat);   // type-2 transform at the plan's raster
 void interpolate_grid(ftcg_plan p, void* out);      // out_j = taps of sample j applied to p->grid
 void run_density_weights(ftcg_plan p);              // iterative density compensation into p->alpha
