@@ -89,6 +89,23 @@ def test_full_size_4096_spread_tiles():
     assert max(errs) < 1e-4
 
 
+def test_full_size_spread_is_bitwise_reproducible():
+    # the 4096^2 workload's spread (fixed-point tiles, more than 256 records
+    # in most of them, so staged in two chunks) is bitwise the same after
+    # re-binning, which may place the records of a tile in another order
+    from paper_1706_08575_amd.ftcg import Plan
+    k, f, _ = S.workload_2d_precision()
+    kd = torch.from_numpy(np.ascontiguousarray(k)).cuda()
+    fd = torch.from_numpy(f).to(torch.complex64).cuda()
+    with Plan(4096, dim=2, dtype="f32", weights="plain") as P:
+        P.set_points(kd)
+        h1 = P.spread_only(fd).clone()
+        P.set_points(kd)
+        h2 = P.spread_only(fd)
+        torch.cuda.synchronize()
+        assert torch.equal(h1, h2)
+
+
 @pytest.mark.parametrize("n", [4096, 8192])
 def test_fft_full_size_elementwise(n):
     # the inverse-FFT passes, deapodization and crop at G = 8192 and 16384
