@@ -294,21 +294,20 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_rows(const WSample<2
 // float64 atomic per touched candidate into the bin-order sums, which start
 // from the self terms pi^4 preset by the bin sort. Launch shape and staging
 // as k_frame_weights_rows with one sample per lane group.
-// One staged candidate i (chunk slot p) against the WT samples of a lane:
+// One staged candidate (chunk slot p) against the WT samples of a lane:
 // each in-box square goes to the sample's sum and, summed over the WT
-// samples, to the candidate's slot. Sample u only takes candidates after
-// first[u] (its own position in its own bin row, else -1) and only while
-// active.
+// samples, to the candidate's slot. Every candidate of a lane's ranges pairs
+// with all of its samples: in the own bin row the range starts after the
+// lane's last live sample (the pair of the lane's two samples is added once,
+// outside the loop), and a lane's idle sample sits far outside every box.
 template <int WT>
-__device__ inline void sym_pair(double (&acc)[WT], double* cacc, int p, int i, const WSample<2>& o,
+__device__ inline void sym_pair(double (&acc)[WT], double* cacc, int p, const WSample<2>& o,
                                 const double (&x)[WT][2], const double (&sn)[WT][2], const double (&cs)[WT][2],
-                                const int (&first)[WT], double R) {
+                                double R) {
   double csum = 0.0;
 #pragma unroll
   for (int u = 0; u < WT; ++u) {
-    const double q = pair_term<2>(o, x[u], sn[u], cs[u], R);
-    // (one sample per lane: its range already starts after first[0])
-    const double q2 = (WT == 1 || i > first[u]) ? wq_square(q) : 0.0;
+    const double q2 = wq_square(pair_term<2>(o, x[u], sn[u], cs[u], R));
     acc[u] += q2;
     csum += q2;
   }
@@ -357,6 +356,15 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
     }
     mylo = max(mylo - g.span, 0);
     myhi = min(myhi + g.span, nb1 - 1);
+    // an idle sample (past the run's end: a copy of its last sample, whose
+    // bins set the window above) moves far outside every box: its terms
+    // are 0, and it needs no test in the pair loop
+#pragma unroll
+    for (int u = 1; u < WT; ++u)
+      if (!live[u]) x[u][0] = x[u][1] = 0x1p100;
+    int nlive = 0;
+#pragma unroll
+    for (int u = 0; u < WT; ++u) nlive += live[u] ? 1 : 0;
     int lo1, hi1;
     {
       int b[2];
@@ -372,15 +380,12 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
     for (int u = 0; u < WT; ++u) acc[u] = 0.0;
     for (int r = b0; r <= rhi; ++r) {
       const int gs = boff[r * nb1 + lo1], ge = boff[r * nb1 + hi1 + 1];
-      // own row: the samples after each of this lane's; idle samples take none
-      int first[WT];
-#pragma unroll
-      for (int u = 0; u < WT; ++u) first[u] = !live[u] ? (1 << 30) : (r == b0 ? t0 + u : -1);
       int ms = 0, me = 0;
       if (active) {
         int fs = boff[r * nb1 + mylo];
         const int fe = boff[r * nb1 + myhi + 1];
-        if (r == b0) fs = max(fs, t0 + 1);
+        // own row: the samples after this lane's live ones
+        if (r == b0) fs = max(fs, t0 + nlive);
         if (fs < fe) {
           const int part = (fe - fs + S - 1) / S;
           ms = min(fs + sub * part, fe);
@@ -407,11 +412,11 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
             const int pb = p + 1 == a1 ? a0 : p + 1;
             const WSample<2> ca = ld_wsample(cand + p);
             const WSample<2> cb = ld_wsample(cand + pb);
-            sym_pair<WT>(acc, cacc, p, q0 + p, ca, x, sn, cs, first, g.R);
-            sym_pair<WT>(acc, cacc, pb, q0 + pb, cb, x, sn, cs, first, g.R);
+            sym_pair<WT>(acc, cacc, p, ca, x, sn, cs, g.R);
+            sym_pair<WT>(acc, cacc, pb, cb, x, sn, cs, g.R);
             p = pb + 1 == a1 ? a0 : pb + 1;
           }
-          if (len & 1) sym_pair<WT>(acc, cacc, p, q0 + p, ld_wsample(cand + p), x, sn, cs, first, g.R);
+          if (len & 1) sym_pair<WT>(acc, cacc, p, ld_wsample(cand + p), x, sn, cs, g.R);
         }
         __syncthreads();
         for (int i = threadIdx.x; i < q1 - q0; i += WB_BLOCK) {
@@ -422,6 +427,26 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
           }
         }
       }
+    }
+    // the pairs among this lane's own samples (left out of its own-row
+    // range), formed once: by the first of the S lanes of the group, and as
+    // the pair loop would (the later sample as the candidate)
+    if (sub == 0) {
+#pragma unroll
+      for (int u = 0; u < WT; ++u)
+#pragma unroll
+        for (int w = u + 1; w < WT; ++w)
+          if (live[w]) {
+            WSample<2> o;
+            for (int a = 0; a < 2; ++a) {
+              o.k[a] = x[w][a];
+              o.sc[a][0] = sn[w][a];
+              o.sc[a][1] = cs[w][a];
+            }
+            const double q2 = wq_square(pair_term<2>(o, x[u], sn[u], cs[u], g.R));
+            acc[u] += q2;
+            acc[w] += q2;
+          }
     }
 #pragma unroll
     for (int u = 0; u < WT; ++u) {
