@@ -281,6 +281,21 @@ typedef FTCG_ENUM { FTCG_ACCUM_FIXED = 0, FTCG_ACCUM_F64 = 1 } ftcg_accum;
  * FTCG_EINVAL for values outside these sets. */
 ftcg_status ftcg_plan_set_tuning(ftcg_plan plan, int tile, int accum, int lds_copies);
 
+/* Work layout of the float32 fixed-point spread (Sec. III-A eq:cgmatrix, the
+ * product Omega D fhat), taking effect at the next execute:
+ *   FTCG_SPREAD_AUTO  (the default): on 2D grids with tile 32 and enough tiles
+ *                     (G >= 4096 at sigma = 2), one workgroup walks a segment
+ *                     of 2 tile columns by 4 or 8 tile rows and uses each
+ *                     sample once per segment it reaches; otherwise one
+ *                     workgroup per tile;
+ *   FTCG_SPREAD_TILES : one workgroup per tile on every grid.
+ * Both accumulate the same exact fixed-point taps; they differ by the float
+ * rounding of the carried rows between the segment's steps and by each
+ * step's quantum (under 1e-6 relative on the SAS workloads).
+ * FTCG_EINVAL for other values. */
+typedef enum { FTCG_SPREAD_AUTO = 0, FTCG_SPREAD_TILES = 1 } ftcg_spread_layout;
+ftcg_status ftcg_plan_set_spread_layout(ftcg_plan plan, int layout);
+
 /* Launch shape of the frame-weight sum (Sec. III-C, eq:difopt), taking effect
  * at the next weight computation:
  *   samples_per_lane : 1, 2 or 4 consecutive bin-sorted samples share each

@@ -53,6 +53,7 @@ _SIGS = [
     ("ftcg_plan_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int)]),
     ("ftcg_plan_set_tuning", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    ("ftcg_plan_set_spread_layout", C.c_int, [C.c_void_p, C.c_int]),
     ("ftcg_plan_set_weight_tuning", C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     ("ftcg_plan_enable_timing", C.c_int, [C.c_void_p, C.c_int]),
     ("ftcg_plan_timing", C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),

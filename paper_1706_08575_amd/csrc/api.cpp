@@ -516,6 +516,13 @@ ftcg_status ftcg_plan_set_tuning(ftcg_plan p, int tile, int accum, int lds_copie
   return FTCG_OK;
 }
 
+ftcg_status ftcg_plan_set_spread_layout(ftcg_plan p, int layout) {
+  if (!p) return FTCG_EINVAL;
+  if (layout != FTCG_SPREAD_AUTO && layout != FTCG_SPREAD_TILES) return FTCG_EINVAL;
+  p->spread_segments = layout == FTCG_SPREAD_AUTO;
+  return FTCG_OK;
+}
+
 ftcg_status ftcg_plan_enable_timing(ftcg_plan p, int enable) {
   if (!p) return FTCG_EINVAL;
   p->timing.enabled = enable != 0;

@@ -188,8 +188,12 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tile_count(const double* __restri
   double u[DIM];
   int c[DIM], key[4], l0[4], l1[4];
   sample_keys<DIM>(k, j, m, g, u, c, key, l0, l1);
+  // counts need no result: the leaders' atomics are not waited for
 #pragma unroll
-  for (int q = 0; q < (1 << DIM); ++q) agg_atomic_add(cnt, key[q] < 0 ? 0 : key[q], key[q] >= 0);
+  for (int q = 0; q < (1 << DIM); ++q) {
+    const KeyGroup kg = key_group(key[q], key[q] >= 0);
+    if (kg.leader == (int)__lane_id()) atomicAdd(&cnt[key[q]], kg.size);
+  }
 }
 
 template <int DIM, class real>
@@ -207,9 +211,16 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_tile_scatter(const double* __rest
   r.f0 = (real)(u[0] - (double)c[0]);
   r.f1 = (DIM == 2) ? (real)(u[DIM - 1] - (double)c[DIM - 1]) : (real)0;
   r.src = (int32_t)j;
+  // every slot's groups claim their ranges before any claim is waited for
+  KeyGroup kg[1 << DIM];
+  int base[1 << DIM];
+#pragma unroll
+  for (int q = 0; q < (1 << DIM); ++q) kg[q] = key_group(key[q], key[q] >= 0);
+#pragma unroll
+  for (int q = 0; q < (1 << DIM); ++q) base[q] = group_claim(cursor, key[q], kg[q]);
 #pragma unroll
   for (int q = 0; q < (1 << DIM); ++q) {
-    const int pos = agg_atomic_add(cursor, key[q] < 0 ? 0 : key[q], key[q] >= 0);
+    const int pos = group_slot(base[q], kg[q]);
     if (key[q] >= 0) {
       r.c01 = (int32_t)(((uint32_t)l0[q] & 0xffffu) | ((uint32_t)l1[q] << 16));
       recs[pos] = r;

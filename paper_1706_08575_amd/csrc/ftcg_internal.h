@@ -177,30 +177,49 @@ struct Timing {
 };
 
 // ---------------------------------------------------------------------------
-// wavefront-aggregated counter increment: lanes holding the same key share one
-// global atomic (rasters arrive in acquisition order, so neighbouring lanes
-// usually bin to the same tile); returns this lane's slot. Lanes with
-// valid == false take part in the vote but get -1.
+// Lanes of a wavefront grouped by equal key (rasters arrive in acquisition
+// order, so neighbouring lanes usually bin to the same tile): for each lane
+// the first lane holding its key (the leader) and its rank among the lanes
+// holding it; a leader also gets the group's size. Register-only, one ballot
+// per distinct key. Lanes with valid == false take part in the vote and form
+// no group (leader -1).
 // ---------------------------------------------------------------------------
+struct KeyGroup {
+  int leader, rank, size;
+};
 
-__device__ inline int agg_atomic_add(int32_t* counters, int key, bool valid) {
+__device__ inline KeyGroup key_group(int key, bool valid) {
   unsigned long long todo = __ballot(valid);
   const int lane = __lane_id();
-  int slot = -1;
+  KeyGroup g{-1, 0, 0};
   while (todo) {
     const int leader = __ffsll((long long)todo) - 1;
     const int lkey = __builtin_amdgcn_readlane(key, leader);
     const unsigned long long match = __ballot(valid && key == lkey) & todo;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&counters[lkey], __popcll(match));
-    base = __builtin_amdgcn_readlane(base, leader);
     if ((match >> lane) & 1ull) {
-      const unsigned long long below = match & ((1ull << lane) - 1ull);
-      slot = base + __popcll(below);
+      g.leader = leader;
+      g.rank = __popcll(match & ((1ull << lane) - 1ull));
+      if (lane == leader) g.size = __popcll(match);
     }
     todo &= ~match;
   }
-  return slot;
+  return g;
+}
+
+// The group's leader adds the group's size to counters[key]; the atomics of
+// all groups of the wavefront go out as one instruction, so a wavefront waits
+// for one round trip however many distinct keys it holds.
+__device__ inline int group_claim(int32_t* counters, int key, const KeyGroup& g) {
+  int base = 0;
+  if (g.leader == (int)__lane_id()) base = atomicAdd(&counters[key], g.size);
+  return base;
+}
+
+// this lane's slot from its leader's claim (every lane of the wavefront
+// executes it); -1 for lanes in no group
+__device__ inline int group_slot(int base, const KeyGroup& g) {
+  const int b = __shfl(base, g.leader < 0 ? 0 : g.leader);
+  return g.leader < 0 ? -1 : b + g.rank;
 }
 
 // XCD-aware block order. Workgroups are dealt to the 8 XCDs round-robin
@@ -240,6 +259,7 @@ struct ftcg_plan_s {
   int64_t G = 0;       // grid edge
   double beta = 0.0;   // kernel exp(-beta s^2)
   int tile_req = 0;    // requested tile edge (0 = automatic)
+  bool spread_segments = true;   // segmented float32 spread on large grids (ftcg_plan_set_spread_layout)
   int w_samples = 0;   // frame-weight kernel: samples per lane (0 = automatic)
   int w_lanes = 0;     // frame-weight kernel (2D): lanes per sample group (0 = automatic)
   int lds_copies = 1;

@@ -333,6 +333,317 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Segmented float32 spread for large grids (the same exact fixed-point taps).
+//
+// The tile binning gives every tile the records of all samples whose
+// footprint reaches it, so a sample near a tile edge has records in up to
+// four tiles, and each walks all (2W)^2 taps (1.81 records per sample on the
+// 4096^2 SAS raster at tile 32). Here one workgroup owns a segment of
+// SEG_CW = 2 tile columns (64 cells) by K tile rows and walks its tile rows
+// top to bottom, one step per tile row, taking the records of that row's two
+// tiles. A record is used only in the tile where its sample is at home along
+// the directions the segment covers: along rows, a record from the tile
+// above or below is skipped (its home copy is taken in its own step) except
+// in the segment's first and last step, where the home copy belongs to the
+// next segment; along columns, a record of the left tile whose sample is at
+// home in the right tile is skipped, and the other way round. So every
+// sample is used once per segment it reaches (1.22 records per sample at
+// K = 8 on the same raster).
+//
+// The step's LDS tile spans tile rows -(W-1) .. 32+W-1 (32 + 2W - 1 rows),
+// which holds every tap of the step's home records. After the step, rows
+// -(W-1) .. 31-(W-1) receive nothing more and are written out; the 2W - 1
+// rows below them still receive taps from the next step's records, so they
+// are carried in float (their fixed-point value times the step's quantum)
+// and added to the next step's first 2W - 1 rows. Each step has its own
+// bound B (the fixed-point kernel's rule over the step's records), so the
+// carry is the sum of two exactly accumulated terms in a fixed order:
+// deterministic, with one float rounding more than the tile kernel. Records
+// from the neighbouring segments above and below (first and last step) have
+// rows outside the LDS tile: they take a loop clipped to it.
+// ---------------------------------------------------------------------------
+constexpr int SEG_BLOCK = 512;
+constexpr int SEG_CW = 2;               // tile columns per segment
+constexpr int SEG_T = 32;               // tile edge
+constexpr int SEG_COLS = SEG_CW * SEG_T;
+
+template <int W, bool SUMS>
+__global__ __launch_bounds__(SEG_BLOCK) void k_spread2d_seg(const Rec<float>* __restrict__ recs,
+                                                            const float* __restrict__ alpha_s,
+                                                            const double* __restrict__ wsum,
+                                                            const int32_t* __restrict__ inv,
+                                                            const int32_t* __restrict__ tile_off,
+                                                            const float2* __restrict__ fhat,
+                                                            float2* __restrict__ grid, int64_t G, int nt, int K,
+                                                            float beta) {
+  constexpr int L = 2 * W;
+  constexpr int CROWS = 2 * W - 1;      // carried rows
+  constexpr int ROWS = SEG_T + CROWS;   // LDS tile rows: tile rows -(W-1) .. SEG_T + W - 1
+  constexpr int TP = SEG_COLS + 1;      // row pitch (64-bit words)
+  __shared__ unsigned long long acc[ROWS * TP];
+  __shared__ float2 carry[CROWS * SEG_COLS];
+  __shared__ float2 sf[SEG_BLOCK];      // f0, f1
+  __shared__ int sc[SEG_BLOCK];         // LDS row | LDS column << 16 of the record's first tap
+  __shared__ float2 sv[SEG_BLOCK];      // alpha * fhat
+  __shared__ float red[SEG_BLOCK / 64];
+  __shared__ long long red2[SEG_BLOCK / 64];
+  __shared__ int ncount[2];             // staged home records (from the front), clipped ones (from the back)
+
+  auto weight = [&](int r, int src) -> float {
+    if constexpr (SUMS)
+      return (float)(wscale<2>() / wsum[inv[src]]);
+    else
+      return alpha_s[r];
+  };
+  const int ncs = nt / SEG_CW;
+  const int seg = blockIdx.x / ncs, cs = blockIdx.x - (blockIdx.x / ncs) * ncs;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int col_cell0 = cs * SEG_COLS;
+
+  for (int idx = tid; idx < ROWS * TP; idx += SEG_BLOCK) acc[idx] = 0ull;
+  for (int idx = tid; idx < CROWS * SEG_COLS; idx += SEG_BLOCK) carry[idx] = make_float2(0.f, 0.f);
+
+  // record r of the step's two tiles [rb, rm) [rm, re): kept?, clipped?, and
+  // the LDS position of its first tap
+  struct Kept {
+    bool keep, clip;
+    int packed;
+  };
+  auto classify = [&](int r, int rm, int t, int c01) -> Kept {
+    const int cc = r >= rm ? 1 : 0;
+    const int l0 = (int)(int16_t)(c01 & 0xffff);
+    const int l1 = c01 >> 16;
+    const bool home0 = l0 >= 0 && l0 < SEG_T;
+    const bool vk = home0 || (t == 0 && l0 < 0) || (t == K - 1 && l0 >= SEG_T);
+    const bool hk = cc ? (l1 >= 0) : (l1 < SEG_T);
+    Kept k;
+    k.keep = vk && hk;
+    k.clip = !home0;
+    // LDS row of the first tap: tile row l0 - W + 1, LDS row 0 = tile row -(W-1)
+    const int row0 = l0;
+    const int col0 = l1 + cc * SEG_T - W + 1;
+    k.packed = (int)(((uint32_t)row0 & 0xffffu) | ((uint32_t)col0 << 16));
+    return k;
+  };
+  // stage one record (compacted: home records from the front, clipped ones
+  // from the back of the stage)
+  auto stage = [&](bool keep, bool clip, float f0, float f1, int packed, float2 c) {
+    const unsigned long long bh = __ballot(keep && !clip), bc = __ballot(keep && clip);
+    int baseh = 0, basec = 0;
+    if (lane == 0) {
+      if (bh) baseh = atomicAdd(&ncount[0], __popcll(bh));
+      if (bc) basec = atomicAdd(&ncount[1], __popcll(bc));
+    }
+    baseh = __shfl(baseh, 0);
+    basec = __shfl(basec, 0);
+    if (keep) {
+      const unsigned long long mine = clip ? bc : bh;
+      const int rank = __popcll(mine & ((1ull << lane) - 1ull));
+      const int slot = clip ? SEG_BLOCK - 1 - (basec + rank) : baseh + rank;
+      sf[slot] = make_float2(f0, f1);
+      sc[slot] = packed;
+      sv[slot] = c;
+    }
+  };
+
+  const float e2b = __expf(-2.f * beta);
+  constexpr int RPW = 64 / L;
+  const int s = lane / L, i = lane - (lane / L) * L;
+  constexpr int NWAVES = SEG_BLOCK / 64;
+
+  for (int t = 0; t < K; ++t) {
+    const int trow = seg * K + t;
+    const int key = trow * nt + cs * SEG_CW;
+    const int rb = tile_off[key], rm = tile_off[key + 1], re = tile_off[key + 2];
+    if (tid < 2) ncount[tid] = 0;
+    __syncthreads();
+    // pass 1: largest |component| of alpha * fhat over the kept records; the
+    // first chunk of SEG_BLOCK records is staged
+    float mx = 0.f;
+    for (int cb = rb; cb < re; cb += SEG_BLOCK) {
+      const int r = cb + tid;
+      bool keep = false, clip = false;
+      float2 c = make_float2(0.f, 0.f);
+      float f0 = 0.f, f1 = 0.f;
+      int packed = 0;
+      if (r < re) {
+        const Rec<float> rec = recs[r];
+        const Kept k = classify(r, rm, t, rec.c01);
+        keep = k.keep;
+        clip = k.clip;
+        packed = k.packed;
+        if (keep) {
+          const float a = weight(r, rec.src);
+          const float2 v = fhat[rec.src];
+          c = make_float2(v.x * a, v.y * a);
+          f0 = rec.f0;
+          f1 = rec.f1;
+          mx = (isfinite(c.x) && isfinite(c.y)) ? fmaxf(mx, fmaxf(fabsf(c.x), fabsf(c.y))) : __builtin_inff();
+        }
+      }
+      if (cb == rb) stage(keep, clip, f0, f1, packed, c);
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if (lane == 0) red[wave] = mx;
+    __syncthreads();
+    mx = 0.f;
+#pragma unroll
+    for (int w = 0; w < NWAVES; ++w) mx = fmaxf(mx, red[w]);
+    const bool bad = !isfinite(mx);
+    float scale = 0.f, unscale = 0.f;
+    if (mx > 0.f && !bad) {
+      // pass 2: integer sum of each kept record's bound in units of 2^-20 mx
+      const float qs = 1048576.f / mx;
+      const int nh = ncount[0], ncl = ncount[1];
+      long long qsum = 0;
+      for (int q = tid; q < nh; q += SEG_BLOCK) {
+        const float2 c = sv[q];
+        qsum += (long long)ceilf(fmaxf(fabsf(c.x), fabsf(c.y)) * qs) + 1;
+      }
+      for (int q = tid; q < ncl; q += SEG_BLOCK) {
+        const float2 c = sv[SEG_BLOCK - 1 - q];
+        qsum += (long long)ceilf(fmaxf(fabsf(c.x), fabsf(c.y)) * qs) + 1;
+      }
+      for (int cb = rb + SEG_BLOCK; cb < re; cb += SEG_BLOCK) {
+        const int r = cb + tid;
+        if (r < re) {
+          const Rec<float> rec = recs[r];
+          if (classify(r, rm, t, rec.c01).keep) {
+            const float a = weight(r, rec.src);
+            const float2 v = fhat[rec.src];
+            qsum += (long long)ceilf(fmaxf(fabsf(v.x * a), fabsf(v.y * a)) * qs) + 1;
+          }
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) qsum += __shfl_xor(qsum, off);
+      __syncthreads();
+      if (lane == 0) red2[wave] = qsum;
+      __syncthreads();
+      qsum = 0;
+#pragma unroll
+      for (int w = 0; w < NWAVES; ++w) qsum += red2[w];
+      const float bound = (float)((double)qsum * (double)mx * (1.0 / 1048576.0) * (1.0 + 1e-6));
+      scale = (2147483648.f - 16777216.f) / bound;
+      unscale = bound / (2147483648.f - 16777216.f);
+
+      // one record's taps: lane i takes LDS column col0 + i, rows row0 .. row0
+      // + 2W - 1 (clipped to the LDS tile when clip)
+      auto splat = [&](float2 f, int packed, float2 c, bool clip) {
+        const int col = (packed >> 16) + i;
+        if (col < 0 || col >= SEG_COLS) return;
+        const int row0 = (int)(int16_t)(packed & 0xffff);
+        const float d1 = (float)(i - W + 1) - f.y;
+        int j0 = 0, j1 = L;
+        if (clip) {
+          j0 = max(0, -row0);
+          j1 = min(L, ROWS - row0);
+        }
+        const float d0 = (float)(1 - W + j0) - f.x;
+        const float w10 = __expf(-beta * (d1 * d1 + d0 * d0)) * scale;
+        float q = __expf(-beta * (2.f * d0 + 1.f));
+        float pr = c.x * w10, pi = c.y * w10;
+        unsigned long long* dst = acc + (row0 + j0) * TP + col;
+        if (!clip) {
+#pragma unroll
+          for (int j = 0; j < L; ++j) {
+            __hip_atomic_fetch_add(dst + j * TP, fx_pack(pr, pi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            pr *= q;
+            pi *= q;
+            q *= e2b;
+          }
+        } else {
+          for (int j = j0; j < j1; ++j) {
+            __hip_atomic_fetch_add(dst, fx_pack(pr, pi), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            dst += TP;
+            pr *= q;
+            pi *= q;
+            q *= e2b;
+          }
+        }
+      };
+      // taps of the staged records: home ones, then clipped ones
+      auto taps = [&]() {
+        const int nh = ncount[0], ncl = ncount[1];
+        for (int base = wave * RPW; base < nh; base += NWAVES * RPW) {
+          const int r = base + s;
+          if (s < RPW && r < nh) splat(sf[r], sc[r], sv[r], false);
+        }
+        for (int base = wave * RPW; base < ncl; base += NWAVES * RPW) {
+          const int r = base + s;
+          if (s < RPW && r < ncl) {
+            const int q = SEG_BLOCK - 1 - r;
+            splat(sf[q], sc[q], sv[q], true);
+          }
+        }
+      };
+      taps();
+      for (int cb = rb + SEG_BLOCK; cb < re; cb += SEG_BLOCK) {
+        __syncthreads();   // every wavefront has left the previous chunk
+        if (tid < 2) ncount[tid] = 0;
+        __syncthreads();
+        const int r = cb + tid;
+        bool keep = false, clip = false;
+        float2 c = make_float2(0.f, 0.f);
+        float f0 = 0.f, f1 = 0.f;
+        int packed = 0;
+        if (r < re) {
+          const Rec<float> rec = recs[r];
+          const Kept k = classify(r, rm, t, rec.c01);
+          keep = k.keep;
+          clip = k.clip;
+          packed = k.packed;
+          if (keep) {
+            const float a = weight(r, rec.src);
+            const float2 v = fhat[rec.src];
+            c = make_float2(v.x * a, v.y * a);
+            f0 = rec.f0;
+            f1 = rec.f1;
+          }
+        }
+        stage(keep, clip, f0, f1, packed, c);
+        __syncthreads();
+        taps();
+      }
+    }
+    __syncthreads();
+    // write the rows that are final, carry the 2W - 1 rows below them
+    const int bmin = t == 0 ? W - 1 : 0;
+    const int bmax = t == K - 1 ? SEG_T + W - 1 : SEG_T;
+    const int64_t row_cell0 = (int64_t)trow * SEG_T - (W - 1);
+    const float fill = bad ? __builtin_nanf("") : 0.f;
+    for (int idx = tid; idx < bmax * SEG_COLS; idx += SEG_BLOCK) {
+      const int b = idx / SEG_COLS, col = idx - (idx / SEG_COLS) * SEG_COLS;
+      float2 o;
+      {
+        const unsigned long long vv = acc[b * TP + col];
+        const int re_ = (int)(unsigned)(vv & 0xffffffffull);
+        const int im_ = (int)((long long)(vv - (unsigned long long)(long long)re_) >> 32);
+        o.x = bad ? fill : (float)re_ * unscale;
+        o.y = bad ? fill : (float)im_ * unscale;
+      }
+      if (b < CROWS) {
+        const float2 cy = carry[b * SEG_COLS + col];
+        o.x += cy.x;
+        o.y += cy.y;
+        if (t < K - 1) {
+          const unsigned long long vv = acc[(SEG_T + b) * TP + col];
+          const int re_ = (int)(unsigned)(vv & 0xffffffffull);
+          const int im_ = (int)((long long)(vv - (unsigned long long)(long long)re_) >> 32);
+          float2 nc;
+          nc.x = bad ? fill : (float)re_ * unscale;
+          nc.y = bad ? fill : (float)im_ * unscale;
+          carry[b * SEG_COLS + col] = nc;
+        }
+      }
+      if (b >= bmin) grid[(row_cell0 + b) * G + col_cell0 + col] = o;
+    }
+    __syncthreads();
+    if (t + 1 < K)
+      for (int idx = tid; idx < ROWS * TP; idx += SEG_BLOCK) acc[idx] = 0ull;
+  }
+}
+
 // 1D: one thread per record walks its 2W taps
 template <class real, int W>
 __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread1d(const Rec<real>* __restrict__ recs,
@@ -398,8 +709,42 @@ static void launch_fx(ftcg_plan p, const void* fhat, void* grid) {
                        p->G, (int)p->nt, (float)p->beta);
 }
 
+// segments of K tile rows for the segmented kernel on grids with enough of
+// them to fill the chip (at least 2048 workgroups), else 0 (the tile kernel)
+static int spread_segment_rows(const ftcg_plan_s* p) {
+  if (p->dim != 2 || p->dtype != FTCG_F32 || p->accum != ACCUM_FIXED || p->tile != SEG_T) return 0;
+  const int64_t nt = p->nt;
+  if (nt % SEG_CW != 0) return 0;
+  for (int K : {8, 4})
+    if (nt % K == 0 && (nt / SEG_CW) * (nt / K) >= 2048) return K;
+  return 0;
+}
+
+template <int W>
+static void launch_seg(ftcg_plan p, const void* fhat, void* grid, int K) {
+  const unsigned nb = (unsigned)((p->nt / SEG_CW) * (p->nt / K));
+  if (p->weights_deferred)
+    hipLaunchKernelGGL((k_spread2d_seg<W, true>), dim3(nb), dim3(SEG_BLOCK), 0, p->stream, p->recs.as<Rec<float>>(),
+                       p->alpha_s.as<float>(), p->ws_sum.as<double>(), p->ws_inv.as<int32_t>(),
+                       p->tile_off.as<int32_t>(), static_cast<const float2*>(fhat), static_cast<float2*>(grid), p->G,
+                       (int)p->nt, K, (float)p->beta);
+  else
+    hipLaunchKernelGGL((k_spread2d_seg<W, false>), dim3(nb), dim3(SEG_BLOCK), 0, p->stream,
+                       p->recs.as<Rec<float>>(), p->alpha_s.as<float>(), nullptr, nullptr, p->tile_off.as<int32_t>(),
+                       static_cast<const float2*>(fhat), static_cast<float2*>(grid), p->G, (int)p->nt, K,
+                       (float)p->beta);
+}
+
 template <int W>
 static void launch_fx_t(ftcg_plan p, const void* fhat, void* grid) {
+  if (p->spread_segments) {
+    const int K = spread_segment_rows(p);
+    if (K > 0) {
+      launch_seg<W>(p, fhat, grid, K);
+      FTCG_HIP(hipGetLastError());
+      return;
+    }
+  }
   switch (p->tile) {
     case 16: launch_fx<W, 16>(p, fhat, grid); break;
     case 32: launch_fx<W, 32>(p, fhat, grid); break;

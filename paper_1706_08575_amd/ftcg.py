@@ -165,6 +165,12 @@ class Plan:
         a = {"fixed": L.FTCG_ACCUM_FIXED, "f64": L.FTCG_ACCUM_F64}[accum]
         L.check(L.call("ftcg_plan_set_tuning", self._h, int(tile), a, int(lds_copies)), "ftcg_plan_set_tuning")
 
+    def set_spread_layout(self, layout: str = "auto") -> None:
+        """"auto" (segments of tile rows on large float32 grids) or "tiles"
+        (one workgroup per tile); applies from the next execute."""
+        v = {"auto": 0, "tiles": 1}[layout]
+        L.check(L.call("ftcg_plan_set_spread_layout", self._h, v), "ftcg_plan_set_spread_layout")
+
     def set_weight_tuning(self, samples_per_lane: int = 0, lanes_per_group: int = 0) -> None:
         """Launch shape of the frame-weight kernel (0 = automatic); applies
         from the next weight computation."""
