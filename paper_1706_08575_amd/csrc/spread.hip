@@ -302,8 +302,12 @@ __global__ __launch_bounds__(SPREAD_BLOCK) void k_spread2d_fx(const Rec<float>* 
         }
         __syncthreads();
       }
-      for (int base = wave * RPW; base < cn; base += NWAVES * RPW) {
-        const int r = base + s;
+      // the RPW records of one pass are cn / RPW apart in the chunk: records
+      // next to each other come from neighbouring samples of one pulse, whose
+      // footprints overlap, and in one pass they would meet on the same LDS banks
+      const int np = (cn + RPW - 1) / RPW;
+      for (int pass = wave; pass < np; pass += NWAVES) {
+        const int r = s * np + pass;
         if (s < RPW && r < cn) {
           const float4 g4 = sgeo[r];
           splat(g4.x, g4.y, __float_as_int(g4.z), g4.w, sval[r]);
@@ -562,15 +566,19 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_spread2d_seg(const Rec<float>* __
           }
         }
       };
-      // taps of the staged records: home ones, then clipped ones
+      // taps of the staged records: home ones, then clipped ones; the RPW
+      // records of one pass are n / RPW apart (neighbouring samples of a pulse
+      // overlap and would meet on the same LDS banks)
       auto taps = [&]() {
         const int nh = ncount[0], ncl = ncount[1];
-        for (int base = wave * RPW; base < nh; base += NWAVES * RPW) {
-          const int r = base + s;
+        const int nph = (nh + RPW - 1) / RPW;
+        for (int pass = wave; pass < nph; pass += NWAVES) {
+          const int r = s * nph + pass;
           if (s < RPW && r < nh) splat(sf[r], sc[r], sv[r], false);
         }
-        for (int base = wave * RPW; base < ncl; base += NWAVES * RPW) {
-          const int r = base + s;
+        const int npc = (ncl + RPW - 1) / RPW;
+        for (int pass = wave; pass < npc; pass += NWAVES) {
+          const int r = s * npc + pass;
           if (s < RPW && r < ncl) {
             const int q = SEG_BLOCK - 1 - r;
             splat(sf[q], sc[q], sv[q], true);
