@@ -112,6 +112,167 @@ static void run_learned_with_audit(ftcg_plan p, const double* k_dev) {
   if (p->used_fallback) run_plain_weights(p);
 }
 
+namespace ftcg {
+
+// set_points in two parts, so that a batch can enqueue the input checks of
+// all its items before the host waits for the first of them.
+// set_points_begin enqueues the input check and the binning passes that need
+// no host decision (its state is kept in p->pending);
+void set_points_begin(ftcg_plan p, int64_t m, const double* k_dev) {
+  p->have_points = false;
+  p->have_weights = false;
+  p->finish_recs = false;
+  p->weights_deferred = false;
+  p->m = m;
+  // 1) input check: finiteness, bounding box and the neighbour-bin
+  //    geometry, reduced on the device; the check also zeroes the tile and
+  //    bin-row counters of the binning passes
+  timing_begin(p, STEP_BIN);
+  int32_t* zero_ptr = nullptr;
+  int64_t zero_n = 0;
+  if (!p->weights_only) {
+    setup_tiles(p);
+    p->tile_cnt.ensure(sizeof(int32_t) * (p->ntiles + 1));
+    zero_ptr = p->tile_cnt.as<int32_t>();
+    zero_n = p->ntiles + 1;
+  }
+  const bool band = p->wmode == FTCG_W_BAND;
+  const bool rows2d = p->dim == 2 && (p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED || band);
+  int32_t* zero_b = nullptr;
+  int64_t zero_nb = 0;
+  if (rows2d) {
+    p->wb_cnt.ensure(sizeof(int32_t) * WROW_CNT_ZERO);
+    zero_b = p->wb_cnt.as<int32_t>();
+    zero_nb = WROW_CNT_ZERO;
+  }
+  auto* part = p->check_part.as<unsigned long long>();
+  const int nparts = launch_check_points(p, k_dev, m, part, zero_ptr, zero_n, zero_b, zero_nb);
+  const int seq = ++p->check_seq;
+  p->pending.seq = seq;
+  launch_check_reduce(p, part, nparts, seq);
+  timing_end(p, STEP_BIN);
+  FTCG_HIP(hipEventRecord(p->ev_check, p->stream));
+  // 2) binning passes that need no host decision are enqueued before the
+  //    host waits for the check, and run during the host's turn (their
+  //    kernels keep every index in range for any input; rejected points
+  //    are reported below):
+  //    - 2D weights, tile counters in LDS: tile records and bin rows fused;
+  //    - otherwise the tile binning: whole when its counters fit LDS, else
+  //      the counting + scan (the tile scatter writes the weights with the
+  //      records later; there these passes outlast the host's turn, and
+  //      the bin rows follow it).
+  //    Records written here get their weights once those are known.
+  const bool tiles = !p->weights_only;
+  const bool early_scatter = tiles && tile_keys_in_lds(p);
+  const bool fused = rows2d && early_scatter;
+  const int64_t cap = m << p->dim;  // worst case 2^dim tile records per sample
+  if (tiles) {
+    p->recs.ensure((p->dtype == FTCG_F64 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * cap);
+    p->alpha_s.ensure((p->dtype == FTCG_F64 ? sizeof(double) : sizeof(float)) * cap);
+    p->tile_off.ensure(sizeof(int32_t) * (p->ntiles + 1));
+    p->tile_scan_tmp.ensure(scan_tmp_bytes(p->ntiles));
+  }
+  if (rows2d) {
+    p->wb_rowoff.ensure(sizeof(int32_t) * (WROW_MAX + 1));
+    p->wb_rowbuf.ensure(sizeof(RowRec) * m);
+    p->scan_tmp.ensure(scan_tmp_bytes(WROW_MAX));
+  }
+  if (fused) {
+    timing_begin(p, STEP_BIN);
+    bin_points_fused(p, k_dev);
+    timing_end(p, STEP_BIN);
+  } else if (tiles) {
+    timing_begin(p, STEP_BIN);
+    if (early_scatter)
+      bin_points_k(p, k_dev);   // weight 1 until the weights are known
+    else
+      bin_count_k(p, k_dev);
+    timing_end(p, STEP_BIN);
+  }
+  p->pending.tiles = tiles;
+  p->pending.early_scatter = early_scatter;
+  p->pending.fused = fused;
+  p->pending.band = band;
+}
+
+// set_points_end waits for the check (host), then enqueues the weights and the
+// rest of the binning
+void set_points_end(ftcg_plan p, const double* k_dev) {
+  const int64_t m = p->m;
+  const int seq = p->pending.seq;
+  const bool tiles = p->pending.tiles, early_scatter = p->pending.early_scatter, fused = p->pending.fused;
+  const bool band = p->pending.band;
+  FTCG_HIP(hipEventSynchronize(p->ev_check));
+  const CheckOut chk = *p->host_geo;
+  if (chk.seq != seq) throw StatusError{FTCG_EHIP};   // the result of an earlier call: not visible yet
+  if (chk.bad) throw StatusError{FTCG_EINVAL};
+  p->wgeom = chk.g;
+  // 3) weights (caller order)
+  p->alpha.ensure(sizeof(double) * m);
+  const bool computed = p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED;
+  // records already written, 2D plain weights: the symmetric sum's finish
+  // is deferred (the fixed-point spread forms the records' weights from the
+  // sums through the caller-to-bin map the bin sort then writes;
+  // finish_deferred_weights serves every other reader)
+  const bool want_finish = early_scatter && p->dim == 2 && p->wmode == FTCG_W_PLAIN;
+  if (computed || band) {
+    if (p->wmode == FTCG_W_LEARNED && !p->mlp) throw StatusError{FTCG_ESTATE};
+    p->finish_recs = want_finish;
+    if (p->dim == 2) {
+      setup_weight_bins(p);
+      timing_begin(p, STEP_WBIN);
+      if (!fused) wrow_bin(p, k_dev, p->wgeom.nb[0]);
+      sort_weight_rows(p);
+      timing_end(p, STEP_WBIN);
+      p->have_wbins = true;
+    } else {
+      build_weight_bins_1d(p, k_dev);
+    }
+    if (p->wmode == FTCG_W_PLAIN) {
+      run_plain_weights(p);
+    } else if (band) {
+      // the records carry weight 1; C is applied to the values before the
+      // spread (execute)
+      fill_ones(p->alpha.as<double>(), m, p->stream);
+      run_band_weights(p);
+    } else {
+      run_learned_with_audit(p, k_dev);
+    }
+    p->have_weights = true;
+  } else if (p->wmode == FTCG_W_NONE) {
+    fill_ones(p->alpha.as<double>(), m, p->stream);
+    p->have_weights = true;
+  }
+  // 4) the records' weights
+  if (tiles) {
+    const bool finished = want_finish && !p->finish_recs;
+    if (!early_scatter) {
+      timing_begin(p, STEP_BIN);
+      bin_scatter_k(p, k_dev);   // with the weights when there are any
+      timing_end(p, STEP_BIN);
+    } else if ((computed || band) && !finished) {
+      timing_begin(p, STEP_BIN);
+      refill_alpha_dev(p);
+      timing_end(p, STEP_BIN);
+    }
+  }
+  // 5) iterative density compensation: spreads and interpolates through
+  //    the records just written (weight 1), then gives them its weights
+  if (p->wmode == FTCG_W_DENSITY) {
+    if (!tiles) throw StatusError{FTCG_EUNSUPPORTED};
+    run_density_weights(p);
+    p->have_weights = true;
+    timing_begin(p, STEP_BIN);
+    refill_alpha_dev(p);
+    timing_end(p, STEP_BIN);
+  }
+  p->finish_recs = false;
+  p->nrec = -1;  // on the device (tile_off[ntiles]); read only when asked for
+  p->have_points = true;
+}
+
+}  // namespace ftcg
+
 extern "C" {
 
 const char* ftcg_status_string(ftcg_status s) {
@@ -214,142 +375,8 @@ ftcg_status ftcg_set_points(ftcg_plan p, int64_t m, const double* k_dev) {
   if (!p || !k_dev) return FTCG_EINVAL;
   if (m < 1 || m >= (int64_t(1) << 31)) return FTCG_EINVAL;
   return guarded([&] {
-    p->have_points = false;
-    p->have_weights = false;
-    p->finish_recs = false;
-    p->weights_deferred = false;
-    p->m = m;
-    // 1) input check: finiteness, bounding box and the neighbour-bin
-    //    geometry, reduced on the device; the check also zeroes the tile and
-    //    bin-row counters of the binning passes
-    timing_begin(p, STEP_BIN);
-    int32_t* zero_ptr = nullptr;
-    int64_t zero_n = 0;
-    if (!p->weights_only) {
-      setup_tiles(p);
-      p->tile_cnt.ensure(sizeof(int32_t) * (p->ntiles + 1));
-      zero_ptr = p->tile_cnt.as<int32_t>();
-      zero_n = p->ntiles + 1;
-    }
-    const bool band = p->wmode == FTCG_W_BAND;
-    const bool rows2d = p->dim == 2 && (p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED || band);
-    int32_t* zero_b = nullptr;
-    int64_t zero_nb = 0;
-    if (rows2d) {
-      p->wb_cnt.ensure(sizeof(int32_t) * WROW_CNT_ZERO);
-      zero_b = p->wb_cnt.as<int32_t>();
-      zero_nb = WROW_CNT_ZERO;
-    }
-    auto* part = p->check_part.as<unsigned long long>();
-    const int nparts = launch_check_points(p, k_dev, m, part, zero_ptr, zero_n, zero_b, zero_nb);
-    const int seq = ++p->check_seq;
-    launch_check_reduce(p, part, nparts, seq);
-    timing_end(p, STEP_BIN);
-    FTCG_HIP(hipEventRecord(p->ev_check, p->stream));
-    // 2) binning passes that need no host decision are enqueued before the
-    //    host waits for the check, and run during the host's turn (their
-    //    kernels keep every index in range for any input; rejected points
-    //    are reported below):
-    //    - 2D weights, tile counters in LDS: tile records and bin rows fused;
-    //    - otherwise the tile binning: whole when its counters fit LDS, else
-    //      the counting + scan (the tile scatter writes the weights with the
-    //      records later; there these passes outlast the host's turn, and
-    //      the bin rows follow it).
-    //    Records written here get their weights once those are known.
-    const bool tiles = !p->weights_only;
-    const bool early_scatter = tiles && tile_keys_in_lds(p);
-    const bool fused = rows2d && early_scatter;
-    const int64_t cap = m << p->dim;  // worst case 2^dim tile records per sample
-    if (tiles) {
-      p->recs.ensure((p->dtype == FTCG_F64 ? sizeof(Rec<double>) : sizeof(Rec<float>)) * cap);
-      p->alpha_s.ensure((p->dtype == FTCG_F64 ? sizeof(double) : sizeof(float)) * cap);
-      p->tile_off.ensure(sizeof(int32_t) * (p->ntiles + 1));
-      p->tile_scan_tmp.ensure(scan_tmp_bytes(p->ntiles));
-    }
-    if (rows2d) {
-      p->wb_rowoff.ensure(sizeof(int32_t) * (WROW_MAX + 1));
-      p->wb_rowbuf.ensure(sizeof(RowRec) * m);
-      p->scan_tmp.ensure(scan_tmp_bytes(WROW_MAX));
-    }
-    if (fused) {
-      timing_begin(p, STEP_BIN);
-      bin_points_fused(p, k_dev);
-      timing_end(p, STEP_BIN);
-    } else if (tiles) {
-      timing_begin(p, STEP_BIN);
-      if (early_scatter)
-        bin_points_k(p, k_dev);   // weight 1 until the weights are known
-      else
-        bin_count_k(p, k_dev);
-      timing_end(p, STEP_BIN);
-    }
-    FTCG_HIP(hipEventSynchronize(p->ev_check));
-    const CheckOut chk = *p->host_geo;
-    if (chk.seq != seq) throw StatusError{FTCG_EHIP};   // the result of an earlier call: not visible yet
-    if (chk.bad) throw StatusError{FTCG_EINVAL};
-    p->wgeom = chk.g;
-    // 3) weights (caller order)
-    p->alpha.ensure(sizeof(double) * m);
-    const bool computed = p->wmode == FTCG_W_PLAIN || p->wmode == FTCG_W_LEARNED;
-    // records already written, 2D plain weights: the symmetric sum's finish
-    // is deferred (the fixed-point spread forms the records' weights from the
-    // sums through the caller-to-bin map the bin sort then writes;
-    // finish_deferred_weights serves every other reader)
-    const bool want_finish = early_scatter && p->dim == 2 && p->wmode == FTCG_W_PLAIN;
-    if (computed || band) {
-      if (p->wmode == FTCG_W_LEARNED && !p->mlp) throw StatusError{FTCG_ESTATE};
-      p->finish_recs = want_finish;
-      if (p->dim == 2) {
-        setup_weight_bins(p);
-        timing_begin(p, STEP_WBIN);
-        if (!fused) wrow_bin(p, k_dev, p->wgeom.nb[0]);
-        sort_weight_rows(p);
-        timing_end(p, STEP_WBIN);
-        p->have_wbins = true;
-      } else {
-        build_weight_bins_1d(p, k_dev);
-      }
-      if (p->wmode == FTCG_W_PLAIN) {
-        run_plain_weights(p);
-      } else if (band) {
-        // the records carry weight 1; C is applied to the values before the
-        // spread (execute)
-        fill_ones(p->alpha.as<double>(), m, p->stream);
-        run_band_weights(p);
-      } else {
-        run_learned_with_audit(p, k_dev);
-      }
-      p->have_weights = true;
-    } else if (p->wmode == FTCG_W_NONE) {
-      fill_ones(p->alpha.as<double>(), m, p->stream);
-      p->have_weights = true;
-    }
-    // 4) the records' weights
-    if (tiles) {
-      const bool finished = want_finish && !p->finish_recs;
-      if (!early_scatter) {
-        timing_begin(p, STEP_BIN);
-        bin_scatter_k(p, k_dev);   // with the weights when there are any
-        timing_end(p, STEP_BIN);
-      } else if ((computed || band) && !finished) {
-        timing_begin(p, STEP_BIN);
-        refill_alpha_dev(p);
-        timing_end(p, STEP_BIN);
-      }
-    }
-    // 5) iterative density compensation: spreads and interpolates through
-    //    the records just written (weight 1), then gives them its weights
-    if (p->wmode == FTCG_W_DENSITY) {
-      if (!tiles) throw StatusError{FTCG_EUNSUPPORTED};
-      run_density_weights(p);
-      p->have_weights = true;
-      timing_begin(p, STEP_BIN);
-      refill_alpha_dev(p);
-      timing_end(p, STEP_BIN);
-    }
-    p->finish_recs = false;
-    p->nrec = -1;  // on the device (tile_off[ntiles]); read only when asked for
-    p->have_points = true;
+    set_points_begin(p, m, k_dev);
+    set_points_end(p, k_dev);
   });
 }
 

@@ -67,11 +67,30 @@ void enqueue_execute(ftcg_batch_s* b, hipStream_t s) {
 // build the tile and task tables from the item plans' tile offsets
 void build_tables(ftcg_batch_s* b) {
   std::vector<BatchTile> tiles;
-  std::vector<int32_t> off;
+  // every item's tile offsets in one pinned buffer, one wait for all of them
+  size_t need = 0;
+  for (ftcg_plan p : b->plans) need += (size_t)p->ntiles + 1;
+  if (need > b->host_off_len) {
+    if (b->host_off) FTCG_HIP(hipHostFree(b->host_off));
+    b->host_off = nullptr;
+    b->host_off_len = 0;
+    FTCG_HIP(hipHostMalloc((void**)&b->host_off, sizeof(int32_t) * need, hipHostMallocDefault));
+    b->host_off_len = need;
+  }
+  {
+    size_t at = 0;
+    for (ftcg_plan p : b->plans) {
+      FTCG_HIP(hipMemcpyAsync(b->host_off + at, p->tile_off.p, sizeof(int32_t) * (p->ntiles + 1),
+                              hipMemcpyDeviceToHost, b->stream));
+      at += (size_t)p->ntiles + 1;
+    }
+    FTCG_HIP(hipStreamSynchronize(b->stream));
+  }
+  size_t at = 0;
   for (int i = 0; i < b->n_items; ++i) {
     ftcg_plan p = b->plans[i];
-    off.resize(p->ntiles + 1);
-    FTCG_HIP(hipMemcpy(off.data(), p->tile_off.p, sizeof(int32_t) * (p->ntiles + 1), hipMemcpyDeviceToHost));
+    const int32_t* off = b->host_off + at;
+    at += (size_t)p->ntiles + 1;
     for (int64_t t = 0; t < p->ntiles; ++t) {
       BatchTile tl;
       tl.item = i;
@@ -163,6 +182,11 @@ ftcg_status ftcg_batch_create(ftcg_batch_s** out, int n_items, const int64_t* n,
     FTCG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     b->persistent_blocks = ncu * 8;
     batch_fft_prepare();
+    for (int q = 0; q < ftcg_batch_s::BATCH_STREAMS; ++q) {
+      FTCG_HIP(hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking));
+      FTCG_HIP(hipEventCreateWithFlags(&b->ev_side[q], hipEventDisableTiming));
+    }
+    FTCG_HIP(hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming));
     for (int i = 0; i < n_items; ++i) {
       ftcg_plan p = nullptr;
       const int64_t nn[2] = {n[i], n[i]};
@@ -229,6 +253,15 @@ ftcg_status ftcg_batch_destroy(ftcg_batch_s* b) {
   DevBuf* bufs[] = {&b->items_dev, &b->tiles, &b->tasks, &b->bounds, &b->scratch, &b->split_tiles, &b->counter,
                     &b->args_dev, &b->grid, &b->tmp, &b->deapod, &b->group_items, &b->twiddle};
   for (DevBuf* d : bufs) d->release();
+  for (int q = 0; q < ftcg_batch_s::BATCH_STREAMS; ++q) {
+    if (b->side[q]) {
+      (void)hipStreamSynchronize(b->side[q]);
+      (void)hipStreamDestroy(b->side[q]);
+    }
+    if (b->ev_side[q]) (void)hipEventDestroy(b->ev_side[q]);
+  }
+  if (b->ev_start) (void)hipEventDestroy(b->ev_start);
+  if (b->host_off) (void)hipHostFree(b->host_off);
   delete b;
   return FTCG_OK;
 }
@@ -267,20 +300,63 @@ ftcg_status ftcg_batch_set_points(ftcg_batch_s* b, const int64_t* m_host, const 
   if (!b || !m_host || !k_dev) return FTCG_EINVAL;
   for (int i = 0; i < b->n_items; ++i)
     if (m_host[i] < 1 || m_host[i] >= (int64_t(1) << 31)) return FTCG_EINVAL;
+  constexpr int NS = ftcg_batch_s::BATCH_STREAMS;
+  // the items' plans enqueue on the side streams for the duration of the
+  // call, and on the batch stream again afterwards, also after an error
+  struct Restore {
+    ftcg_batch_s* b;
+    ~Restore() {
+      for (ftcg_plan p : b->plans) p->stream = b->stream;
+    }
+  } restore{b};
   return guard([&] {
     b->have_points = false;
     drop_graph(b);
-    int64_t off = 0, grid = 0, tmp = 0, img = 0, dp = 0;
+    // the side streams start after the work already on the batch stream (a
+    // previous execute may still read the records rewritten here)
+    FTCG_HIP(hipEventRecord(b->ev_start, b->stream));
+    for (int q = 0; q < NS; ++q) FTCG_HIP(hipStreamWaitEvent(b->side[q], b->ev_start, 0));
+    // items to streams, largest first onto the least loaded (by samples)
+    std::vector<int> order(b->n_items);
+    for (int i = 0; i < b->n_items; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return m_host[x] > m_host[y]; });
+    int64_t load[NS] = {};
+    std::vector<int64_t> off(b->n_items);
+    {
+      int64_t o = 0;
+      for (int i = 0; i < b->n_items; ++i) {
+        off[i] = o;
+        o += m_host[i];
+      }
+      b->m_total = o;
+    }
+    for (int i : order) {
+      int q = 0;
+      for (int r = 1; r < NS; ++r)
+        if (load[r] < load[q]) q = r;
+      load[q] += m_host[i];
+      b->plans[i]->stream = b->side[q];
+    }
+    // every item's input check and early binning, then the rest of each
+    // item once the host has read its check
+    for (int i : order) set_points_begin(b->plans[i], m_host[i], k_dev + 2 * off[i]);
+    for (int i : order) {
+      ftcg_plan p = b->plans[i];
+      set_points_end(p, k_dev + 2 * off[i]);
+      finish_deferred_weights(p);   // the batched spread reads the records' weights
+    }
+    for (int q = 0; q < NS; ++q) {
+      FTCG_HIP(hipEventRecord(b->ev_side[q], b->side[q]));
+      FTCG_HIP(hipStreamWaitEvent(b->stream, b->ev_side[q], 0));
+    }
+    int64_t grid = 0, tmp = 0, img = 0, dp = 0;
     for (int i = 0; i < b->n_items; ++i) {
       ftcg_plan p = b->plans[i];
-      ftcg_status s = ftcg_set_points(p, m_host[i], k_dev + 2 * off);
-      if (s != FTCG_OK) throw StatusError{s};
-      finish_deferred_weights(p);   // the batched spread reads the records' weights
       b->m[i] = m_host[i];
       BatchItem& it = b->items[i];
       it.recs = p->recs.as<Rec<float>>();
       it.alpha_s = p->alpha_s.as<float>();
-      it.fhat_off = off;
+      it.fhat_off = off[i];
       it.grid_off = grid;
       it.tmp_off = tmp;
       it.img_off = img;
@@ -291,13 +367,11 @@ ftcg_status ftcg_batch_set_points(ftcg_batch_s* b, const int64_t* m_host, const 
       it.beta = (float)p->beta;
       FTCG_HIP(hipMemcpyAsync(b->deapod.as<double>() + dp, p->deapod.p, sizeof(double) * p->n,
                               hipMemcpyDeviceToDevice, b->stream));
-      off += m_host[i];
       grid += p->G * p->G;
       tmp += p->n * p->G;
       img += p->n * p->n;
       dp += p->n;
     }
-    b->m_total = off;
     FTCG_HIP(hipMemcpyAsync(b->items_dev.p, b->items.data(), sizeof(BatchItem) * b->n_items,
                             hipMemcpyHostToDevice, b->stream));
     build_tables(b);

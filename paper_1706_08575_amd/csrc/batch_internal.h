@@ -72,6 +72,15 @@ struct ftcg_batch_s {
   struct ftcg_mlp_s* mlp = nullptr;
   double audit_threshold = 1e-4;
   int64_t audit_samples = 4096;
+  // set_points runs the items on BATCH_STREAMS streams of default priority
+  // (joined back into `stream` by events), so that the small items' launches
+  // and short kernels overlap the large items' weight sums
+  static constexpr int BATCH_STREAMS = 3;
+  hipStream_t side[BATCH_STREAMS] = {};
+  hipEvent_t ev_side[BATCH_STREAMS] = {};
+  hipEvent_t ev_start = nullptr;
+  int32_t* host_off = nullptr;   // pinned: every item's tile offsets
+  size_t host_off_len = 0;
 };
 
 namespace ftcg {

@@ -345,6 +345,12 @@ struct ftcg_plan_s {
   ftcg::CheckOut* host_geo = nullptr;
   hipEvent_t ev_check = nullptr;
   int check_seq = 0;
+  // between the two parts of set_points: the call's check number and the
+  // binning decisions taken before the host has read the check
+  struct PendingPoints {
+    int seq = 0;
+    bool tiles = false, early_scatter = false, fused = false, band = false;
+  } pending;
 };
 
 namespace ftcg {
@@ -374,6 +380,10 @@ void sort_weight_rows(ftcg_plan p);                  // 2D bins from the rows (+
 void build_weight_bins_1d(ftcg_plan p, const double* k);   // 1D sorted neighbour bins
 void run_plain_weights(ftcg_plan p);                // alpha (caller order) from the bins
 void finish_deferred_weights(ftcg_plan p);          // no-op unless p->weights_deferred
+// ftcg_set_points in two parts (a batch enqueues every item's first part
+// before the host waits for the first input check); throw on errors
+void set_points_begin(ftcg_plan p, int64_t m, const double* k_dev);
+void set_points_end(ftcg_plan p, const double* k_dev);
 // plain weights of the samples idx[0..n) (caller indices) into out[0..n)
 void plain_weights_at(ftcg_plan p, const double* k, const int32_t* idx, int64_t n, double* out);
 void fill_ones(double* a, int64_t m, hipStream_t s);
