@@ -163,7 +163,9 @@ void set_points_begin(ftcg_plan p, int64_t m, const double* k_dev) {
   //      the bin rows follow it).
   //    Records written here get their weights once those are known.
   const bool tiles = !p->weights_only;
-  const bool early_scatter = tiles && tile_keys_in_lds(p);
+  // 2D weights bin their rows with the tiles at any tile count; otherwise the
+  // tile scatter runs early only when its counters fit LDS
+  const bool early_scatter = tiles && (tile_keys_in_lds(p) || rows2d);
   const bool fused = rows2d && early_scatter;
   const int64_t cap = m << p->dim;  // worst case 2^dim tile records per sample
   if (tiles) {

@@ -479,6 +479,117 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_scatter(const double* __rest
   }
 }
 
+// The same fusion beyond LDS_TILE_KEYS tiles (the 4096^2 raster: 65 536
+// tiles): the tile counters stay in global memory and take one atomic per
+// group of lanes with the same key (key_group / group_claim), the bin rows
+// are counted in LDS as above. Both passes take one group of BIN_IPT *
+// BIN_BLOCK samples per workgroup.
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin2g_count(const double* __restrict__ k, int64_t m, TileGeom tg,
+                                                           const WBinGeom* __restrict__ wgp,
+                                                           int32_t* __restrict__ tile_cnt,
+                                                           int32_t* __restrict__ row_cnt, int rounds) {
+  const WBinGeom wg = *wgp;
+  __shared__ int32_t hr[WROW_MAX];
+  const int nrow = wg.nb[0];
+  for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) hr[i] = 0;
+  __syncthreads();
+  for (int rd = 0; rd < rounds; ++rd) {
+    double u[BIN_IPT][2], x[BIN_IPT][2];
+    int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4], row[BIN_IPT], col[BIN_IPT];
+    bin2_keys(k, m, tg, wg, ((int64_t)blockIdx.x * rounds + rd) * BIN_IPT * BIN_BLOCK, u, c, key, l0, l1, row, col,
+              x);
+#pragma unroll
+    for (int i = 0; i < BIN_IPT; ++i) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const KeyGroup kg = key_group(key[i][q], key[i][q] >= 0);
+        if (kg.leader == (int)__lane_id()) atomicAdd(&tile_cnt[key[i][q]], kg.size);
+      }
+      if (row[i] >= 0) atomicAdd(&hr[row[i]], 1);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) {
+    const int v = hr[i];
+    if (v) atomicAdd(&row_cnt[i], v);
+  }
+}
+
+template <class real>
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin2g_scatter(const double* __restrict__ k, int64_t m, TileGeom tg,
+                                                             const WBinGeom* __restrict__ wgp,
+                                                             int32_t* __restrict__ tile_cursor,
+                                                             int32_t* __restrict__ row_cursor,
+                                                             Rec<real>* __restrict__ recs,
+                                                             RowRec* __restrict__ rowbuf) {
+  const WBinGeom wg = *wgp;
+  __shared__ int32_t br[WROW_MAX + LDS_SPARE];   // row counters, then one spare word per lane
+  const int nrow = wg.nb[0];
+  for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) br[i] = 0;
+  __syncthreads();
+  const int64_t j0 = (int64_t)blockIdx.x * BIN_IPT * BIN_BLOCK;
+  double u[BIN_IPT][2], x[BIN_IPT][2];
+  int c[BIN_IPT][2], key[BIN_IPT][4], l0[BIN_IPT][4], l1[BIN_IPT][4], row[BIN_IPT], col[BIN_IPT];
+  bin2_keys(k, m, tg, wg, j0, u, c, key, l0, l1, row, col, x);
+  // tile ranges: every slot's groups claim before any claim is waited for
+  KeyGroup kg[BIN_IPT][4];
+  int base[BIN_IPT][4];
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) kg[i][q] = key_group(key[i][q], key[i][q] >= 0);
+    if (row[i] >= 0) atomicAdd(&br[row[i]], 1);
+  }
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) base[i][q] = group_claim(tile_cursor, key[i][q], kg[i][q]);
+  __syncthreads();
+  {
+    // one row range per row seen; a thread's claims are all in flight together
+    constexpr int PER = WROW_MAX / BIN_BLOCK;
+    int v[PER], r[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = threadIdx.x + q * BIN_BLOCK;
+      v[q] = i < nrow ? br[i] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) r[q] = v[q] ? atomicAdd(&row_cursor[threadIdx.x + q * BIN_BLOCK], v[q]) : 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+      if (v[q]) br[threadIdx.x + q * BIN_BLOCK] = r[q];
+  }
+  __syncthreads();
+  int rpos[BIN_IPT];
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i) rpos[i] = lds_claim(br, row[i], nrow);
+#pragma unroll
+  for (int i = 0; i < BIN_IPT; ++i) {
+    const int64_t j = j0 + (int64_t)i * BIN_BLOCK + threadIdx.x;
+    Rec<real> rc;
+    rc.f0 = (real)(u[i][0] - (double)c[i][0]);
+    rc.f1 = (real)(u[i][1] - (double)c[i][1]);
+    rc.src = (int32_t)j;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int pos = group_slot(base[i][q], kg[i][q]);
+      if (key[i][q] >= 0) {
+        rc.c01 = (int32_t)(((uint32_t)l0[i][q] & 0xffffu) | ((uint32_t)l1[i][q] << 16));
+        recs[pos] = rc;
+      }
+    }
+    if (row[i] >= 0) {
+      RowRec rr;
+      rr.k0 = x[i][0];
+      rr.k1 = x[i][1];
+      rr.j = (int32_t)j;
+      rr.b1 = col[i];
+      rowbuf[rpos[i]] = rr;
+    }
+  }
+}
+
 // record-order weights, record count read on the device
 template <class real>
 __global__ __launch_bounds__(BIN_BLOCK) void k_refill_alpha_dev(const Rec<real>* __restrict__ recs,
@@ -613,11 +724,42 @@ static void bin_points_fused_t(ftcg_plan p, const double* k) {
   FTCG_HIP(hipGetLastError());
 }
 
+// more tiles than LDS holds: global tile counters, LDS bin rows
+template <class real>
+static void bin_points_fused_g_t(ftcg_plan p, const double* k) {
+  const TileGeom tg = tile_geom(p);
+  const WBinGeom* wg = &p->geo.as<CheckOut>()->g;
+  hipStream_t s = p->stream;
+  const int64_t m = p->m;
+  int32_t* tcnt = p->tile_cnt.as<int32_t>();   // zeroed by the input check
+  int32_t* rcnt = p->wb_cnt.as<int32_t>();     // zeroed by the input check
+  const int64_t per = (int64_t)BIN_IPT * BIN_BLOCK;
+  // one round per workgroup (4096^2 raster, binning step with 1 / 2 / 4 / 8
+  // count rounds: 0.440 / 0.471 / 0.492 / 0.487 ms: the rounds' loads and
+  // key votes run one after another)
+  const unsigned nbc = (unsigned)((m + per - 1) / per);
+  hipLaunchKernelGGL(k_bin2g_count, dim3(nbc), dim3(BIN_BLOCK), 0, s, k, m, tg, wg, tcnt, rcnt, 1);
+  exclusive_scan_i32(tcnt, p->tile_off.as<int32_t>(), p->ntiles, p->tile_scan_tmp.as<int32_t>(), s, tcnt);
+  exclusive_scan_i32(rcnt, p->wb_rowoff.as<int32_t>(), WROW_MAX, p->scan_tmp.as<int32_t>(), s, rcnt);
+  const unsigned nbs = (unsigned)((m + per - 1) / per);
+  hipLaunchKernelGGL(k_bin2g_scatter<real>, dim3(nbs), dim3(BIN_BLOCK), 0, s, k, m, tg, wg, tcnt, rcnt,
+                     p->recs.as<Rec<real>>(), p->wb_rowbuf.as<RowRec>());
+  FTCG_HIP(hipGetLastError());
+}
+
 void bin_points_fused(ftcg_plan p, const double* k) {
-  if (p->dtype == FTCG_F64)
-    bin_points_fused_t<double>(p, k);
-  else
-    bin_points_fused_t<float>(p, k);
+  const bool lds = tile_keys_in_lds(p);
+  if (p->dtype == FTCG_F64) {
+    if (lds)
+      bin_points_fused_t<double>(p, k);
+    else
+      bin_points_fused_g_t<double>(p, k);
+  } else {
+    if (lds)
+      bin_points_fused_t<float>(p, k);
+    else
+      bin_points_fused_g_t<float>(p, k);
+  }
 }
 
 void refill_alpha_dev(ftcg_plan p) {
