@@ -114,6 +114,14 @@ __device__ inline double pair_add(double acc, const WSample<DIM>& o, const doubl
   return acc + wq_square(pair_term<DIM>(o, x, sn, cs, R));
 }
 
+// staged candidate p of an LDS chunk: the byte offset 48 p by the full-rate
+// 24-bit multiply (the 32-bit one is quarter rate, and the pair loop forms one
+// address per candidate)
+__device__ inline const WSample<2>* cand_at(const WSample<2>* base, int p) {
+  return reinterpret_cast<const WSample<2>*>(reinterpret_cast<const char*>(base) +
+                                             __umul24((unsigned)p, (unsigned)sizeof(WSample<2>)));
+}
+
 // a candidate record; 2D records (48 bytes) sit in 16-byte aligned arrays
 // and are read as three 16-byte words
 template <int DIM>
@@ -410,13 +418,13 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
           int p = a0 + (int)(((unsigned)t0 * 5u) % (unsigned)len);
           for (int j = 0; j + 1 < len; j += 2) {
             const int pb = p + 1 == a1 ? a0 : p + 1;
-            const WSample<2> ca = ld_wsample(cand + p);
-            const WSample<2> cb = ld_wsample(cand + pb);
+            const WSample<2> ca = ld_wsample(cand_at(cand, p));
+            const WSample<2> cb = ld_wsample(cand_at(cand, pb));
             sym_pair<WT>(acc, cacc, p, ca, x, sn, cs, g.R);
             sym_pair<WT>(acc, cacc, pb, cb, x, sn, cs, g.R);
             p = pb + 1 == a1 ? a0 : pb + 1;
           }
-          if (len & 1) sym_pair<WT>(acc, cacc, p, ld_wsample(cand + p), x, sn, cs, g.R);
+          if (len & 1) sym_pair<WT>(acc, cacc, p, ld_wsample(cand_at(cand, p)), x, sn, cs, g.R);
         }
         __syncthreads();
         for (int i = threadIdx.x; i < q1 - q0; i += WB_BLOCK) {
