@@ -32,6 +32,9 @@ __device__ inline unsigned long long ordered_bits(double x) {
 // order-preserving integers; one workgroup of k_check_reduce then reduces the
 // partials (no atomics, no initialisation pass). The same launch zeroes zero_a[0 .. zero_na) and
 // zero_b[0 .. zero_nb), the counters of the binnings that follow.
+// VEC: 2D points read as one 16-byte word each (k 16-byte aligned), 8 in
+// flight per thread
+template <bool VEC>
 __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __restrict__ k, int64_t m, int dim,
                                                             unsigned long long* __restrict__ part,
                                                             int32_t* __restrict__ zero_a, int64_t zero_na,
@@ -45,14 +48,20 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __rest
   unsigned long long lo[2] = {~0ull, ~0ull}, hi[2] = {0ull, 0ull};
   bool bad = false;
   // CHECK_UNROLL points per thread per step, all loaded before any is used
-  constexpr int CHECK_UNROLL = 4;
+  constexpr int CHECK_UNROLL = VEC ? 8 : 4;
   for (int64_t j0 = gt; j0 < m; j0 += CHECK_UNROLL * gs) {
     double x[CHECK_UNROLL][2];
 #pragma unroll
     for (int u = 0; u < CHECK_UNROLL; ++u) {
       const int64_t j = j0 + u * gs;
-      x[u][0] = j < m ? k[j * dim] : 0.0;
-      x[u][1] = (j < m && dim == 2) ? k[j * dim + 1] : 0.0;
+      if constexpr (VEC) {
+        const double2 v = j < m ? reinterpret_cast<const double2*>(k)[j] : make_double2(0.0, 0.0);
+        x[u][0] = v.x;
+        x[u][1] = v.y;
+      } else {
+        x[u][0] = j < m ? k[j * dim] : 0.0;
+        x[u][1] = (j < m && dim == 2) ? k[j * dim + 1] : 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < CHECK_UNROLL; ++u) {
@@ -108,8 +117,12 @@ int launch_check_points(ftcg_plan p, const double* k, int64_t m, unsigned long l
   int64_t nb = (m + 2 * BIN_BLOCK - 1) / (2 * BIN_BLOCK);  // 2 points per thread at least
   if (nb > CHECK_PARTS) nb = CHECK_PARTS;
   if (nb < 1) nb = 1;
-  hipLaunchKernelGGL(k_check_points, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream, k, m, p->dim, part,
-                     zero_a, zero_na, zero_b, zero_nb);
+  if (p->dim == 2 && reinterpret_cast<uintptr_t>(k) % 16 == 0)
+    hipLaunchKernelGGL(k_check_points<true>, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream, k, m, p->dim, part,
+                       zero_a, zero_na, zero_b, zero_nb);
+  else
+    hipLaunchKernelGGL(k_check_points<false>, dim3((unsigned)nb), dim3(BIN_BLOCK), 0, p->stream, k, m, p->dim, part,
+                       zero_a, zero_na, zero_b, zero_nb);
   FTCG_HIP(hipGetLastError());
   return (int)nb;
 }
