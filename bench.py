@@ -79,12 +79,22 @@ def step_bytes(step, m, nrec, n, G, dim, dtype):
     if step == "fft2_deapod":
         return (n * G * cs + n * n * cs) if dim == 2 else (G * cs + n * cs)
     if step == "bin":
-        # read k, write one record (2 offsets, cell, index) + weight per record
+        if dim == 2:
+            # 2D weights bin tiles and bin rows together: read k, write one
+            # record (2 offsets, cell, index) per record and one row-grouped
+            # sample (k, index, bin column: 24 B) per sample
+            return m * 8 * dim + nrec * 16 + m * 24
+        # read k, write one record (offset, cell, index) + weight per record
         return m * 8 * dim + nrec * (16 + rs)
     if step == "weight_bin":
+        if dim == 2:
+            # the row sort: read the row-grouped samples, write the bin-ordered
+            # sample (k, sin, cos: 48 B), its caller index, the caller-to-bin
+            # map and the self term of its sum
+            return m * (24 + 48 + 4 + 4 + 8)
         # read k twice (count, scatter), bin id written and read, write the
-        # bin-ordered sample (k, sin, cos), its index and the caller-order sin/cos
-        return m * (2 * 8 * dim + 4 + 4 + 24 * dim + 4 + 16 * dim)
+        # bin-ordered sample (k, sin, cos), its index and the inverse map
+        return m * (2 * 8 * dim + 4 + 4 + 24 * dim + 4 + 4)
     return None
 
 
