@@ -300,7 +300,9 @@ ftcg_status ftcg_plan_set_spread_layout(ftcg_plan plan, int layout);
  * at the next weight computation:
  *   samples_per_lane : 1, 2 or 4 consecutive bin-sorted samples share each
  *                      lane's candidate reads (0 = automatic: 2 in 2D from
- *                      2^20 samples, else 1; 4 uses the one-sided sum);
+ *                      2^20 samples unless a sample has more than about
+ *                      10^4 candidate neighbours, else 1; 4 uses the
+ *                      one-sided sum);
  *   lanes_per_group  : 1, 2 or 4 lanes split every candidate range of a group
  *                      of samples and add their partial sums (2D only;
  *                      0 = automatic: 1 when a sample has more than about

@@ -1054,15 +1054,21 @@ constexpr bool WEIGHT_SYMMETRIC = true;
 constexpr int SYM_MAX_WT = 2;   // samples per lane the symmetric kernel is built for
 
 void run_plain_weights(ftcg_plan p) {
-  const int wt = p->w_samples ? p->w_samples : (p->dim == 2 && p->m >= (int64_t(1) << 20) ? 2 : 1);
+  // candidates per sample (2D): the mean bin population times the window
+  const WBinGeom& g = p->wgeom;
+  const double cand =
+      p->dim == 2 ? (double)p->m / ((double)g.nb[0] * g.nb[1]) * (2 * g.span + 1) * (2 * g.span + 1) : 0.0;
+  // samples per lane: 2 in 2D from 2^20 samples, but 1 when a sample has more
+  // than about 10^4 candidates (3.5 M samples on a 256^2 image: 39 against
+  // 41 ms)
+  const int wt = p->w_samples ? p->w_samples
+                              : (p->dim == 2 && p->m >= (int64_t(1) << 20) && cand <= 1e4 ? 2 : 1);
   if (p->dim == 2) {
     // lanes per sample group: the plan's tuning, else 4 below 2^21 samples
     // and 2 from there, but 1 when a sample has more than about 10^4
     // candidates (measured on SAS rasters of 2^16 .. 2^23 samples at
     // 0.002 .. 13 samples per grid cell: long lists already fill the lanes,
     // and more lanes per sample only multiply the LDS staging per sample)
-    const WBinGeom& g = p->wgeom;
-    const double cand = (double)p->m / ((double)g.nb[0] * g.nb[1]) * (2 * g.span + 1) * (2 * g.span + 1);
     const int S = p->w_lanes ? p->w_lanes : (cand > 1e4 ? 1 : (p->m < (int64_t(1) << 21) ? 4 : 2));
     if (wt <= SYM_MAX_WT && WEIGHT_SYMMETRIC) {
       const int key = (wt == 2 ? 10 : 0) + S;
