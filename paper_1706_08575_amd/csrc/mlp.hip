@@ -50,43 +50,59 @@ __device__ inline int wbin_clamp(double x, double kmin, double h, int nb) {
   return v < 0 ? 0 : (v >= nb ? nb - 1 : v);
 }
 
+__device__ inline void knn_visit(double kx0, double kx1, int oi, const double* x, int jself, double R,
+                                 unsigned long long (&key)[KNN]);
+
 __device__ inline void knn_visit_bin(const WSample<2>* __restrict__ ss, const int32_t* __restrict__ sidx, int beg,
                                      int end, const double* x, int jself, double R,
                                      unsigned long long (&key)[KNN]) {
-  for (int i = beg; i < end; ++i) {
-    const int oi = sidx[i];
-    const double dx = ss[i].k[0] - x[0];
-    const double dy = ss[i].k[1] - x[1];
-    if (oi == jself || fabs(dx) > R || fabs(dy) > R) continue;
-    const float fx = (float)dx, fy = (float)dy;
-    const float d2 = __fadd_rn(__fmul_rn(fx, fx), __fmul_rn(fy, fy));
-    const unsigned long long kc = ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)oi;
-    if (kc < key[KNN - 1]) {
-      // sorted insertion, branch free: walk down using the old neighbours
+  for (int i = beg; i < end; ++i) knn_visit(ss[i].k[0], ss[i].k[1], sidx[i], x, jself, R, key);
+}
+
+// visits one candidate (caller index oi, coordinates kx) for sample (x, jself)
+__device__ inline void knn_visit(double kx0, double kx1, int oi, const double* x, int jself, double R,
+                                 unsigned long long (&key)[KNN]) {
+  const double dx = kx0 - x[0];
+  const double dy = kx1 - x[1];
+  if (oi == jself || fabs(dx) > R || fabs(dy) > R) return;
+  const float fx = (float)dx, fy = (float)dy;
+  const float d2 = __fadd_rn(__fmul_rn(fx, fx), __fmul_rn(fy, fy));
+  const unsigned long long kc = ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)oi;
+  if (kc < key[KNN - 1]) {
+    // sorted insertion, branch free: walk down using the old neighbours
 #pragma unroll
-      for (int q = KNN - 1; q > 0; --q) {
-        const unsigned long long lo = key[q - 1];
-        key[q] = (kc < lo) ? lo : (kc < key[q] ? kc : key[q]);
-      }
-      key[0] = kc < key[0] ? kc : key[0];
+    for (int q = KNN - 1; q > 0; --q) {
+      const unsigned long long lo = key[q - 1];
+      key[q] = (kc < lo) ? lo : (kc < key[q] ? kc : key[q]);
     }
+    key[0] = kc < key[0] ? kc : key[0];
   }
 }
 
-// keys (float32 d2 bits << 32 | caller index) of the 16 nearest box
-// neighbours of sample (x, jself); empty slots stay ~0. Bins are visited in
-// rings of growing Chebyshev distance around the sample's bin; after ring r
-// every unvisited sample lies at least `reach` (the distance from x to the
-// edge of the (2r+1)^2 block, sides clipped at the bin grid's edge excluded)
-// away, so the search stops once the 16th key is strictly nearer than that.
-__device__ inline void knn_search(const WSample<2>* __restrict__ ss, const int32_t* __restrict__ sidx,
-                                  const int32_t* __restrict__ boff, const WBinGeom& g, const double* x, int jself,
-                                  unsigned long long (&key)[KNN]) {
-#pragma unroll
-  for (int q = 0; q < KNN; ++q) key[q] = ~0ull;
-  const int b0 = wbin_clamp(x[0], g.kmin[0], g.h, g.nb[0]);
-  const int b1 = wbin_clamp(x[1], g.kmin[1], g.h, g.nb[1]);
-  for (int r = 0; r <= g.span; ++r) {
+// after the rings 0 .. r around bin (b0, b1): true when every unvisited
+// sample lies at least `reach` (the distance from x to the edge of the
+// (2r+1)^2 block, sides clipped at the bin grid's edge excluded) away and the
+// 16th key is strictly nearer than that (with a margin for float rounding)
+__device__ inline bool knn_done(const unsigned long long (&key)[KNN], const WBinGeom& g, const double* x, int b0,
+                                int b1, int r) {
+  if (key[KNN - 1] == ~0ull) return false;
+  const int lo0 = max(b0 - r, 0), hi0 = min(b0 + r, g.nb[0] - 1);
+  const int lo1 = max(b1 - r, 0), hi1 = min(b1 + r, g.nb[1] - 1);
+  double reach = 1e300;
+  if (lo0 > 0) reach = fmin(reach, x[0] - (g.kmin[0] + lo0 * g.h));
+  if (hi0 < g.nb[0] - 1) reach = fmin(reach, g.kmin[0] + (hi0 + 1) * g.h - x[0]);
+  if (lo1 > 0) reach = fmin(reach, x[1] - (g.kmin[1] + lo1 * g.h));
+  if (hi1 < g.nb[1] - 1) reach = fmin(reach, g.kmin[1] + (hi1 + 1) * g.h - x[1]);
+  const float d16 = __uint_as_float((unsigned)(key[KNN - 1] >> 32));
+  return (double)d16 < reach * reach * (1.0 - 1e-6);
+}
+
+// rings r0 .. span around the sample's bin (b0, b1) from global memory, ring
+// by ring, until knn_done
+__device__ inline void knn_rings(const WSample<2>* __restrict__ ss, const int32_t* __restrict__ sidx,
+                                 const int32_t* __restrict__ boff, const WBinGeom& g, const double* x, int jself,
+                                 int b0, int b1, int r0, unsigned long long (&key)[KNN]) {
+  for (int r = r0; r <= g.span; ++r) {
     const int lo0 = max(b0 - r, 0), hi0 = min(b0 + r, g.nb[0] - 1);
     const int lo1 = max(b1 - r, 0), hi1 = min(b1 + r, g.nb[1] - 1);
     for (int c0 = lo0; c0 <= hi0; ++c0) {
@@ -105,16 +121,22 @@ __device__ inline void knn_search(const WSample<2>* __restrict__ ss, const int32
         }
       }
     }
-    if (key[KNN - 1] == ~0ull) continue;
-    double reach = 1e300;
-    if (lo0 > 0) reach = fmin(reach, x[0] - (g.kmin[0] + lo0 * g.h));
-    if (hi0 < g.nb[0] - 1) reach = fmin(reach, g.kmin[0] + (hi0 + 1) * g.h - x[0]);
-    if (lo1 > 0) reach = fmin(reach, x[1] - (g.kmin[1] + lo1 * g.h));
-    if (hi1 < g.nb[1] - 1) reach = fmin(reach, g.kmin[1] + (hi1 + 1) * g.h - x[1]);
-    const float d16 = __uint_as_float((unsigned)(key[KNN - 1] >> 32));
-    // strictly closer than anything outside (with a margin for float rounding)
-    if ((double)d16 < reach * reach * (1.0 - 1e-6)) return;
+    if (knn_done(key, g, x, b0, b1, r)) return;
   }
+}
+
+// keys (float32 d2 bits << 32 | caller index) of the 16 nearest box
+// neighbours of sample (x, jself); empty slots stay ~0. Bins are visited in
+// rings of growing Chebyshev distance around the sample's bin, until every
+// unvisited sample is farther than the 16th (knn_done).
+__device__ inline void knn_search(const WSample<2>* __restrict__ ss, const int32_t* __restrict__ sidx,
+                                  const int32_t* __restrict__ boff, const WBinGeom& g, const double* x, int jself,
+                                  unsigned long long (&key)[KNN]) {
+#pragma unroll
+  for (int q = 0; q < KNN; ++q) key[q] = ~0ull;
+  const int b0 = wbin_clamp(x[0], g.kmin[0], g.h, g.nb[0]);
+  const int b1 = wbin_clamp(x[1], g.kmin[1], g.h, g.nb[1]);
+  knn_rings(ss, sidx, boff, g, x, jself, b0, b1, 0, key);
 }
 
 // features (float32) and the analytic estimate of one sample (sorted
@@ -264,6 +286,20 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ f
   if (base + tid < n) y[base + tid] = ys[tid];
 }
 
+// Staged search of a workgroup's 256 consecutive bin-sorted samples: when
+// they share one bin row, the candidates of the rings 0 .. KNN_RING around
+// all of their bins (bin rows b0 - 2 .. b0 + 2, the workgroup's bin columns
+// widened by 2 on each side) are copied to LDS once (coalesced), and each
+// sample walks its rings 0 .. 2 there, in the order and with the early exit
+// of the search from global memory; a sample whose 16th neighbour is not yet
+// known to be the nearest continues with ring 3 from global memory. A workgroup spanning two bin rows, or too many candidates,
+// searches from global memory as before. The candidates visited differ, the
+// result (the 16 smallest keys of the box) does not.
+constexpr int KNN_RING = 2;
+constexpr int KNN_ROWS = 2 * KNN_RING + 1;
+constexpr int KNN_STAGE = 2048;    // staged candidates at most (k and caller index: 40 KiB)
+constexpr int KNN_COLS = 128;      // staged bin columns per row at most
+
 // fused: 16-NN features, MLP, alpha_hat = base * exp(y), in caller order
 __global__ __launch_bounds__(256) void k_learned_weights(const WSample<2>* __restrict__ ss,
                                                          const int32_t* __restrict__ sidx,
@@ -272,19 +308,112 @@ __global__ __launch_bounds__(256) void k_learned_weights(const WSample<2>* __res
                                                          const _Float16* __restrict__ P16,
                                                          const float* __restrict__ P32,
                                                          double* __restrict__ alpha) {
-  __shared__ _Float16 xs[256 * NF];
+  // the staged candidates, then (after the search) the half features
+  constexpr size_t STAGE_BYTES = KNN_STAGE * (sizeof(double2) + sizeof(int));
+  constexpr size_t XS_BYTES = 256 * NF * sizeof(_Float16);
+  __shared__ __align__(16) unsigned char pool[STAGE_BYTES > XS_BYTES ? STAGE_BYTES : XS_BYTES];
+  double2* sk = reinterpret_cast<double2*>(pool);
+  int* sid = reinterpret_cast<int*>(pool + KNN_STAGE * sizeof(double2));
+  _Float16* xs = reinterpret_cast<_Float16*>(pool);
+  __shared__ int sbo[KNN_ROWS][KNN_COLS + 1];   // LDS offset of each staged bin, per row
+  __shared__ int sinfo[8];                       // b0 min, b0 max, b1 min, b1 max, staged flag, c1
   __shared__ float ys[256];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t t = xcd_block(blockIdx.x, gridDim.x) * 256 + tid;
-  double b = 1.0;
-  int j = -1;
+  double x[2] = {0.0, 0.0};
+  int j = -1, b0 = 0, b1 = 0;
   if (t < m) {
     j = sidx[t];
-    const double x[2] = {ss[t].k[0], ss[t].k[1]};
-    unsigned long long key[KNN];
-    knn_search(ss, sidx, boff, g, x, j, key);
-    float f[NF];
-    b = knn_features_of(key, ss, inv, t, (float)g.R, f);
+    x[0] = ss[t].k[0];
+    x[1] = ss[t].k[1];
+    b0 = wbin_clamp(x[0], g.kmin[0], g.h, g.nb[0]);
+    b1 = wbin_clamp(x[1], g.kmin[1], g.h, g.nb[1]);
+  }
+  if (tid < 4) sinfo[tid] = (tid & 1) ? -1 : (1 << 30);
+  __syncthreads();
+  if (j >= 0) {
+    atomicMin(&sinfo[0], b0);
+    atomicMax(&sinfo[1], b0);
+    atomicMin(&sinfo[2], b1);
+    atomicMax(&sinfo[3], b1);
+  }
+  __syncthreads();
+  const int r0 = sinfo[0], c1 = max(sinfo[2] - KNN_RING, 0), c2 = min(sinfo[3] + KNN_RING, g.nb[1] - 1);
+  bool staged = sinfo[1] == r0 && r0 >= 0 && c2 - c1 + 1 <= KNN_COLS;
+  if (staged) {
+    // per staged row: its candidate range in the bin order and LDS base
+    if (tid == 0) {
+      int base = 0;
+      for (int q = 0; q < KNN_ROWS; ++q) {
+        const int r = r0 - KNN_RING + q;
+        const int n = (r >= 0 && r < g.nb[0]) ? boff[r * g.nb[1] + c2 + 1] - boff[r * g.nb[1] + c1] : 0;
+        sbo[q][KNN_COLS] = base;   // (the row's base, overwritten below)
+        base += n;
+      }
+      sinfo[4] = base <= KNN_STAGE ? 1 : 0;
+    }
+    __syncthreads();
+    staged = sinfo[4] != 0;
+    if (staged) {
+      const int ncol = c2 - c1 + 2;
+      int rbase[KNN_ROWS];
+#pragma unroll
+      for (int q = 0; q < KNN_ROWS; ++q) rbase[q] = sbo[q][KNN_COLS];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < KNN_ROWS; ++q) {
+        const int r = r0 - KNN_RING + q;
+        if (r < 0 || r >= g.nb[0]) continue;
+        const int gb = boff[r * g.nb[1] + c1];
+        const int n = boff[r * g.nb[1] + c2 + 1] - gb;
+        for (int i = tid; i < n; i += 256) {
+          sk[rbase[q] + i] = make_double2(ss[gb + i].k[0], ss[gb + i].k[1]);
+          sid[rbase[q] + i] = sidx[gb + i];
+        }
+        for (int c = tid; c < ncol; c += 256) sbo[q][c] = rbase[q] + boff[r * g.nb[1] + c1 + c] - gb;
+      }
+      __syncthreads();
+    }
+  }
+  unsigned long long key[KNN];
+#pragma unroll
+  for (int q = 0; q < KNN; ++q) key[q] = ~0ull;
+  if (j >= 0) {
+    if (staged) {
+      // rings 0 .. KNN_RING from LDS, in the order and with the early exit
+      // of the search from global memory, then ring KNN_RING + 1 on from there
+      auto visit = [&](int q, int cb, int ce) {   // staged row q, bin columns cb .. ce
+        const int e = sbo[q][ce + 1 - c1];
+        for (int i = sbo[q][cb - c1]; i < e; ++i) {
+          const double2 kc = sk[i];
+          knn_visit(kc.x, kc.y, sid[i], x, j, g.R, key);
+        }
+      };
+      bool done = false;
+      for (int r = 0; r <= KNN_RING && !done; ++r) {
+        const int lo0 = max(b0 - r, 0), hi0 = min(b0 + r, g.nb[0] - 1);
+        const int lo1 = max(b1 - r, 0), hi1 = min(b1 + r, g.nb[1] - 1);
+        for (int c0 = lo0; c0 <= hi0; ++c0) {
+          const int q = c0 - (r0 - KNN_RING);
+          if (c0 == b0 - r || c0 == b0 + r) {
+            visit(q, lo1, hi1);
+          } else {
+            if (b1 - r >= 0) visit(q, b1 - r, b1 - r);
+            if (r > 0 && b1 + r < g.nb[1]) visit(q, b1 + r, b1 + r);
+          }
+        }
+        done = knn_done(key, g, x, b0, b1, r);
+      }
+      if (!done) knn_rings(ss, sidx, boff, g, x, j, b0, b1, KNN_RING + 1, key);
+    } else {
+      knn_rings(ss, sidx, boff, g, x, j, b0, b1, 0, key);
+    }
+  }
+  float f[NF];
+  double b = 1.0;
+  if (j >= 0) b = knn_features_of(key, ss, inv, t, (float)g.R, f);
+  __syncthreads();   // the stage is no longer read: its LDS takes the features
+  if (j >= 0) {
 #pragma unroll
     for (int q = 0; q < NF; ++q) xs[tid * NF + q] = (_Float16)f[q];
   } else {

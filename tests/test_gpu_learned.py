@@ -159,6 +159,32 @@ def test_learned_plan_end_to_end(small):
     assert abs(rep["audit_estimate"] - est) < 1e-9 * est + 1e-15
 
 
+@pytest.mark.parametrize("n,pulses,per_pulse", [(512, 256, 1024), (1024, 512, 2048)])
+def test_fused_learned_weights_equal_features_then_network(n, pulses, per_pulse):
+    # the fused kernel's 16-NN search (staged in LDS for workgroups whose
+    # samples share a bin row, from global memory otherwise) against the
+    # separate feature kernel (ring search from global memory, bitwise equal
+    # to the oracle's features in test_features_match_oracle) followed by the
+    # separate inference kernel: the same features give the same network
+    # output, so alpha_hat agrees to the rounding of the last exp
+    from paper_1706_08575_amd.ftcg import Plan
+    from paper_1706_08575_amd.mlp import Mlp
+    k, _, _ = S.make_sas(S.seed_for(4) + 11, n=n, pulses=pulses, per_pulse=per_pulse)
+    kd = dev(k)
+    with Mlp(S.mlp_init(3)) as net:
+        with Plan(n, dim=2, weights="learned") as P:
+            P.set_mlp(net, audit_threshold=float("inf"), audit_samples=64)
+            P.set_points(kd)
+            a = host(P.get_weights())
+        F, B = net.features(kd, 8.0)
+        y = host(net.forward(F)).astype(np.float64)
+        B = host(B)
+    ref = B * np.exp(y)
+    d = np.abs(a - ref) / ref
+    print(f"m = {len(k)}: fused vs features + network, max rel {d.max():.2e}")
+    assert d.max() < 1e-13
+
+
 def test_audit_fallback_forced_from_host(small):
     from paper_1706_08575_amd.ftcg import Plan
     from paper_1706_08575_amd.mlp import Mlp
