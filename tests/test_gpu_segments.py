@@ -119,3 +119,45 @@ def test_segments_non_finite_value_stays_local():
     far = np.ones((G, G), dtype=bool)
     far[max(0, r - 80):r + 80, max(0, c - 140):c + 140] = False
     assert np.isfinite(H[far]).all()
+
+
+@pytest.mark.parametrize("case", ["single", "corners", "wrapped"])
+def test_segments_sparse_and_wrapped(case):
+    # degenerate inputs on the segmented layout (n = 2048, G = 4096): one
+    # sample; samples on segment corners and stripe edges (every other step
+    # and segment empty); a raster whose samples lie up to 2.2 n outside the
+    # k-box, so that their taps wrap around the grid edges. Every cell against
+    # the per-tile kernel, the cells near the samples against the oracle.
+    n, G, T, K = 2048, 4096, 32, 4
+    rng = np.random.default_rng(17)
+    if case == "single":
+        u = np.array([[1234.3, 2999.7]])
+    elif case == "corners":
+        pts = []
+        for r in (K * T * 3, K * T * 7 - 1, K * T * 11 + 0.5):
+            for c in (2 * T * 5, 2 * T * 9 - 1, 2 * T * 20 + 0.25, 0.0, G - 0.5):
+                pts.append([r + rng.uniform(-0.5, 0.5), c])
+        u = np.array(pts)
+    else:
+        u = rng.uniform(0, G, size=(3000, 2))
+    k = (u - G / 2) / 2.0
+    if case == "wrapped":
+        k += rng.integers(-2, 3, size=k.shape) * n * 1.1
+    f = (rng.standard_normal(len(k)) + 1j * rng.standard_normal(len(k))).astype(np.complex128)
+    Hs, a = _spread(k, f, "auto")
+    Ht, _ = _spread(k, f, "tiles")
+    d = torch.linalg.vector_norm(Hs - Ht).item() / torch.linalg.vector_norm(Ht).item()
+    assert d < 1e-6, d
+    c = a * f
+    uu = np.mod(2.0 * k + G / 2, G)
+    num = den = 0.0
+    for (r, cc) in uu[:40]:
+        r0 = int(np.clip(int(r) - 16, 0, G - 32))
+        c0 = int(np.clip(int(cc) - 16, 0, G - 32))
+        got = Hs[r0:r0 + 32, c0:c0 + 32].cpu().numpy()
+        ref = O.spread_window(k, c, n, r0, c0, 32, 32)
+        num += np.linalg.norm(got - ref) ** 2
+        den += np.linalg.norm(ref) ** 2
+    err = float(np.sqrt(num / den))
+    print(f"{case}: vs per-tile {d:.2e}, windows vs oracle {err:.2e}")
+    assert err < 2e-5
