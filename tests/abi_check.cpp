@@ -92,6 +92,7 @@ int main() {
   EXPECT(ftcg_plan_info(NULL, &l, &l, &l, &i), FTCG_EINVAL);
   EXPECT(ftcg_plan_set_tuning(NULL, 32, 0, 1), FTCG_EINVAL);
   EXPECT(ftcg_plan_set_weight_tuning(NULL, 0, 0), FTCG_EINVAL);
+  EXPECT(ftcg_plan_set_spread_layout(NULL, 0), FTCG_EINVAL);
   EXPECT(ftcg_plan_enable_timing(NULL, 1), FTCG_EINVAL);
   EXPECT(ftcg_plan_timing(NULL, &d, &l), FTCG_EINVAL);
   EXPECT(ftcg_plan_set_mlp(NULL, NULL, 1e-4, 16), FTCG_EINVAL);
@@ -131,6 +132,8 @@ int main() {
     EXPECT(ftcg_plan_set_tuning(q, 48, 0, 1), FTCG_EINVAL);
     EXPECT(ftcg_plan_set_tuning(q, 32, 2, 1), FTCG_EINVAL);
     EXPECT(ftcg_plan_set_weight_tuning(q, 3, 0), FTCG_EINVAL);
+    EXPECT(ftcg_plan_set_spread_layout(q, 2), FTCG_EINVAL);
+    EXPECT(ftcg_plan_set_spread_layout(q, -1), FTCG_EINVAL);
     EXPECT(ftcg_frame_approx(q, 4, &d, buf, buf), FTCG_EUNSUPPORTED);   // float32 plan
     EXPECT(ftcg_plan_destroy(q), FTCG_OK);
   }

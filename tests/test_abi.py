@@ -71,6 +71,7 @@ def test_null_arguments():
     for name, args in (("ftcg_plan_destroy", (None,)), ("ftcg_set_points", (None, 10, None)),
                        ("ftcg_execute", (None, None, None)), ("ftcg_set_weights", (None, None)),
                        ("ftcg_get_weights", (None, None, None)), ("ftcg_plan_set_tuning", (None, 64, 0, 1)),
+                       ("ftcg_plan_set_spread_layout", (None, 0)),
                        ("ftcg_plan_info", (None, None, None, None, None)),
                        ("ftcg_spread_only", (None, None, None)), ("ftcg_grid_to_image", (None, None, None)),
                        ("ftcg_plan_enable_timing", (None, 1)), ("ftcg_plan_timing", (None, None, None)),
