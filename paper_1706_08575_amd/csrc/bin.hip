@@ -497,14 +497,28 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin2_scatter(const double* __rest
 // group of lanes with the same key (key_group / group_claim), the bin rows
 // are counted in LDS as above. Both passes take one group of BIN_IPT *
 // BIN_BLOCK samples per workgroup.
+// The tile counts of a workgroup are gathered first in a small LDS table
+// (open addressing, one insertion per group of lanes with the same key): the
+// consecutive samples of a workgroup meet about a hundred tiles, so the table
+// turns one global atomic per key group and wavefront into one per tile and
+// workgroup. A key that finds no slot within CNT_PROBES probes goes to the
+// global counter directly.
+constexpr int CNT_SLOTS = 1024;
+constexpr int CNT_PROBES = 8;
+
 __global__ __launch_bounds__(BIN_BLOCK) void k_bin2g_count(const double* __restrict__ k, int64_t m, TileGeom tg,
                                                            const WBinGeom* __restrict__ wgp,
                                                            int32_t* __restrict__ tile_cnt,
                                                            int32_t* __restrict__ row_cnt, int rounds) {
   const WBinGeom wg = *wgp;
   __shared__ int32_t hr[WROW_MAX];
+  __shared__ int32_t tkey[CNT_SLOTS], tcnt[CNT_SLOTS];
   const int nrow = wg.nb[0];
   for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) hr[i] = 0;
+  for (int i = threadIdx.x; i < CNT_SLOTS; i += BIN_BLOCK) {
+    tkey[i] = -1;
+    tcnt[i] = 0;
+  }
   __syncthreads();
   for (int rd = 0; rd < rounds; ++rd) {
     double u[BIN_IPT][2], x[BIN_IPT][2];
@@ -516,12 +530,28 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin2g_count(const double* __restr
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const KeyGroup kg = key_group(key[i][q], key[i][q] >= 0);
-        if (kg.leader == (int)__lane_id()) atomicAdd(&tile_cnt[key[i][q]], kg.size);
+        if (kg.leader == (int)__lane_id()) {
+          const int kk = key[i][q];
+          int h = (int)(((unsigned)kk * 2654435761u) >> 22);   // 10 bits
+          bool placed = false;
+          for (int pr = 0; pr < CNT_PROBES && !placed; ++pr, h = (h + 1) & (CNT_SLOTS - 1)) {
+            const int old = atomicCAS(&tkey[h], -1, kk);
+            if (old == -1 || old == kk) {
+              atomicAdd(&tcnt[h], kg.size);
+              placed = true;
+            }
+          }
+          if (!placed) atomicAdd(&tile_cnt[kk], kg.size);
+        }
       }
       if (row[i] >= 0) atomicAdd(&hr[row[i]], 1);
     }
   }
   __syncthreads();
+  for (int i = threadIdx.x; i < CNT_SLOTS; i += BIN_BLOCK) {
+    const int kk = tkey[i];
+    if (kk >= 0) atomicAdd(&tile_cnt[kk], tcnt[i]);
+  }
   for (int i = threadIdx.x; i < nrow; i += BIN_BLOCK) {
     const int v = hr[i];
     if (v) atomicAdd(&row_cnt[i], v);
