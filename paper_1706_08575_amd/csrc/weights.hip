@@ -322,6 +322,17 @@ __device__ inline void sym_pair(double (&acc)[WT], double* cacc, int p, const WS
   if (csum != 0.0) __hip_atomic_fetch_add(cacc + p, csum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Work balance of the symmetric sum: a wavefront runs its pair loop as long
+// as its longest lane range, and the candidate counts of the groups' windows
+// vary along a bin row by tens of percent (lattice rasters against the bin
+// grid), so taken in bin order a wavefront's lanes idle about a quarter of
+// the loop. Each run therefore orders its groups by candidate count, heaviest
+// first (a counting sort in LDS), and lanes take groups in that order: the
+// wavefronts then hold groups of about equal work. Which lane forms which
+// pair does not change the sums (every square is quantized, every sum exact).
+constexpr int WKEYS = 512;   // work buckets of the ordering; counts of WKEYS - 1 and more share the last
+static_assert(WKEYS % WB_BLOCK == 0, "whole buckets per thread in the scan");
+
 template <int WT, int S>
 __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>* __restrict__ ss,
                                                                 const int32_t* __restrict__ boff, WBinGeom g,
@@ -332,8 +343,12 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
   // 512 with two (0.366 against 0.388 ms at 2^20, 1.59 against 2.18 ms at
   // 2^23, where the wider runs fill the chunk)
   constexpr int CH = WT == 1 ? 256 : WCH;
+  constexpr int NG = WB_BLOCK / S;   // groups of WT samples per run
   __shared__ __align__(16) WSample<2> cand[CH];
   __shared__ double cacc[CH];
+  __shared__ int whist[WKEYS];
+  __shared__ int wpart[WB_BLOCK / 64];
+  __shared__ int gorder[NG];
   for (int i = threadIdx.x; i < CH; i += WB_BLOCK) cacc[i] = 0.0;   // ordered by the first chunk's barriers
   const int64_t lid = xcd_block_chunk(blockIdx.x, gridDim.x, chunk);
   const int b0 = (int)(lid / cx), bx = (int)(lid % cx);
@@ -343,7 +358,69 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
   const int sub = (int)threadIdx.x % S;
   for (int c0 = rs + bx * RUN; c0 < re; c0 += cx * RUN) {
     const int cend = min(c0 + RUN, re);
-    const int t0 = c0 + ((int)threadIdx.x / S) * WT;   // this lane's samples t0 .. t0 + WT - 1
+    // order the run's groups by candidate count (the ranges of the pair loop
+    // below, summed over the rows), heaviest first
+    for (int i = threadIdx.x; i < WKEYS; i += WB_BLOCK) whist[i] = 0;
+    __syncthreads();   // (also: the previous run's order has been read)
+    int key = 0, slot = 0;
+    if (sub == 0) {
+      const int gt0 = c0 + ((int)threadIdx.x / S) * WT;
+      int work = 0;
+      if (gt0 < cend) {
+        int lo = 1 << 30, hi = -1, nl = 0;
+#pragma unroll
+        for (int u = 0; u < WT; ++u)
+          if (gt0 + u < cend) {
+            const double2 kk = *reinterpret_cast<const double2*>(ss[gt0 + u].k);
+            double xk[2] = {kk.x, kk.y};
+            int b[2];
+            wbin_of<2>(xk, g, b);
+            lo = min(lo, b[1]);
+            hi = max(hi, b[1]);
+            ++nl;
+          }
+        lo = max(lo - g.span, 0);
+        hi = min(hi + g.span, nb1 - 1);
+        for (int r = b0; r <= rhi; ++r) {
+          int fs = boff[r * nb1 + lo];
+          const int fe = boff[r * nb1 + hi + 1];
+          if (r == b0) fs = max(fs, gt0 + nl);
+          work += max(fe - fs, 0);
+        }
+      }
+      key = WKEYS - 1 - min(work, WKEYS - 1);
+      slot = atomicAdd(&whist[key], 1);
+    }
+    __syncthreads();
+    {   // exclusive scan of the bucket counts, WKEYS / WB_BLOCK buckets per thread
+      constexpr int PER = WKEYS / WB_BLOCK;
+      int v[PER], tot = 0;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        v[q] = whist[threadIdx.x * PER + q];
+        tot += v[q];
+      }
+      int incl = tot;
+      const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+      }
+      if (lane == 63) wpart[wv] = incl;
+      __syncthreads();
+      int pre = incl - tot;
+      for (int q = 0; q < wv; ++q) pre += wpart[q];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        whist[threadIdx.x * PER + q] = pre;
+        pre += v[q];
+      }
+    }
+    __syncthreads();
+    if (sub == 0) gorder[whist[key] + slot] = (int)threadIdx.x / S;
+    __syncthreads();
+    const int t0 = c0 + gorder[threadIdx.x / S] * WT;   // this lane's samples t0 .. t0 + WT - 1
     const bool active = t0 < cend;
     double x[WT][2], sn[WT][2], cs[WT][2];
     int mylo = 1 << 30, myhi = -1;
