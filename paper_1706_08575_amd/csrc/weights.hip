@@ -488,11 +488,15 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_sym(const WSample<2>
         }
         __syncthreads();
         const int a0 = max(ms, q0) - q0, a1 = min(me, q1) - q0;
-        // Lanes of one bin walk the same range; each starts at its own
-        // rotation of it, so their candidate atomics meet different slots.
+        // Each lane starts at its own rotation of its range: lanes of one bin
+        // walk the same range, and a start on slot (lane mod 16) mod 16 puts
+        // the 16 lanes of a quarter wavefront on different LDS banks (a
+        // 48-byte record covers 12 banks of 4 bytes; records 16 apart share
+        // them), for the record reads and the slot atomics alike.
         const int len = a1 - a0;
         if (len > 0) {
-          int p = a0 + (int)(((unsigned)t0 * 5u) % (unsigned)len);
+          const unsigned ph = ((unsigned)threadIdx.x - (unsigned)a0) & 15u;
+          int p = a0 + (int)(ph % (unsigned)len);
           for (int j = 0; j + 1 < len; j += 2) {
             const int pb = p + 1 == a1 ? a0 : p + 1;
             const WSample<2> ca = ld_wsample(cand_at(cand, p));
