@@ -219,6 +219,125 @@ __device__ __attribute__((always_inline)) inline void lds_ifft(typename CxF<real
   }
 }
 
+// A row of L = PPT * nts points held in registers, thread t holding v[u] =
+// element t + u nts, transformed through two LDS buffers. The first
+// butterflies of a thread (b = t + u nts, inputs b + r L/R) read only its own
+// elements, and so do the outputs of its last radix-8 butterflies (written to
+// b + r L/8), so the first stage is taken from the registers the row was
+// loaded into and the last one leaves its outputs there: on return v[u] holds
+// output element t + u nts. In between the stages run out of place (read one
+// buffer, write the other), one barrier each, and the row makes 4 LDS round
+// trips and 4 barriers at L = 8192 instead of 6 and 12. The buffer the last
+// stage read may still be read by slower threads on return, so the next row
+// starts in the other one (cur names the buffer the next first stage
+// writes). Twiddles as in lds_ifft.
+template <class real, int PPT>
+__device__ __attribute__((always_inline)) inline void reg_ifft_db(typename CxF<real>::t (&v)[PPT],
+                                                                  typename CxF<real>::t* b0,
+                                                                  typename CxF<real>::t* b1, int& cur, int L,
+                                                                  int log2L, int t, int nts,
+                                                                  const typename CxF<real>::t* tw_lo,
+                                                                  const typename CxF<real>::t* tw_hi, int log2T) {
+  using cx = typename CxF<real>::t;
+  static_assert(PPT % 8 == 0, "radix-8 stages take 8 points per butterfly");
+  cx* A = cur ? b1 : b0;
+  cx* B = cur ? b0 : b1;
+  int Ns, log2Ns;
+  const int pre = log2L % 3;
+  if (pre == 1) {
+    constexpr int NB = PPT / 2;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int b = t + u * nts;
+      A[lp(2 * b)] = cadd(v[u], v[u + NB]);
+      A[lp(2 * b + 1)] = csub(v[u], v[u + NB]);
+    }
+    Ns = 2;
+    log2Ns = 1;
+  } else if (pre == 2) {
+    constexpr int NB = PPT / 4;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int b = t + u * nts;
+      cx w0 = v[u], w1 = v[u + NB], w2 = v[u + 2 * NB], w3 = v[u + 3 * NB];
+      idft4(w0, w1, w2, w3);
+      A[lp(4 * b)] = w0;
+      A[lp(4 * b + 1)] = w1;
+      A[lp(4 * b + 2)] = w2;
+      A[lp(4 * b + 3)] = w3;
+    }
+    Ns = 4;
+    log2Ns = 2;
+  } else {
+    constexpr int NB = PPT / 8;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int b = t + u * nts;
+      cx w[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) w[r] = v[u + r * NB];
+      idft8(w);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) A[lp(8 * b + r)] = w[r];
+    }
+    Ns = 8;
+    log2Ns = 3;
+  }
+  constexpr int NB8 = PPT / 8;
+  const int eighth = L >> 3;
+  auto twiddle = [&](cx (&w)[8], int k, int sh) {
+    const int j = k << sh;
+    const cx w1 = cmul(tw_hi[j >> 6], tw_lo[j & 63]);
+    const cx w2 = cmul(w1, w1);
+    const cx w3 = cmul(w2, w1);
+    const cx w4 = cmul(w2, w2);
+    w[1] = cmul(w[1], w1);
+    w[2] = cmul(w[2], w2);
+    w[3] = cmul(w[3], w3);
+    w[4] = cmul(w[4], w4);
+    w[5] = cmul(w[5], cmul(w4, w1));
+    w[6] = cmul(w[6], cmul(w4, w2));
+    w[7] = cmul(w[7], cmul(w4, w3));
+  };
+  for (; Ns < eighth; Ns <<= 3, log2Ns += 3) {
+    __syncthreads();
+    const int sh = log2T - log2Ns - 3;
+#pragma unroll
+    for (int u = 0; u < NB8; ++u) {
+      const int b = t + u * nts;
+      const int k = b & (Ns - 1);
+      cx w[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) w[r] = A[lp(b + r * eighth)];
+      twiddle(w, k, sh);
+      idft8(w);
+      const int d = (b - k) * 8 + k;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) B[lp(d + r * Ns)] = w[r];
+    }
+    cx* tmp = A;
+    A = B;
+    B = tmp;
+  }
+  // last stage, Ns = L / 8: butterfly b < Ns has k = b and writes b + r Ns
+  __syncthreads();
+  {
+    const int sh = log2T - log2Ns - 3;
+#pragma unroll
+    for (int u = 0; u < NB8; ++u) {
+      const int b = t + u * nts;
+      cx w[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) w[r] = A[lp(b + r * eighth)];
+      twiddle(w, b, sh);
+      idft8(w);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[u + r * NB8] = w[r];
+    }
+  }
+  cur = A == b0 ? 1 : 0;
+}
+
 // RB consecutive rows r0..r0+RB-1 through one workgroup, RC of them at a
 // time (RC = 1 or RB): the threads form RC slots of blockDim.x / RC threads,
 // slot s owning LDS buf[s Lp ..) (Lp = padded_len(L)) and rows s, s + RC, ...
@@ -229,15 +348,16 @@ __device__ __attribute__((always_inline)) inline void lds_ifft(typename CxF<real
 // All RB rows of an output q' then leave as one RB-element segment at
 // dst[q' out_stride_q + r0]: through LDS staged q'-major when RC = RB, or
 // straight from registers when RC = 1 (one thread then holds all RB rows).
-template <class real, int RB, int RC, int MAXQ, int PPT>
+template <class real, int RB, int RC, int MAXQ, int PPT, bool DB>
 __device__ __attribute__((always_inline)) inline void fft_rows_block(const typename CxF<real>::t* __restrict__ src, int64_t in_row_stride,
                                       typename CxF<real>::t* __restrict__ dst, int64_t out_stride_q, int L,
                                       int log2L, int ncrop, int crop_off, int r0, int pre_sign,
                                       const double* __restrict__ dq, const double* __restrict__ drow,
                                       typename CxF<real>::t* buf, const typename CxF<real>::t* __restrict__ tw,
                                       int log2T) {
-  // twiddle tables behind the RC row buffers: lo (64 entries), hi (2^log2T / 64)
-  typename CxF<real>::t* tw_lo = buf + (size_t)RC * padded_len(L);
+  // twiddle tables behind the row buffers (RC, or 2 with db): lo (64
+  // entries), hi (2^log2T / 64)
+  typename CxF<real>::t* tw_lo = buf + (size_t)(DB ? 2 : RC) * padded_len(L);
   typename CxF<real>::t* tw_hi = tw_lo + 64;
   {
     const int ntw = 64 + max(1, (1 << log2T) >> 6);
@@ -257,6 +377,62 @@ __device__ __attribute__((always_inline)) inline void fft_rows_block(const typen
 #pragma unroll
     for (int u = 0; u < PPT; ++u)
       if (t + u * nts < L) nxt[u] = s0[t + u * nts];
+  }
+  if constexpr (RC == 1 && DB) {
+    {
+      // register path (the host sets db when L == PPT nts, the crop keeps
+      // the middle half, crop_off = L / 4 = (PPT / 4) nts, and two row
+      // buffers fit the LDS): the cropped output qp = t + kq nts is element
+      // crop_off + qp = t + (PPT / 4 + kq) nts of the row, register
+      // PPT / 4 + kq, an index fixed at compile time
+      constexpr int U0 = PPT / 4;
+      static_assert(U0 + MAXQ <= PPT || MAXQ > 4, "the cropped outputs are registers of the row");
+      int cur = 0;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int row = r0 + j;
+        cx v[PPT];
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+          v[u] = nxt[u];
+          if (pre_sign && ((row + t + u * nts) & 1)) {
+            v[u].x = -v[u].x;
+            v[u].y = -v[u].y;
+          }
+        }
+        if (j + 1 < NJ) {
+          const cx* s1 = src + (int64_t)(j + 1) * in_row_stride;
+#pragma unroll
+          for (int u = 0; u < PPT; ++u) nxt[u] = s1[t + u * nts];
+        }
+        reg_ifft_db<real, PPT>(v, buf, buf + padded_len(L), cur, L, log2L, t, nts, tw_lo, tw_hi, log2T);
+        const double fr = drow ? drow[row] : 1.0;
+#pragma unroll
+        for (int kq = 0; kq < MAXQ; ++kq) {
+          const int qp = t + kq * nts;
+          if (U0 + kq < PPT && qp < ncrop) {
+            const int q = qp + crop_off;
+            double f = (q & 1) ? -fr : fr;
+            if (dq) f *= dq[qp];
+            const real fs = (real)f;
+            cx w = v[U0 + kq < PPT ? U0 + kq : PPT - 1];
+            w.x *= fs;
+            w.y *= fs;
+            outv[j][kq] = w;
+          }
+        }
+      }
+#pragma unroll
+      for (int kq = 0; kq < MAXQ; ++kq) {
+        const int qp = t + kq * nts;
+        if (qp < ncrop) {
+          cx* d = dst + (int64_t)qp * out_stride_q;
+#pragma unroll
+          for (int j = 0; j < RB; ++j) d[j] = outv[j][kq];
+        }
+      }
+      return;
+    }
   }
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
@@ -323,7 +499,7 @@ __device__ __attribute__((always_inline)) inline void fft_rows_block(const typen
   }
 }
 
-template <class real, int RB, int RC, int MAXQ, int PPT>
+template <class real, int RB, int RC, int MAXQ, int PPT, bool DB>
 __global__ void k_fft_rows(const typename CxF<real>::t* __restrict__ in, int64_t in_row_stride,
                            typename CxF<real>::t* __restrict__ out, int64_t out_stride_q, int L, int log2L,
                            int ncrop, int crop_off, int rows, int pre_sign, const double* __restrict__ dq,
@@ -333,14 +509,15 @@ __global__ void k_fft_rows(const typename CxF<real>::t* __restrict__ in, int64_t
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx* buf = reinterpret_cast<cx*>(smem_raw);
   const int r0 = (int)xcd_block(blockIdx.x, gridDim.x) * RB;
-  fft_rows_block<real, RB, RC, MAXQ, PPT>(in + (int64_t)r0 * in_row_stride, in_row_stride, out + r0, out_stride_q,
-                                          L, log2L, ncrop, crop_off, r0, pre_sign, dq, drow, buf, tw, log2T);
+  fft_rows_block<real, RB, RC, MAXQ, PPT, DB>(in + (int64_t)r0 * in_row_stride, in_row_stride, out + r0,
+                                              out_stride_q, L, log2L, ncrop, crop_off, r0, pre_sign, dq, drow, buf, tw,
+                                              log2T);
 }
 
 // batched passes over the items of one grid size G (all with n = G / sigma),
 // RB rows per workgroup: pass 1 maps row block b to item list[b*RB / G], grid
 // rows b*RB % G ..; pass 2 maps it to item list[b*RB / n], intermediate rows
-template <int RB, int RC, int MAXQ, int PPT>
+template <int RB, int RC, int MAXQ, int PPT, bool DB>
 __global__ void k_fft_rows_batched(const BatchItem* __restrict__ items, const int* __restrict__ list,
                                    const BatchArgs* __restrict__ args, int pass, int L, int log2L, int n,
                                    const float2* __restrict__ tw, int log2T) {
@@ -352,12 +529,12 @@ __global__ void k_fft_rows_batched(const BatchItem* __restrict__ items, const in
   const int row = r % per;
   const int crop_off = (L - n) / 2;
   if (pass == 1) {
-    fft_rows_block<float, RB, RC, MAXQ, PPT>(args->grid + it.grid_off + (int64_t)row * L, L,
+    fft_rows_block<float, RB, RC, MAXQ, PPT, DB>(args->grid + it.grid_off + (int64_t)row * L, L,
                                              args->tmp + it.tmp_off + row, L, L, log2L, n, crop_off, row, 1, nullptr,
                                              nullptr, buf, tw, log2T);
   } else {
     const double* d = args->deapod + it.deapod_off;
-    fft_rows_block<float, RB, RC, MAXQ, PPT>(args->tmp + it.tmp_off + (int64_t)row * L, L,
+    fft_rows_block<float, RB, RC, MAXQ, PPT, DB>(args->tmp + it.tmp_off + (int64_t)row * L, L,
                                              args->images + it.img_off + row, n, L, log2L, n, crop_off, row, 0, d,
                                              d, buf, tw, log2T);
   }
@@ -389,6 +566,18 @@ static FftShape fft_shape(int64_t L, int64_t ncrop, int64_t rows, int elem_bytes
   return f;
 }
 
+// the register path of fft_rows_block (first and last stage in registers,
+// two LDS row buffers): one-row-at-a-time shapes whose threads hold the whole
+// row (L == PPT nts), the middle half cropped (oversampling 2: the cropped
+// outputs are registers PPT / 4 .. of each thread), and two padded rows plus
+// the twiddle tables within the 160 KiB of LDS
+static int fft_db(const FftShape& f, int64_t L, int64_t crop_off, int elem_bytes) {
+  if (f.rc != 1 || (int64_t)f.nts * f.ppt != L || crop_off * 4 != L) return 0;
+  if (f.ppt / 4 + f.maxq > f.ppt) return 0;
+  const int64_t lds = (2 * (int64_t)padded_len((int)L) + 64 + std::max<int64_t>(1, L >> 6)) * elem_bytes;
+  return lds <= 160 * 1024 ? 1 : 0;
+}
+
 // calls fn.template operator()<RB, RC, MAXQ, PPT>() for the shape f
 template <class Fn>
 static void dispatch_shape(const FftShape& f, Fn&& fn) {
@@ -418,18 +607,25 @@ struct BatchedLaunch {
   FftShape f;
   int L, log2L, n;
   const float2* tw;
-  template <int RB, int RC, int MAXQ, int PPT>
-  void operator()() const {
+  template <int RB, int RC, int MAXQ, int PPT, bool DB>
+  void go() const {
     static bool attr_done = false;
     if (!attr_done) {
-      FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows_batched<RB, RC, MAXQ, PPT>,
+      FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows_batched<RB, RC, MAXQ, PPT, DB>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
       attr_done = true;
     }
-    const size_t lds = ((size_t)RC * padded_len(L) + 64 + std::max(1, L >> 6)) * sizeof(float2);
-    hipLaunchKernelGGL((k_fft_rows_batched<RB, RC, MAXQ, PPT>), dim3((unsigned)(rows / RB)), dim3(f.nts * RC), lds,
-                       b->stream, b->items_dev.as<BatchItem>(), list, b->args_dev.as<BatchArgs>(), pass, L, log2L, n,
-                       tw, log2L);
+    const size_t lds = ((size_t)(DB ? 2 : RC) * padded_len(L) + 64 + std::max(1, L >> 6)) * sizeof(float2);
+    hipLaunchKernelGGL((k_fft_rows_batched<RB, RC, MAXQ, PPT, DB>), dim3((unsigned)(rows / RB)), dim3(f.nts * RC),
+                       lds, b->stream, b->items_dev.as<BatchItem>(), list, b->args_dev.as<BatchArgs>(), pass, L, log2L,
+                       n, tw, log2L);
+  }
+  template <int RB, int RC, int MAXQ, int PPT>
+  void operator()() const {
+    if (fft_db(f, L, (L - n) / 2, (int)sizeof(float2)))
+      go<RB, RC, MAXQ, PPT, true>();
+    else
+      go<RB, RC, MAXQ, PPT, false>();
   }
 };
 
@@ -481,25 +677,32 @@ struct RowsLaunch {
   FftShape f;
   const double* dq;
   const double* drow;
-  template <int RB, int RC, int MAXQ, int PPT>
-  void operator()() const {
+  template <int RB, int RC, int MAXQ, int PPT, bool DB>
+  void go() const {
     using cx = typename CxF<real>::t;
     const int L = (int)c->G;
     int log2L = 0;
     while ((1 << log2L) < L) ++log2L;
-    const size_t lds = ((size_t)RC * padded_len(L) + 64 + std::max(1, L >> 6)) * sizeof(cx);
+    const int ncrop = (int)c->n;
+    const int crop_off = (int)((c->G - c->n) / 2);
+    const size_t lds = ((size_t)(DB ? 2 : RC) * padded_len(L) + 64 + std::max(1, L >> 6)) * sizeof(cx);
     static bool attr_done = false;
     if (!attr_done) {
-      FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows<real, RB, RC, MAXQ, PPT>,
+      FTCG_HIP(hipFuncSetAttribute((const void*)k_fft_rows<real, RB, RC, MAXQ, PPT, DB>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
       attr_done = true;
     }
-    const int ncrop = (int)c->n;
-    const int crop_off = (int)((c->G - c->n) / 2);
-    hipLaunchKernelGGL((k_fft_rows<real, RB, RC, MAXQ, PPT>), dim3((unsigned)(rows / RB)), dim3(f.nts * RC), lds,
+    hipLaunchKernelGGL((k_fft_rows<real, RB, RC, MAXQ, PPT, DB>), dim3((unsigned)(rows / RB)), dim3(f.nts * RC), lds,
                        c->stream, static_cast<const cx*>(in), in_row_stride, static_cast<cx*>(out), out_stride_q, L,
                        log2L, ncrop, crop_off, rows, pre_sign, dq, drow, static_cast<const cx*>(c->tw), log2L);
     FTCG_HIP(hipGetLastError());
+  }
+  template <int RB, int RC, int MAXQ, int PPT>
+  void operator()() const {
+    if (fft_db(f, c->G, (c->G - c->n) / 2, (int)sizeof(typename CxF<real>::t)))
+      go<RB, RC, MAXQ, PPT, true>();
+    else
+      go<RB, RC, MAXQ, PPT, false>();
   }
 };
 
