@@ -589,19 +589,25 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin2g_scatter(const double* __res
     for (int q = 0; q < 4; ++q) base[i][q] = group_claim(tile_cursor, key[i][q], kg[i][q]);
   __syncthreads();
   {
-    // one row range per row seen; a thread's claims are all in flight together
-    constexpr int PER = WROW_MAX / BIN_BLOCK;
-    int v[PER], r[PER];
+    // one row range per row seen; a thread's claims are in flight eight at a
+    // time (all sixteen took 97 VGPRs, occupancy 4; eight take 85, occupancy
+    // 5: 4096^2 binning 0.438 -> 0.425 ms)
+    constexpr int PER = WROW_MAX / BIN_BLOCK, HALF = PER / 2;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int i = threadIdx.x + q * BIN_BLOCK;
-      v[q] = i < nrow ? br[i] : 0;
+    for (int h = 0; h < PER; h += HALF) {
+      int v[HALF], r[HALF];
+#pragma unroll
+      for (int q = 0; q < HALF; ++q) {
+        const int i = threadIdx.x + (h + q) * BIN_BLOCK;
+        v[q] = i < nrow ? br[i] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < HALF; ++q)
+        r[q] = v[q] ? atomicAdd(&row_cursor[threadIdx.x + (h + q) * BIN_BLOCK], v[q]) : 0;
+#pragma unroll
+      for (int q = 0; q < HALF; ++q)
+        if (v[q]) br[threadIdx.x + (h + q) * BIN_BLOCK] = r[q];
     }
-#pragma unroll
-    for (int q = 0; q < PER; ++q) r[q] = v[q] ? atomicAdd(&row_cursor[threadIdx.x + q * BIN_BLOCK], v[q]) : 0;
-#pragma unroll
-    for (int q = 0; q < PER; ++q)
-      if (v[q]) br[threadIdx.x + q * BIN_BLOCK] = r[q];
   }
   __syncthreads();
   int rpos[BIN_IPT];
