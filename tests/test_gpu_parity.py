@@ -228,6 +228,25 @@ def test_fft_lengths(n):
     assert O.rel_l2(img, O.grid_to_image(H, n)) < 3e-6
 
 
+@pytest.mark.parametrize("dim,n,dtype", [(2, 2048, "f64"), (2, 1024, "f64"), (1, 4096, "f32"), (1, 2048, "f64"),
+                                         (1, 256, "f32"), (1, 8192, "f32")])
+def test_fft_row_shapes(dim, n, dtype):
+    # row lengths whose passes run with the first and last stage in registers
+    # and two LDS row buffers (2D float64 at G = 4096, 1D rows of 512 .. 8192
+    # points in float32 and 4096 in float64), next to ones that do not
+    # (2D float64 at G = 2048, 1D 16384 points), against the oracle
+    rng = np.random.default_rng(1000 * dim + n)
+    G = 2 * n
+    shape = (G,) * dim
+    H = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    from paper_1706_08575_amd.ftcg import Plan
+    cd = torch.complex64 if dtype == "f32" else torch.complex128
+    with Plan(n, dim=dim, dtype=dtype, weights="none") as P:
+        img = host(P.grid_to_image(dev(H, cd)))
+    tol = 3e-6 if dtype == "f32" else 1e-12
+    assert O.rel_l2(img, O.grid_to_image(H, n)) < tol
+
+
 # ---------------------------------------------------------------------------
 # edge cases
 # ---------------------------------------------------------------------------
