@@ -122,6 +122,24 @@ __device__ inline const WSample<2>* cand_at(const WSample<2>* base, int p) {
                                              __umul24((unsigned)p, (unsigned)sizeof(WSample<2>)));
 }
 
+// Copy of a chunk of staged candidates (n4 16-byte words, at most 3 CH) to
+// LDS: each thread issues all its loads before the first store, so a chunk
+// costs one memory latency instead of one per word a thread copies.
+template <int CH>
+__device__ inline void stage_chunk(const float4* __restrict__ src, float4* dst, int n4) {
+  constexpr int PER = (3 * CH + WB_BLOCK - 1) / WB_BLOCK;
+  float4 v[PER];
+  // (a chunk is never empty: the clamped index of a thread past its end
+  // reads the last word, and the store below skips it)
+#pragma unroll
+  for (int u = 0; u < PER; ++u) v[u] = src[min((int)threadIdx.x + u * WB_BLOCK, n4 - 1)];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = (int)threadIdx.x + u * WB_BLOCK;
+    if (i < n4) dst[i] = v[u];
+  }
+}
+
 // a candidate record; 2D records (48 bytes) sit in 16-byte aligned arrays
 // and are read as three 16-byte words
 template <int DIM>
@@ -272,10 +290,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_rows(const WSample<2
         const int q1 = min(q0 + WCH, ge);
         __syncthreads();  // the previous chunk has been consumed
         {
-          const float4* src = reinterpret_cast<const float4*>(ss + q0);
-          float4* dst = reinterpret_cast<float4*>(cand);
-          const int n4 = (q1 - q0) * 3;
-          for (int i = threadIdx.x; i < n4; i += WB_BLOCK) dst[i] = src[i];
+          stage_chunk<WCH>(reinterpret_cast<const float4*>(ss + q0), reinterpret_cast<float4*>(cand), (q1 - q0) * 3);
         }
         __syncthreads();
         const int a0 = max(ms, q0), a1 = min(me, q1);
@@ -485,10 +500,7 @@ __global__ __launch_bounds__(WB_BLOCK, 5) void k_frame_weights_sym(const WSample
         const int q1 = min(q0 + CH, ge);
         __syncthreads();   // the previous chunk has been consumed and flushed
         {
-          const float4* src = reinterpret_cast<const float4*>(ss + q0);
-          float4* dst = reinterpret_cast<float4*>(cand);
-          const int n4 = (q1 - q0) * 3;
-          for (int i = threadIdx.x; i < n4; i += WB_BLOCK) dst[i] = src[i];
+          stage_chunk<CH>(reinterpret_cast<const float4*>(ss + q0), reinterpret_cast<float4*>(cand), (q1 - q0) * 3);
         }
         __syncthreads();
         const int a0 = max(ms, q0) - q0, a1 = min(me, q1) - q0;
