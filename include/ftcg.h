@@ -333,7 +333,7 @@ ftcg_status ftcg_plan_timing(ftcg_plan plan, double* ms, int64_t* count);
 /* ------------------------------------------------------------------------
  * Learned frame weights (FTCG_W_LEARNED). Not in the paper: a small network
  * predicts the frame-optimal weight of eq:difopt from the local raster
- * geometry, and the plain float64 weights remain the fallback and the judge
+ * geometry, and the plain float64 weights remain the fallback and the measure
  * of its error.
  *   feature of sample j : offsets k_i - k_j (float32, nearest first) of the 16
  *                         nearest other samples within ||k_i - k_j||_inf <= R,
