@@ -67,7 +67,7 @@ typedef FTCG_ENUM {
   FTCG_ENOMEM = 2,        /* device allocation failed */
   FTCG_EHIP = 3,          /* a HIP runtime call failed */
   FTCG_ESTATE = 4,        /* call out of order (e.g. execute before set_points) */
-  FTCG_EUNSUPPORTED = 5   /* valid request this build does not implement */
+  FTCG_EUNSUPPORTED = 5   /* valid request this library does not implement */
 } ftcg_status;
 
 typedef FTCG_ENUM { FTCG_F64 = 0, FTCG_F32 = 1 } ftcg_dtype;

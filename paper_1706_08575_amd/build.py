@@ -68,7 +68,7 @@ if __name__ == "__main__":
 def build_abi_check(verbose: bool = False) -> str:
     """Executable of tests/abi_check.cpp against the library's objects, with the
     host code of the entry-point files (the .cpp sources: argument checks,
-    status plumbing, plan lifecycle) and the driver built with
+    status plumbing, plan lifecycle) and the test program built with
     AddressSanitizer and UndefinedBehaviorSanitizer. Device code is built
     as usual (the sanitizers apply to the host side only); the .hip objects
     come from the regular build. Returns the executable's path."""

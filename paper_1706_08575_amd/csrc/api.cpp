@@ -284,7 +284,7 @@ const char* ftcg_status_string(ftcg_status s) {
     case FTCG_ENOMEM: return "FTCG_ENOMEM: device allocation failed";
     case FTCG_EHIP: return "FTCG_EHIP: HIP runtime error";
     case FTCG_ESTATE: return "FTCG_ESTATE: call out of order";
-    case FTCG_EUNSUPPORTED: return "FTCG_EUNSUPPORTED: not supported by this build";
+    case FTCG_EUNSUPPORTED: return "FTCG_EUNSUPPORTED: not supported by this library";
   }
   return "FTCG_?: unknown status";
 }
