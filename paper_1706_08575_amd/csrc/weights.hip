@@ -742,13 +742,17 @@ void launch_check_reduce(ftcg_plan p, const unsigned long long* part, int nparts
 //     samples there as {k, caller index, bin column} (rowbuf, grouped by row);
 //  4. k_wrow_sort: one workgroup per row reads its range in order, counts the
 //     samples per bin column in LDS, scans them, writes the bin offsets boff
-//     of the whole row, orders the row in LDS (rows of up to WROW_LMAX
+//     of the whole row, orders the row in LDS (rows of up to WROW_LMAX_*
 //     samples) and writes the sorted samples (k, sin, cos) and their caller
 //     index coalesced, and (when asked) the inverse map; longer rows place
 //     their samples directly. Every write stays inside the row's own range.
 // The row counters arrive zeroed (the input check clears them).
 constexpr int WROW_IPT = 4;
-constexpr int WROW_LMAX = 16384;   // rows up to this many samples are ordered in LDS
+// Rows up to this many samples are ordered in LDS (a position and a column
+// array of 2 bytes per sample): 16000 with 1024 threads per row (80 KiB of
+// LDS, two workgroups per compute unit), 8192 with 256 (49 KiB, three).
+constexpr int WROW_LMAX_WIDE = 16000;
+constexpr int WROW_LMAX_NARROW = 8192;
 
 
 // Steps 1 and 3 take `rounds` groups of WROW_IPT * WB_BLOCK consecutive
@@ -855,7 +859,7 @@ __global__ __launch_bounds__(WB_BLOCK) void k_wrow_scatter(const double* __restr
 // BS threads per row: 1024 for rows of thousands of samples (the LDS of a
 // row keeps at most three workgroups on a compute unit, so wider workgroups
 // are what puts more wavefronts in flight), 256 below
-template <int BS>
+template <int BS, int LMAX>
 __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __restrict__ row_off,
                                                   const RowRec* __restrict__ rowbuf,
                                                   int32_t* __restrict__ boff, WSample<2>* __restrict__ ss,
@@ -864,9 +868,11 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
   constexpr int ITEMS = 4096 / BS;
   __shared__ int32_t cnt[4096 + 64];   // bin counters, then one spare word per lane
   __shared__ int32_t wsum[BS / 64];
-  __shared__ uint16_t perm[WROW_LMAX];
+  __shared__ uint16_t perm[LMAX];
+  __shared__ uint16_t col[LMAX];       // bin column of each row entry, kept by the counting pass
   const int b0 = blockIdx.x, nb1 = g.nb[1];
   const int rs = row_off[b0], re = row_off[b0 + 1];
+  const bool fits = re - rs <= LMAX;
   const int t = threadIdx.x;
   for (int i = t; i < nb1; i += BS) cnt[i] = 0;
   __syncthreads();
@@ -878,7 +884,10 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
     for (int u = 0; u < SU; ++u) b[u] = i0 + u * BS < re ? rowbuf[i0 + u * BS].b1 : -1;
 #pragma unroll
     for (int u = 0; u < SU; ++u)
-      if (b[u] >= 0) atomicAdd(&cnt[b[u]], 1);
+      if (b[u] >= 0) {
+        atomicAdd(&cnt[b[u]], 1);
+        if (fits) col[i0 + u * BS - rs] = (uint16_t)b[u];
+      }
   }
   __syncthreads();
   // exclusive scan of cnt[0 .. nb1): thread t owns entries t*ITEMS .. +ITEMS-1
@@ -913,13 +922,14 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
   }
   if (b0 == g.nb[0] - 1 && t == 0) boff[g.nb[0] * nb1] = re;
   __syncthreads();
-  if (re - rs <= WROW_LMAX) {
+  if (fits) {
     // rows that fit: the sorted order is built in LDS first (perm[pos] = the
-    // row entry placed at pos), so the sorted arrays are written coalesced
+    // row entry placed at pos; the columns come from LDS, not from a second
+    // read of the records), so the sorted arrays are written coalesced
     for (int i0 = rs + t; i0 < re; i0 += SU * BS) {
       int b[SU], pos[SU];
 #pragma unroll
-      for (int u = 0; u < SU; ++u) b[u] = i0 + u * BS < re ? rowbuf[i0 + u * BS].b1 : -1;
+      for (int u = 0; u < SU; ++u) b[u] = i0 + u * BS < re ? (int)col[i0 + u * BS - rs] : -1;
       // branch-free claims (entries past the end add to a spare word per lane)
 #pragma unroll
       for (int u = 0; u < SU; ++u) pos[u] = atomicAdd(&cnt[b[u] >= 0 ? b[u] : 4096 + (int)__lane_id()], 1);
@@ -1019,9 +1029,9 @@ void sort_weight_rows(ftcg_plan p) {
                        p->ws_idx.as<int32_t>(), need_inv ? p->ws_inv.as<int32_t>() : nullptr, p->ws_sum.as<double>());
   };
   if (p->m >= (int64_t)4096 * g.nb[0])   // rows of 4096 samples or more on average
-    launch(k_wrow_sort<1024>, 1024);
+    launch(k_wrow_sort<1024, WROW_LMAX_WIDE>, 1024);
   else
-    launch(k_wrow_sort<WB_BLOCK>, WB_BLOCK);
+    launch(k_wrow_sort<WB_BLOCK, WROW_LMAX_NARROW>, WB_BLOCK);
   FTCG_HIP(hipGetLastError());
   p->ws_sum_fresh = true;
 }
