@@ -317,23 +317,68 @@ __global__ __launch_bounds__(WB_BLOCK) void k_frame_weights_rows(const WSample<2
 // float64 atomic per touched candidate into the bin-order sums, which start
 // from the self terms pi^4 preset by the bin sort. Launch shape and staging
 // as k_frame_weights_rows with one sample per lane group.
-// One staged candidate (chunk slot p) against the WT samples of a lane:
-// each in-box square goes to the sample's sum and, summed over the WT
-// samples, to the candidate's slot. Every candidate of a lane's ranges pairs
-// with all of its samples: in the own bin row the range starts after the
-// lane's last live sample (the pair of the lane's two samples is added once,
-// outside the loop), and a lane's idle sample sits far outside every box.
+// pi^2 T_in of one staged candidate for each of the WT (<= 2) samples of a
+// lane, 0 outside the box. As pair_term, with one float64 reciprocal for both
+// samples: r = 1 / (den_0 den_1), q_0 = num_0 den_1 r, q_1 = num_1 den_0 r.
+// With eps = 2^-250 a den lies in [2^-500, 2^64) for a live sample (|d| below
+// 2^32 inside any window) and near 2^200 for an idle one (at 2^100), so the
+// product of two stays a normal number; d + eps == d for |d| >= 2^-196,
+// below which the factor is pi to rounding either way.
+constexpr double WEPS_SYM = 0x1p-250;
+constexpr double WPI_EPS_SYM = WPI * WEPS_SYM;
+template <int WT>
+__device__ inline void sym_terms(const WSample<2>& o, const double (&x)[WT][2], const double (&sn)[WT][2],
+                                 const double (&cs)[WT][2], double R, double (&q)[WT]) {
+#pragma clang fp contract(off)
+  static_assert(WT == 1 || WT == 2, "one shared reciprocal for at most two samples");
+  double num[WT], den[WT];
+  bool in[WT];
+#pragma unroll
+  for (int u = 0; u < WT; ++u) {
+    const double d0 = o.k[0] - x[u][0], d1 = o.k[1] - x[u][1];
+    in[u] = fmax(fabs(d0), fabs(d1)) <= R;
+    // sin(pi (k_i - k_n)) = sin(pi k_i) cos(pi k_n) - cos(pi k_i) sin(pi k_n),
+    // both products rounded, so it is exactly 0 when k_i == k_n
+    const double s0 = o.sc[0][0] * cs[u][0] - o.sc[0][1] * sn[u][0];
+    const double s1 = o.sc[1][0] * cs[u][1] - o.sc[1][1] * sn[u][1];
+    num[u] = (s0 + WPI_EPS_SYM) * (s1 + WPI_EPS_SYM);
+    den[u] = (d0 + WEPS_SYM) * (d1 + WEPS_SYM);
+  }
+  if constexpr (WT == 1) {
+    q[0] = num[0] * rcp64(den[0]);
+  } else {
+    const double r = rcp64(den[0] * den[1]);
+    q[0] = num[0] * (den[1] * r);
+    q[1] = num[1] * (den[0] * r);
+  }
+#pragma unroll
+  for (int u = 0; u < WT; ++u) q[u] = __hiloint2double(in[u] ? __double2hiint(q[u]) : 0, __double2loint(q[u]));
+}
+
+// One staged candidate (chunk slot p) against the WT samples of a lane. A
+// lane's own sums take the squares as they are: the bin sort orders every bin
+// by caller index, so a lane's samples, its ranges and the order in which it
+// walks them are the same on every run, and each of its sums is rounded to
+// the quantum of the sums once, before it leaves the lane. The candidate's
+// slot, which lanes add to in any order, takes the sum of its squares rounded
+// to that quantum (two fused multiply-adds onto 1.5 * 2^16, then the exact
+// subtraction). Every candidate of a lane's ranges pairs with all of its
+// samples: in the own bin row the range starts after the lane's last live
+// sample (the pair of the lane's two samples is added once, outside the
+// loop), and a lane's idle sample sits far outside every box.
 template <int WT>
 __device__ inline void sym_pair(double (&acc)[WT], double* cacc, int p, const WSample<2>& o,
                                 const double (&x)[WT][2], const double (&sn)[WT][2], const double (&cs)[WT][2],
                                 double R) {
-  double csum = 0.0;
+  double q[WT];
+  sym_terms<WT>(o, x, sn, cs, R, q);
+  double c = WQ_MAGIC;
 #pragma unroll
   for (int u = 0; u < WT; ++u) {
-    const double q2 = wq_square(pair_term<2>(o, x[u], sn[u], cs[u], R));
-    acc[u] += q2;
-    csum += q2;
+    acc[u] = fma(q[u], q[u], acc[u]);
+    c = fma(q[u], q[u], c);
   }
+  const double csum = c - WQ_MAGIC;
   if (csum != 0.0) __hip_atomic_fetch_add(cacc + p, csum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -504,14 +549,14 @@ __global__ __launch_bounds__(WB_BLOCK, 5) void k_frame_weights_sym(const WSample
         }
         __syncthreads();
         const int a0 = max(ms, q0) - q0, a1 = min(me, q1) - q0;
-        // Each lane starts at its own rotation of its range: lanes of one bin
-        // walk the same range, and a start on slot (lane mod 16) mod 16 puts
-        // the 16 lanes of a quarter wavefront on different LDS banks (a
-        // 48-byte record covers 12 banks of 4 bytes; records 16 apart share
-        // them), for the record reads and the slot atomics alike.
+        // Each group starts at its own rotation of its range (a function of
+        // its first sample and of the range, so a lane's order of addition
+        // is the same on every run): groups of one bin walk the same range,
+        // and different starts spread their slot atomics and record reads
+        // over different slots and LDS banks.
         const int len = a1 - a0;
         if (len > 0) {
-          const unsigned ph = ((unsigned)threadIdx.x - (unsigned)a0) & 15u;
+          const unsigned ph = ((unsigned)t0 * 5u + (unsigned)sub * 8u - (unsigned)a0) & 15u;
           int p = a0 + (int)(ph % (unsigned)len);
           for (int j = 0; j < len; ++j) {
             sym_pair<WT>(acc, cacc, p, ld_wsample(cand_at(cand, p)), x, sn, cs, g.R);
@@ -552,7 +597,8 @@ __global__ __launch_bounds__(WB_BLOCK, 5) void k_frame_weights_sym(const WSample
     for (int u = 0; u < WT; ++u) {
 #pragma unroll
       for (int off = 1; off < S; off <<= 1) acc[u] += __shfl_xor(acc[u], off, 64);
-      if (sub == 0 && live[u]) unsafeAtomicAdd(wsum + t0 + u, acc[u]);
+      // rounded to the quantum of the sums (exact from here on)
+      if (sub == 0 && live[u]) unsafeAtomicAdd(wsum + t0 + u, (acc[u] + WQ_MAGIC) - WQ_MAGIC);
     }
   }
 }
@@ -748,7 +794,7 @@ void launch_check_reduce(ftcg_plan p, const unsigned long long* part, int nparts
 //     their samples directly. Every write stays inside the row's own range.
 // The row counters arrive zeroed (the input check clears them).
 constexpr int WROW_IPT = 4;
-// Rows up to this many samples are ordered in LDS (a position and a column
+// Rows up to this many samples are ordered in LDS (a position and a key
 // array of 2 bytes per sample): 16000 with 1024 threads per row (80 KiB of
 // LDS, two workgroups per compute unit), 8192 with 256 (49 KiB, three).
 constexpr int WROW_LMAX_WIDE = 16000;
@@ -869,7 +915,7 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
   __shared__ int32_t cnt[4096 + 64];   // bin counters, then one spare word per lane
   __shared__ int32_t wsum[BS / 64];
   __shared__ uint16_t perm[LMAX];
-  __shared__ uint16_t col[LMAX];       // bin column of each row entry, kept by the counting pass
+  __shared__ uint16_t key[LMAX];       // low 16 bits of the caller index of the entry at each position
   const int b0 = blockIdx.x, nb1 = g.nb[1];
   const int rs = row_off[b0], re = row_off[b0 + 1];
   const bool fits = re - rs <= LMAX;
@@ -884,10 +930,7 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
     for (int u = 0; u < SU; ++u) b[u] = i0 + u * BS < re ? rowbuf[i0 + u * BS].b1 : -1;
 #pragma unroll
     for (int u = 0; u < SU; ++u)
-      if (b[u] >= 0) {
-        atomicAdd(&cnt[b[u]], 1);
-        if (fits) col[i0 + u * BS - rs] = (uint16_t)b[u];
-      }
+      if (b[u] >= 0) atomicAdd(&cnt[b[u]], 1);
   }
   __syncthreads();
   // exclusive scan of cnt[0 .. nb1): thread t owns entries t*ITEMS .. +ITEMS-1
@@ -923,21 +966,33 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
   if (b0 == g.nb[0] - 1 && t == 0) boff[g.nb[0] * nb1] = re;
   __syncthreads();
   if (fits) {
-    // rows that fit: the sorted order is built in LDS first (perm[pos] = the
-    // row entry placed at pos; the columns come from LDS, not from a second
-    // read of the records), so the sorted arrays are written coalesced
+    // rows that fit: the order is built in LDS first (perm[pos] = the row
+    // entry claimed at pos, key[pos] the low bits of its caller index), so the
+    // sorted arrays are written coalesced
     for (int i0 = rs + t; i0 < re; i0 += SU * BS) {
-      int b[SU], pos[SU];
+      int b[SU], pos[SU], jj[SU];
 #pragma unroll
-      for (int u = 0; u < SU; ++u) b[u] = i0 + u * BS < re ? (int)col[i0 + u * BS - rs] : -1;
+      for (int u = 0; u < SU; ++u) {
+        const bool in = i0 + u * BS < re;
+        b[u] = in ? rowbuf[i0 + u * BS].b1 : -1;
+        jj[u] = in ? rowbuf[i0 + u * BS].j : 0;
+      }
       // branch-free claims (entries past the end add to a spare word per lane)
 #pragma unroll
       for (int u = 0; u < SU; ++u) pos[u] = atomicAdd(&cnt[b[u] >= 0 ? b[u] : 4096 + (int)__lane_id()], 1);
 #pragma unroll
       for (int u = 0; u < SU; ++u)
-        if (b[u] >= 0) perm[pos[u] - rs] = (uint16_t)(i0 + u * BS - rs);
+        if (b[u] >= 0) {
+          perm[pos[u] - rs] = (uint16_t)(i0 + u * BS - rs);
+          key[pos[u] - rs] = (uint16_t)(jj[u] & 0xffff);
+        }
     }
     __syncthreads();
+    // The claims above come in whatever order the lanes' atomics meet; each
+    // sample then goes to its rank within its bin by caller index (low 16
+    // bits first, the full index on equal low bits), so the order within a
+    // bin, and everything summed in bin order, is the same on every run. The
+    // counters now hold the end of each bin (the start of the next).
     for (int q0 = t; q0 < re - rs; q0 += SU * BS) {
       RowRec r[SU];
 #pragma unroll
@@ -949,15 +1004,28 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
       for (int u = 0; u < SU; ++u) {
         const int q = q0 + u * BS;
         if (q < re - rs) {
+          const int b = r[u].b1;
+          const int bs = (b > 0 ? cnt[b - 1] : rs) - rs, be = cnt[b] - rs;
+          const int kq = key[q];
+          int rank = 0;
+          for (int q2 = bs; q2 < be; ++q2) {
+            const int k2 = key[q2];
+            if (k2 < kq) {
+              ++rank;
+            } else if (k2 == kq && q2 != q) {
+              if (rowbuf[rs + perm[q2]].j < r[u].j) ++rank;
+            }
+          }
+          const int d = bs + rank;
           WSample<2> smp;
           smp.k[0] = r[u].k0;
           smp.k[1] = r[u].k1;
           sincospi(r[u].k0, &smp.sc[0][0], &smp.sc[0][1]);
           sincospi(r[u].k1, &smp.sc[1][0], &smp.sc[1][1]);
-          ss[rs + q] = smp;
-          sidx[rs + q] = r[u].j;
-          if (inv) inv[r[u].j] = rs + q;
-          if (sums) sums[rs + q] = wself<2>();   // the self term
+          ss[rs + d] = smp;
+          sidx[rs + d] = r[u].j;
+          if (inv) inv[r[u].j] = rs + d;
+          if (sums) sums[rs + d] = wself<2>();   // the self term
         }
       }
     }
@@ -975,6 +1043,36 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
     sidx[pos] = r.j;
     if (inv) inv[r.j] = pos;
     if (sums) sums[pos] = wself<2>();
+  }
+}
+
+// Rows too long for LDS were placed in atomic claim order; here each of
+// their bins is put in caller-index order (an insertion sort by one thread
+// per bin, moving the sample records and the caller indices and fixing the
+// inverse map), so that every bin is ordered the same way on every run.
+// Rows that fit were ordered by the row sort; their workgroups return.
+template <int BS, int LMAX>
+__global__ __launch_bounds__(BS) void k_wrow_order(WBinGeom g, const int32_t* __restrict__ row_off,
+                                                   const int32_t* __restrict__ boff, WSample<2>* __restrict__ ss,
+                                                   int32_t* __restrict__ sidx, int32_t* __restrict__ inv) {
+  const int b0 = blockIdx.x, nb1 = g.nb[1];
+  if (row_off[b0 + 1] - row_off[b0] <= LMAX) return;
+  for (int c = threadIdx.x; c < nb1; c += BS) {
+    const int bs = boff[b0 * nb1 + c], be = boff[b0 * nb1 + c + 1];
+    for (int i = bs + 1; i < be; ++i) {
+      const WSample<2> w = ss[i];
+      const int32_t j = sidx[i];
+      int p = i;
+      while (p > bs && sidx[p - 1] > j) {
+        ss[p] = ss[p - 1];
+        sidx[p] = sidx[p - 1];
+        --p;
+      }
+      ss[p] = w;
+      sidx[p] = j;
+    }
+    if (inv)
+      for (int i = bs; i < be; ++i) inv[sidx[i]] = i;
   }
 }
 
@@ -1028,10 +1126,18 @@ void sort_weight_rows(ftcg_plan p) {
                        p->wb_rowbuf.as<RowRec>(), p->wb_off.as<int32_t>(), p->ws_k.as<WSample<2>>(),
                        p->ws_idx.as<int32_t>(), need_inv ? p->ws_inv.as<int32_t>() : nullptr, p->ws_sum.as<double>());
   };
-  if (p->m >= (int64_t)4096 * g.nb[0])   // rows of 4096 samples or more on average
+  auto order = [&](auto kern, int bs) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)g.nb[0]), dim3(bs), 0, p->stream, g, p->wb_rowoff.as<int32_t>(),
+                       p->wb_off.as<int32_t>(), p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(),
+                       need_inv ? p->ws_inv.as<int32_t>() : nullptr);
+  };
+  if (p->m >= (int64_t)4096 * g.nb[0]) {   // rows of 4096 samples or more on average
     launch(k_wrow_sort<1024, WROW_LMAX_WIDE>, 1024);
-  else
+    order(k_wrow_order<WB_BLOCK, WROW_LMAX_WIDE>, WB_BLOCK);
+  } else {
     launch(k_wrow_sort<WB_BLOCK, WROW_LMAX_NARROW>, WB_BLOCK);
+    order(k_wrow_order<WB_BLOCK, WROW_LMAX_NARROW>, WB_BLOCK);
+  }
   FTCG_HIP(hipGetLastError());
   p->ws_sum_fresh = true;
 }
