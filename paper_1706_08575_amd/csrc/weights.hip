@@ -1041,24 +1041,15 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
     sincospi(r.k1, &smp.sc[1][0], &smp.sc[1][1]);
     ss[pos] = smp;
     sidx[pos] = r.j;
-    if (inv) inv[r.j] = pos;
     if (sums) sums[pos] = wself<2>();
   }
-}
-
-// Rows too long for LDS were placed in atomic claim order; here each of
-// their bins is put in caller-index order (an insertion sort by one thread
-// per bin, moving the sample records and the caller indices and fixing the
-// inverse map), so that every bin is ordered the same way on every run.
-// Rows that fit were ordered by the row sort; their workgroups return.
-template <int BS, int LMAX>
-__global__ __launch_bounds__(BS) void k_wrow_order(WBinGeom g, const int32_t* __restrict__ row_off,
-                                                   const int32_t* __restrict__ boff, WSample<2>* __restrict__ ss,
-                                                   int32_t* __restrict__ sidx, int32_t* __restrict__ inv) {
-  const int b0 = blockIdx.x, nb1 = g.nb[1];
-  if (row_off[b0 + 1] - row_off[b0] <= LMAX) return;
-  for (int c = threadIdx.x; c < nb1; c += BS) {
-    const int bs = boff[b0 * nb1 + c], be = boff[b0 * nb1 + c + 1];
+  // Rows too long for LDS were placed in claim order; each of their bins is
+  // then put in caller-index order (an insertion sort by one thread per bin,
+  // on the records the workgroup has just written: the barrier makes them
+  // visible), and the inverse map written from that order.
+  __syncthreads();
+  for (int c = t; c < nb1; c += BS) {
+    const int bs = boff[b0 * nb1 + c], be = c + 1 < nb1 ? boff[b0 * nb1 + c + 1] : re;
     for (int i = bs + 1; i < be; ++i) {
       const WSample<2> w = ss[i];
       const int32_t j = sidx[i];
@@ -1126,18 +1117,10 @@ void sort_weight_rows(ftcg_plan p) {
                        p->wb_rowbuf.as<RowRec>(), p->wb_off.as<int32_t>(), p->ws_k.as<WSample<2>>(),
                        p->ws_idx.as<int32_t>(), need_inv ? p->ws_inv.as<int32_t>() : nullptr, p->ws_sum.as<double>());
   };
-  auto order = [&](auto kern, int bs) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)g.nb[0]), dim3(bs), 0, p->stream, g, p->wb_rowoff.as<int32_t>(),
-                       p->wb_off.as<int32_t>(), p->ws_k.as<WSample<2>>(), p->ws_idx.as<int32_t>(),
-                       need_inv ? p->ws_inv.as<int32_t>() : nullptr);
-  };
-  if (p->m >= (int64_t)4096 * g.nb[0]) {   // rows of 4096 samples or more on average
+  if (p->m >= (int64_t)4096 * g.nb[0])   // rows of 4096 samples or more on average
     launch(k_wrow_sort<1024, WROW_LMAX_WIDE>, 1024);
-    order(k_wrow_order<WB_BLOCK, WROW_LMAX_WIDE>, WB_BLOCK);
-  } else {
+  else
     launch(k_wrow_sort<WB_BLOCK, WROW_LMAX_NARROW>, WB_BLOCK);
-    order(k_wrow_order<WB_BLOCK, WROW_LMAX_NARROW>, WB_BLOCK);
-  }
   FTCG_HIP(hipGetLastError());
   p->ws_sum_fresh = true;
 }
