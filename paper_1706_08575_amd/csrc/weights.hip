@@ -794,11 +794,12 @@ void launch_check_reduce(ftcg_plan p, const unsigned long long* part, int nparts
 //     their samples directly. Every write stays inside the row's own range.
 // The row counters arrive zeroed (the input check clears them).
 constexpr int WROW_IPT = 4;
-// Rows up to this many samples are ordered in LDS (a position and a key
-// array of 2 bytes per sample): 16000 with 1024 threads per row (80 KiB of
-// LDS, two workgroups per compute unit), 8192 with 256 (49 KiB, three).
-constexpr int WROW_LMAX_WIDE = 16000;
-constexpr int WROW_LMAX_NARROW = 8192;
+// Rows up to this many samples are ordered in LDS (a position, a column and
+// a key array of 2 bytes per sample): 10240 with 1024 threads per row (77 KiB
+// of LDS, two workgroups per compute unit), 6144 with 256 (53 KiB, three).
+// Longer rows are placed by global claims and ordered after the placement.
+constexpr int WROW_LMAX_WIDE = 10240;
+constexpr int WROW_LMAX_NARROW = 6144;
 
 
 // Steps 1 and 3 take `rounds` groups of WROW_IPT * WB_BLOCK consecutive
@@ -915,7 +916,8 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
   __shared__ int32_t cnt[4096 + 64];   // bin counters, then one spare word per lane
   __shared__ int32_t wsum[BS / 64];
   __shared__ uint16_t perm[LMAX];
-  __shared__ uint16_t key[LMAX];       // low 16 bits of the caller index of the entry at each position
+  __shared__ uint16_t col[LMAX];       // bin column of each row entry (from the counting pass)
+  __shared__ uint16_t key[LMAX];       // low 16 bits of each row entry's caller index
   const int b0 = blockIdx.x, nb1 = g.nb[1];
   const int rs = row_off[b0], re = row_off[b0 + 1];
   const bool fits = re - rs <= LMAX;
@@ -925,12 +927,22 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
   // (SU entries per thread per step: their loads are in flight together)
   constexpr int SU = 4;
   for (int i0 = rs + t; i0 < re; i0 += SU * BS) {
-    int b[SU];
+    int b[SU], jj[SU];
 #pragma unroll
-    for (int u = 0; u < SU; ++u) b[u] = i0 + u * BS < re ? rowbuf[i0 + u * BS].b1 : -1;
+    for (int u = 0; u < SU; ++u) {
+      const bool in = i0 + u * BS < re;
+      b[u] = in ? rowbuf[i0 + u * BS].b1 : -1;
+      jj[u] = in ? rowbuf[i0 + u * BS].j : 0;
+    }
 #pragma unroll
     for (int u = 0; u < SU; ++u)
-      if (b[u] >= 0) atomicAdd(&cnt[b[u]], 1);
+      if (b[u] >= 0) {
+        atomicAdd(&cnt[b[u]], 1);
+        if (fits) {
+          col[i0 + u * BS - rs] = (uint16_t)b[u];
+          key[i0 + u * BS - rs] = (uint16_t)(jj[u] & 0xffff);
+        }
+      }
   }
   __syncthreads();
   // exclusive scan of cnt[0 .. nb1): thread t owns entries t*ITEMS .. +ITEMS-1
@@ -967,25 +979,19 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
   __syncthreads();
   if (fits) {
     // rows that fit: the order is built in LDS first (perm[pos] = the row
-    // entry claimed at pos, key[pos] the low bits of its caller index), so the
-    // sorted arrays are written coalesced
+    // entry claimed at pos; columns and keys kept by the counting pass, so the
+    // records are not read again for the claims), so the sorted arrays are
+    // written coalesced
     for (int i0 = rs + t; i0 < re; i0 += SU * BS) {
-      int b[SU], pos[SU], jj[SU];
+      int b[SU], pos[SU];
 #pragma unroll
-      for (int u = 0; u < SU; ++u) {
-        const bool in = i0 + u * BS < re;
-        b[u] = in ? rowbuf[i0 + u * BS].b1 : -1;
-        jj[u] = in ? rowbuf[i0 + u * BS].j : 0;
-      }
+      for (int u = 0; u < SU; ++u) b[u] = i0 + u * BS < re ? (int)col[i0 + u * BS - rs] : -1;
       // branch-free claims (entries past the end add to a spare word per lane)
 #pragma unroll
       for (int u = 0; u < SU; ++u) pos[u] = atomicAdd(&cnt[b[u] >= 0 ? b[u] : 4096 + (int)__lane_id()], 1);
 #pragma unroll
       for (int u = 0; u < SU; ++u)
-        if (b[u] >= 0) {
-          perm[pos[u] - rs] = (uint16_t)(i0 + u * BS - rs);
-          key[pos[u] - rs] = (uint16_t)(jj[u] & 0xffff);
-        }
+        if (b[u] >= 0) perm[pos[u] - rs] = (uint16_t)(i0 + u * BS - rs);
     }
     __syncthreads();
     // The claims above come in whatever order the lanes' atomics meet; each
@@ -1006,10 +1012,10 @@ __global__ __launch_bounds__(BS) void k_wrow_sort(WBinGeom g, const int32_t* __r
         if (q < re - rs) {
           const int b = r[u].b1;
           const int bs = (b > 0 ? cnt[b - 1] : rs) - rs, be = cnt[b] - rs;
-          const int kq = key[q];
+          const int kq = key[perm[q]];
           int rank = 0;
           for (int q2 = bs; q2 < be; ++q2) {
-            const int k2 = key[q2];
+            const int k2 = key[perm[q2]];
             if (k2 < kq) {
               ++rank;
             } else if (k2 == kq && q2 != q) {
