@@ -549,14 +549,18 @@ __global__ __launch_bounds__(WB_BLOCK, 5) void k_frame_weights_sym(const WSample
         }
         __syncthreads();
         const int a0 = max(ms, q0) - q0, a1 = min(me, q1) - q0;
-        // Each group starts at its own rotation of its range (a function of
-        // its first sample and of the range, so a lane's order of addition
-        // is the same on every run): groups of one bin walk the same range,
-        // and different starts spread their slot atomics and record reads
-        // over different slots and LDS banks.
+        // Each lane starts at its own rotation of its range, on slot
+        // (t0 / WT) S + sub modulo 16: groups of one bin walk the same range,
+        // and the work order puts neighbouring groups (the same bins, so the
+        // same work) in neighbouring lanes, whose starts then fall on
+        // different LDS banks (a 48-byte record covers 12 of the 64 four-byte
+        // banks; records 16 apart share them), for the record reads and the
+        // slot atomics alike. The start is a function of the group and the
+        // range, not of the lane, so a lane's order of addition is the same
+        // on every run.
         const int len = a1 - a0;
         if (len > 0) {
-          const unsigned ph = ((unsigned)t0 * 5u + (unsigned)sub * 8u - (unsigned)a0) & 15u;
+          const unsigned ph = ((unsigned)((t0 / WT) * S + sub) - (unsigned)a0) & 15u;
           int p = a0 + (int)(ph % (unsigned)len);
           for (int j = 0; j < len; ++j) {
             sym_pair<WT>(acc, cacc, p, ld_wsample(cand_at(cand, p)), x, sn, cs, g.R);
