@@ -137,18 +137,9 @@ struct TileGeom {
   int T;                  // tile edge
   int nt;                 // tiles per axis
   int W;
+  int tshift;             // log2 T when T is a power of two, else -1
+  double inv_g;           // 1 / G, used (exactly) when G is a power of two, else 0
 };
-
-// u modulo G in [0, G). Rounding can land exactly on G; anything still
-// outside [0, G) (a non-finite u, or |u| so large that the reduction has no
-// bits left) becomes 0, so every tile key stays in range for any input. The
-// binning can run before the host has seen the input check, which then
-// rejects non-finite samples.
-__device__ inline double wrap_u(double u, double G) {
-  double w = u - G * floor(u / G);
-  if (w >= G) w -= G;
-  return (w >= 0.0 && w < G) ? w : 0.0;
-}
 
 __device__ inline int floor_div(int a, int b) {  // b > 0
   int q = a / b;
@@ -157,14 +148,30 @@ __device__ inline int floor_div(int a, int b) {  // b > 0
 
 __device__ inline int wrap_tile(int t, int nt) { return t < 0 ? t + nt : (t >= nt ? t - nt : t); }
 
+// u modulo G in [0, G). Rounding can land exactly on G; anything still
+// outside [0, G) (a non-finite u, or |u| so large that the reduction has no
+// bits left) becomes 0, so every tile key stays in range for any input. The
+// binning can run before the host has seen the input check, which then
+// rejects non-finite samples. Where G is a power of two (the usual case),
+// u / G is exactly u * (1 / G), and where the tile edge T is one,
+// floor(a / T) is exactly a >> log2 T: the same results bit for bit without
+// the divisions.
+__device__ inline double wrap_u(double u, const TileGeom& g) {
+  const double G = (double)g.G;
+  double w = u - G * floor(g.inv_g != 0.0 ? u * g.inv_g : u / G);
+  if (w >= G) w -= G;
+  return (w >= 0.0 && w < G) ? w : 0.0;
+}
+__device__ inline int tile_floor(int a, const TileGeom& g) { return g.tshift >= 0 ? a >> g.tshift : floor_div(a, g.T); }
+
 template <int DIM>
 __device__ inline void sample_tiles(const double* __restrict__ k, int64_t j, const TileGeom& g, double* u,
                                     int* c, int* tlo, int* thi) {
   for (int a = 0; a < DIM; ++a) {
-    u[a] = wrap_u(g.sigma * k[j * DIM + a] + g.half_g, (double)g.G);
+    u[a] = wrap_u(g.sigma * k[j * DIM + a] + g.half_g, g);
     c[a] = (int)floor(u[a]);
-    tlo[a] = floor_div(c[a] - g.W + 1, g.T);
-    thi[a] = floor_div(c[a] + g.W, g.T);
+    tlo[a] = tile_floor(c[a] - g.W + 1, g);
+    thi[a] = tile_floor(c[a] + g.W, g);
   }
 }
 
@@ -666,6 +673,10 @@ static TileGeom tile_geom(ftcg_plan p) {
   g.T = p->tile;
   g.nt = (int)p->nt;
   g.W = p->W;
+  g.tshift = -1;
+  for (int s = 0; s < 31; ++s)
+    if ((1 << s) == g.T) g.tshift = s;
+  g.inv_g = (g.G > 0 && (g.G & (g.G - 1)) == 0) ? 1.0 / (double)g.G : 0.0;
   return g;
 }
 
