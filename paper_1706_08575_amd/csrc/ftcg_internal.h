@@ -94,16 +94,18 @@ constexpr double WPI = 3.141592653589793238462643383279502884;
 template <int DIM>
 constexpr double wscale() { return DIM == 1 ? WPI * WPI : WPI * WPI * WPI * WPI; }
 
-// Determinism of the frame-weight sums. Every term (pi^DIM T_in)^2 <= pi^4
-// that enters a sum is rounded to a multiple of 2^-36 (one fused
-// multiply-add against 1.5 * 2^16, whose neighbours are 2^-36 apart, then the
-// exact subtraction of that constant), and so is the self term. Sums of such
-// multiples are exact while they stay below 2^17 (sum T^2 below about 1300 in
-// 2D and 13000 in 1D, far above any raster's density), so the order in which
-// lanes, LDS atomics and global atomics add them does not change a bit: the
-// weights are bitwise reproducible although the kernels add with atomics.
-// The rounding moves each term by at most 2^-37 absolutely, about 1e-13 of
-// the sum, which always holds the self term pi^DIM.
+// Determinism of the frame-weight sums. Every value that an atomic adds to a
+// sum is rounded to a multiple of 2^-36 (one fused multiply-add against
+// 1.5 * 2^16, whose neighbours are 2^-36 apart, then the exact subtraction of
+// that constant): each term (pi^DIM T_in)^2 <= pi^4 in most kernels, a lane's
+// partial sum (added in a fixed order: bins are ordered by caller index) in
+// the symmetric 2D kernel, and the self term. Sums of such multiples are
+// exact while they stay below 2^17 (sum T^2 below about 1300 in 2D and 13000
+// in 1D, far above any raster's density), so the order in which lanes, LDS
+// atomics and global atomics add them does not change a bit: the weights are
+// bitwise reproducible although the kernels add with atomics. Each rounding
+// moves a value by at most 2^-37 absolutely, about 1e-13 of the sum, which
+// always holds the self term pi^DIM.
 constexpr double WQ_MAGIC = 98304.0;   // 1.5 * 2^16
 __device__ inline double wq_square(double q) { return fma(q, q, WQ_MAGIC) - WQ_MAGIC; }
 template <int DIM>
