@@ -63,17 +63,20 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_check_points(const double* __rest
         x[u][1] = (j < m && dim == 2) ? k[j * dim + 1] : 0.0;
       }
     }
+    // (branch-free; the axis loop has a compile-time bound for 2D points)
+    const int nd = VEC ? 2 : dim;
 #pragma unroll
     for (int u = 0; u < CHECK_UNROLL; ++u) {
-      if (j0 + u * gs >= m) continue;
-      for (int a = 0; a < dim; ++a) {
-        if (!isfinite(x[u][a])) {
-          bad = true;
-          continue;
-        }
+      const bool in = j0 + u * gs < m;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        if (a >= nd) break;
+        const bool fin = isfinite(x[u][a]);
+        bad = bad || (in && !fin);
+        const bool use = in && fin;
         const unsigned long long o = ordered_bits(x[u][a]);
-        lo[a] = o < lo[a] ? o : lo[a];
-        hi[a] = o > hi[a] ? o : hi[a];
+        lo[a] = (use && o < lo[a]) ? o : lo[a];
+        hi[a] = (use && o > hi[a]) ? o : hi[a];
       }
     }
   }
