@@ -365,8 +365,12 @@ __device__ inline void sym_terms(const WSample<2>& o, const double (&x)[WT][2], 
 // subtraction). Every candidate of a lane's ranges pairs with all of its
 // samples: in the own bin row the range starts after the lane's last live
 // sample (the pair of the lane's two samples is added once, outside the
-// loop), and a lane's idle sample sits far outside every box.
-template <int WT>
+// loop), and a lane's idle sample sits far outside every box. SKIP0 skips
+// the slot's add when its sum is 0 (a candidate outside the boxes of all of
+// the lane's samples); adding the 0 instead keeps the loop one basic block,
+// which pays where a wavefront's lanes walk long ranges (two lanes per
+// group), and not with four.
+template <int WT, bool SKIP0>
 __device__ inline void sym_pair(double (&acc)[WT], double* cacc, int p, const WSample<2>& o,
                                 const double (&x)[WT][2], const double (&sn)[WT][2], const double (&cs)[WT][2],
                                 double R) {
@@ -379,7 +383,7 @@ __device__ inline void sym_pair(double (&acc)[WT], double* cacc, int p, const WS
     c = fma(q[u], q[u], c);
   }
   const double csum = c - WQ_MAGIC;
-  if (csum != 0.0) __hip_atomic_fetch_add(cacc + p, csum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  if (!SKIP0 || csum != 0.0) __hip_atomic_fetch_add(cacc + p, csum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Work balance of the symmetric sum: a wavefront runs its pair loop as long
@@ -563,7 +567,7 @@ __global__ __launch_bounds__(WB_BLOCK, 5) void k_frame_weights_sym(const WSample
           const unsigned ph = ((unsigned)((t0 / WT) * S + sub) - (unsigned)a0) & 15u;
           int p = a0 + (int)(ph % (unsigned)len);
           for (int j = 0; j < len; ++j) {
-            sym_pair<WT>(acc, cacc, p, ld_wsample(cand_at(cand, p)), x, sn, cs, g.R);
+            sym_pair<WT, (S > 2)>(acc, cacc, p, ld_wsample(cand_at(cand, p)), x, sn, cs, g.R);
             p = p + 1 == a1 ? a0 : p + 1;
           }
         }
