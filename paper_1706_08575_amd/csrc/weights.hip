@@ -390,10 +390,14 @@ __device__ inline void sym_pair(double (&acc)[WT], double* cacc, int p, const WS
 // as its longest lane range, and the candidate counts of the groups' windows
 // vary along a bin row by tens of percent (lattice rasters against the bin
 // grid), so taken in bin order a wavefront's lanes idle about a quarter of
-// the loop. Each run therefore orders its groups by candidate count, heaviest
-// first (a counting sort in LDS), and lanes take groups in that order: the
-// wavefronts then hold groups of about equal work. Which lane forms which
-// pair does not change the sums (every square is quantized, every sum exact).
+// the loop. With two lanes per group, each run therefore orders its groups by
+// candidate count, heaviest first (a counting sort in LDS), and lanes take
+// groups in that order: the wavefronts then hold groups of about equal work.
+// With four lanes per group the runs are short and the ordering costs more
+// than it balances (2^17 samples: 0.043 -> 0.038 ms without it; 2^20: no
+// change), so those take groups in bin order. Which lane takes which group
+// does not change the sums: a group's order of addition depends on the group
+// alone (its start below), and the candidate slots add exactly quantized sums.
 constexpr int WKEYS = 512;   // work buckets of the ordering; counts of WKEYS - 1 and more share the last
 static_assert(WKEYS % WB_BLOCK == 0, "whole buckets per thread in the scan");
 
@@ -412,6 +416,7 @@ __global__ __launch_bounds__(WB_BLOCK, 5) void k_frame_weights_sym(const WSample
   // 2^23, where the wider runs fill the chunk)
   constexpr int CH = WT == 1 ? 256 : WCH;
   constexpr int NG = WB_BLOCK / S;   // groups of WT samples per run
+  constexpr bool ORDER = S <= 2;      // work order (four lanes per group: short runs, order costs more)
   __shared__ __align__(16) WSample<2> cand[CH];
   __shared__ double cacc[CH];
   __shared__ int whist[WKEYS];
@@ -426,69 +431,73 @@ __global__ __launch_bounds__(WB_BLOCK, 5) void k_frame_weights_sym(const WSample
   const int sub = (int)threadIdx.x % S;
   for (int c0 = rs + bx * RUN; c0 < re; c0 += cx * RUN) {
     const int cend = min(c0 + RUN, re);
-    // order the run's groups by candidate count (the ranges of the pair loop
-    // below, summed over the rows), heaviest first
-    for (int i = threadIdx.x; i < WKEYS; i += WB_BLOCK) whist[i] = 0;
-    __syncthreads();   // (also: the previous run's order has been read)
-    int key = 0, slot = 0;
-    if (sub == 0) {
-      const int gt0 = c0 + ((int)threadIdx.x / S) * WT;
-      int work = 0;
-      if (gt0 < cend) {
-        int lo = 1 << 30, hi = -1, nl = 0;
+    int gi = (int)threadIdx.x / S;   // this lane's group: in bin order, or by work
+    if constexpr (ORDER) {
+      // order the run's groups by candidate count (the ranges of the pair loop
+      // below, summed over the rows), heaviest first
+      for (int i = threadIdx.x; i < WKEYS; i += WB_BLOCK) whist[i] = 0;
+      __syncthreads();   // (also: the previous run's order has been read)
+      int key = 0, slot = 0;
+      if (sub == 0) {
+        const int gt0 = c0 + gi * WT;
+        int work = 0;
+        if (gt0 < cend) {
+          int lo = 1 << 30, hi = -1, nl = 0;
 #pragma unroll
-        for (int u = 0; u < WT; ++u)
-          if (gt0 + u < cend) {
-            const double2 kk = *reinterpret_cast<const double2*>(ss[gt0 + u].k);
-            double xk[2] = {kk.x, kk.y};
-            int b[2];
-            wbin_of<2>(xk, g, b);
-            lo = min(lo, b[1]);
-            hi = max(hi, b[1]);
-            ++nl;
+          for (int u = 0; u < WT; ++u)
+            if (gt0 + u < cend) {
+              const double2 kk = *reinterpret_cast<const double2*>(ss[gt0 + u].k);
+              double xk[2] = {kk.x, kk.y};
+              int b[2];
+              wbin_of<2>(xk, g, b);
+              lo = min(lo, b[1]);
+              hi = max(hi, b[1]);
+              ++nl;
+            }
+          lo = max(lo - g.span, 0);
+          hi = min(hi + g.span, nb1 - 1);
+          for (int r = b0; r <= rhi; ++r) {
+            int fs = boff[r * nb1 + lo];
+            const int fe = boff[r * nb1 + hi + 1];
+            if (r == b0) fs = max(fs, gt0 + nl);
+            work += max(fe - fs, 0);
           }
-        lo = max(lo - g.span, 0);
-        hi = min(hi + g.span, nb1 - 1);
-        for (int r = b0; r <= rhi; ++r) {
-          int fs = boff[r * nb1 + lo];
-          const int fe = boff[r * nb1 + hi + 1];
-          if (r == b0) fs = max(fs, gt0 + nl);
-          work += max(fe - fs, 0);
+        }
+        key = WKEYS - 1 - min(work, WKEYS - 1);
+        slot = atomicAdd(&whist[key], 1);
+      }
+      __syncthreads();
+      {   // exclusive scan of the bucket counts, WKEYS / WB_BLOCK buckets per thread
+        constexpr int PER = WKEYS / WB_BLOCK;
+        int v[PER], tot = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          v[q] = whist[threadIdx.x * PER + q];
+          tot += v[q];
+        }
+        int incl = tot;
+        const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int y = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += y;
+        }
+        if (lane == 63) wpart[wv] = incl;
+        __syncthreads();
+        int pre = incl - tot;
+        for (int q = 0; q < wv; ++q) pre += wpart[q];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          whist[threadIdx.x * PER + q] = pre;
+          pre += v[q];
         }
       }
-      key = WKEYS - 1 - min(work, WKEYS - 1);
-      slot = atomicAdd(&whist[key], 1);
-    }
-    __syncthreads();
-    {   // exclusive scan of the bucket counts, WKEYS / WB_BLOCK buckets per thread
-      constexpr int PER = WKEYS / WB_BLOCK;
-      int v[PER], tot = 0;
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        v[q] = whist[threadIdx.x * PER + q];
-        tot += v[q];
-      }
-      int incl = tot;
-      const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
-      }
-      if (lane == 63) wpart[wv] = incl;
       __syncthreads();
-      int pre = incl - tot;
-      for (int q = 0; q < wv; ++q) pre += wpart[q];
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        whist[threadIdx.x * PER + q] = pre;
-        pre += v[q];
-      }
+      if (sub == 0) gorder[whist[key] + slot] = (int)threadIdx.x / S;
+      __syncthreads();
+      gi = gorder[gi];
     }
-    __syncthreads();
-    if (sub == 0) gorder[whist[key] + slot] = (int)threadIdx.x / S;
-    __syncthreads();
-    const int t0 = c0 + gorder[threadIdx.x / S] * WT;   // this lane's samples t0 .. t0 + WT - 1
+    const int t0 = c0 + gi * WT;   // this lane's samples t0 .. t0 + WT - 1
     const bool active = t0 < cend;
     double x[WT][2], sn[WT][2], cs[WT][2];
     int mylo = 1 << 30, myhi = -1;
@@ -555,8 +564,9 @@ __global__ __launch_bounds__(WB_BLOCK, 5) void k_frame_weights_sym(const WSample
         const int a0 = max(ms, q0) - q0, a1 = min(me, q1) - q0;
         // Each lane starts at its own rotation of its range, on slot
         // (t0 / WT) S + sub modulo 16: groups of one bin walk the same range,
-        // and the work order puts neighbouring groups (the same bins, so the
-        // same work) in neighbouring lanes, whose starts then fall on
+        // and the work order (or the bin order, without it) puts neighbouring
+        // groups (the same bins, so the same work) in neighbouring lanes,
+        // whose starts then fall on
         // different LDS banks (a 48-byte record covers 12 of the 64 four-byte
         // banks; records 16 apart share them), for the record reads and the
         // slot atomics alike. The start is a function of the group and the
