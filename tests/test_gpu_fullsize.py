@@ -106,6 +106,23 @@ def test_full_size_spread_is_bitwise_reproducible():
         assert torch.equal(h1, h2)
 
 
+def test_full_size_weights_are_bitwise_reproducible():
+    # the 4096^2 workload's frame weights (symmetric kernel, two samples per
+    # lane, two lanes per group, groups ordered by work in each run) are
+    # bitwise the same after re-binning
+    from paper_1706_08575_amd.ftcg import Plan
+    k, _, _ = S.workload_2d_precision()
+    kd = torch.from_numpy(np.ascontiguousarray(k)).cuda()
+    with Plan(4096, dim=2, dtype="f32", weights="plain") as P:
+        P.set_points(kd)
+        w1 = P.get_weights().clone()
+        P.set_points(kd)
+        w2 = P.get_weights()
+        torch.cuda.synchronize()
+        assert torch.equal(w1, w2)
+        assert bool(torch.all(w1 > 0)) and bool(torch.all(w1 <= 1 + 1e-12))
+
+
 @pytest.mark.parametrize("n", [4096, 8192])
 def test_fft_full_size_elementwise(n):
     # the inverse-FFT passes, deapodization and crop at G = 8192 and 16384

@@ -396,19 +396,26 @@ def test_long_bin_row_bitwise_and_oracle():
     assert np.max(np.abs(wa - a_ref) / a_ref) < 1e-10
 
 
-@pytest.mark.parametrize("n,pulses,per_pulse,spl", [(128, 64, 128, 0), (256, 256, 512, 2), (256, 256, 512, 4)])
-def test_repeat_is_bitwise_stable(n, pulses, per_pulse, spl):
+@pytest.mark.parametrize("n,pulses,per_pulse,spl,lpg",
+                         [(128, 64, 128, 0, 0), (256, 256, 512, 2, 0), (256, 256, 512, 2, 2),
+                          (256, 256, 512, 4, 0)])
+def test_repeat_is_bitwise_stable(n, pulses, per_pulse, spl, lpg):
     # Run to run, and across re-binning (atomic slot claims reorder samples
     # within their bins and records within their tiles), the weights and the
-    # image are bitwise equal: the weight sums add terms rounded to a common
-    # quantum (exact float64 additions, so the atomics' order cannot matter)
-    # and the spread adds exact integers. spl selects the symmetric (2) and
-    # the one-sided (4) weight kernels at 2^17 samples.
+    # image are bitwise equal: the bin sort puts every bin in caller-index
+    # order, a lane's own sums add its pairs in an order fixed by its group,
+    # whichever lane takes the group, and round once; the candidate slots and
+    # the global sums add terms rounded to a common quantum (exact float64
+    # additions, so the atomics' order cannot matter); the spread adds exact
+    # integers. spl selects the symmetric (2) and the one-sided (4) weight
+    # kernels at 2^17 samples; lpg = 2 takes the symmetric kernel with two
+    # lanes per group, whose runs order their groups by work through LDS
+    # atomics (the instance of rasters of 2^21 samples and more).
     k, f, _ = S.make_sas(31, n, pulses, per_pulse)
     from paper_1706_08575_amd.ftcg import Plan
     with Plan(n, dim=2) as P:
         if spl:
-            P.set_weight_tuning(spl, 0)
+            P.set_weight_tuning(spl, lpg)
         ff = dev(f, torch.complex64)
         P.set_points(dev(k))
         a = host(P.execute(ff))
